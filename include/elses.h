@@ -1,0 +1,192 @@
+/*
+ * elses.h -- C ABI of the MI355X (gfx950) generalized shifted Krylov solver.
+ *
+ * The library solves the generalized shifted linear equations
+ *
+ *     (z_k B - A) x_{j,k} = e_j ,   k = 1..K,  Im z_k > 0,
+ *
+ * for many basis columns j of a sparse real-symmetric Hamiltonian A and a
+ * sparse real-symmetric positive-definite overlap B (paper Sec. III-A,
+ * Eqs. 9 and 13).  All shifts of one column share one Krylov subspace
+ * (Sec. III-B, Eq. 14).  The solutions feed the energy integral for the
+ * density matrix (Eq. 12) and the projected quantities e_j^T rho X e_j
+ * (Eq. 7), which only need rho on the sparsity pattern of X (Sec. II-B,
+ * nearsightedness).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are given per atom block (Sec. II-C: composite index
+ *   i <-> (I, alpha)).  Atoms carry 4 orbitals (C: s, px, py, pz) or 1 (H: s),
+ *   in any order; orbitals are numbered atom by atom.  Numbering atoms with
+ *   spatial locality (e.g. along a space-filling curve) makes the sparse
+ *   products cache-friendly; it does not change results.
+ * - "Host" pointers are read during the call only; the caller keeps
+ *   ownership.  "Device" pointers are GPU memory the caller allocated (for
+ *   example torch tensors); the library never frees or retains them.
+ * - Work is enqueued on the context's HIP stream.  Entry points that return
+ *   results synchronise that stream before returning.
+ * - Complex numbers are two doubles (re, im) interleaved.
+ * - No exceptions cross the ABI.  A non-OK status leaves a message for
+ *   elses_last_error().  Argument errors are reported before any launch.
+ */
+#ifndef ELSES_H
+#define ELSES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ELSES_OK = 0,
+    ELSES_ERR_INVALID_ARG = 1,    /* bad argument; nothing was launched          */
+    ELSES_ERR_HIP = 2,            /* a HIP runtime call failed                    */
+    ELSES_ERR_OOM = 3,            /* device allocation failed                     */
+    ELSES_ERR_NOT_SPD = 4,        /* overlap B is not positive definite           */
+    ELSES_WARN_NOT_CONVERGED = 5  /* outputs written; some (j,k) missed the tol   */
+} elses_status;
+
+enum { ELSES_FP64 = 0, ELSES_MIXED = 1 };          /* storage precision of A, B  */
+enum { ELSES_OUT_PATTERN = 0, ELSES_OUT_FULL = 1 }; /* extent of x_out            */
+
+typedef struct elses_ctx_s *elses_ctx;
+typedef struct elses_mat_s *elses_mat;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the handle. */
+elses_status elses_ctx_create(int device, void *hip_stream, elses_ctx *out);
+void elses_ctx_destroy(elses_ctx ctx);
+/* Message of the last failed call on this context (static storage of the
+ * context, valid until the next call). Never NULL. */
+const char *elses_last_error(elses_ctx ctx);
+
+/*
+ * System description (all HOST pointers, copied by elses_mat_create).
+ *  n_atoms        number of atoms N
+ *  n_orb[N]       orbitals per atom: 4 or 1
+ *  blk_row_ptr    [N+1] block-row pointer; row I lists its coupled atoms J,
+ *                 including I itself, in ascending J; the block pattern must
+ *                 be symmetric ((I,J) present <=> (J,I) present)
+ *  blk_col        [nnzb] atom index J of each block
+ *  A_val, B_val   values of each block (n_orb[I] x n_orb[J], row-major),
+ *                 blocks concatenated in pattern order; A and B share the
+ *                 pattern; both must be symmetric (paper Sec. II-A)
+ *  pos            [3N] atom positions (Angstrom); may be NULL when no region
+ *                 solves are requested
+ *  box            side of the periodic cube (Angstrom); <= 0: not periodic
+ */
+typedef struct {
+    int32_t n_atoms;
+    const int8_t *n_orb;
+    const int64_t *blk_row_ptr;
+    const int32_t *blk_col;
+    const double *A_val;
+    const double *B_val;
+    const double *pos;
+    double box;
+} elses_system;
+
+/*
+ * Upload a system and prepare it for solves.  precision: ELSES_FP64 keeps A
+ * and B in FP64; ELSES_MIXED additionally stores FP32 planes used by the
+ * overlap solve with FP64 residual refinement.  Estimates the spectral
+ * interval of B (used by the overlap solve) and fails with ELSES_ERR_NOT_SPD
+ * if B is not positive definite.
+ */
+elses_status elses_mat_create(elses_ctx ctx, const elses_system *sys, int precision, elses_mat *out);
+void elses_mat_destroy(elses_mat mat);
+
+/* Number of orbitals M, and the largest pattern length max_j |P_j|. */
+elses_status elses_mat_info(elses_mat mat, int64_t *M, int64_t *pmax, double *b_lo, double *b_hi);
+
+/*
+ * Pattern layout.  For column j on atom J, P_j is the ascending list of
+ * orbitals of the atoms coupled to J (the rows i with B_ij structurally
+ * present; Sec. II-B: rho_ij is needed only where X_ij != 0).
+ * pat_off (HOST, n_cols+1) receives the prefix sums of |P_j| over `cols`;
+ * rows (HOST, may be NULL) receives the concatenated row lists.
+ */
+elses_status elses_pattern(elses_mat mat, int32_t n_cols, const int32_t *cols, int64_t *pat_off, int32_t *rows);
+
+typedef struct {
+    double tol;          /* relative residual ||e_j - (z B - A) x|| per (j,k); default 1e-8 */
+    int32_t max_outer;   /* outer (Lanczos) iterations per column; default 20000            */
+    double inner_tol;    /* relative residual of each overlap solve; default 1e-13          */
+    int32_t out_mode;    /* ELSES_OUT_PATTERN or ELSES_OUT_FULL (global mode only)          */
+    int32_t slots;       /* columns advanced together (multiple of 64); 0 = autotune        */
+    int32_t use_mixed;   /* 1: FP32 overlap solve + FP64 refinement (needs ELSES_MIXED)     */
+    int32_t audit;       /* 1: recompute FP64 true residuals (ELSES_OUT_FULL only)          */
+    int32_t reserved;
+} elses_opts;
+
+/* Fill *o with the defaults listed above. */
+void elses_opts_default(elses_opts *o);
+
+/*
+ * Solve (z_k B - A) x = e_j for every j in cols (HOST, n_cols distinct
+ * column indices in [0, M)) and every shift (HOST, n_shifts complex, Im > 0).
+ *
+ * x_out (DEVICE, complex interleaved), may be NULL:
+ *   ELSES_OUT_PATTERN: column c occupies [pat_off[c]*K, pat_off[c+1]*K)
+ *                      complex entries laid out [K][|P_j|];
+ *   ELSES_OUT_FULL:    [n_cols][K][M].
+ * iters_out (DEVICE int32 [n_cols]) outer iterations, may be NULL.
+ * resid_out (DEVICE double [n_cols*K]) residual per (j,k): the recursive
+ *   estimate, or with opts->audit the recomputed FP64 true residual; may be
+ *   NULL.
+ * Returns ELSES_WARN_NOT_CONVERGED if some (j,k) ended above tol (outputs
+ * are still written).
+ */
+elses_status elses_shifted_solve(elses_ctx ctx, elses_mat mat, int32_t n_cols, const int32_t *cols,
+                                 int32_t n_shifts, const double *shifts, const elses_opts *opts,
+                                 double *x_out, int32_t *iters_out, double *resid_out);
+
+/*
+ * Density-matrix elements on the pattern (Eq. 12 discretised on the shifts):
+ *     rho_ij = sum_k Im(c_k x_{j,k,i}),  i in P_j,
+ * with complex weights c (HOST, n_shifts complex; for the Fermi-weighted
+ * midpoint rule c_k = -(1/pi) w_k f(Re z_k)).
+ * rho_out (DEVICE double, pattern layout pat_off) receives rho.
+ * traces_out (HOST double[2]) receives sum_j e_j^T rho B e_j and
+ * sum_j e_j^T rho A e_j over the requested columns (Eq. 7), may be NULL.
+ * col_traces_out (DEVICE double [n_cols][2]) per-column values, may be NULL.
+ * x_out / iters_out / resid_out as in elses_shifted_solve (may be NULL).
+ */
+elses_status elses_density_matrix(elses_ctx ctx, elses_mat mat, int32_t n_cols, const int32_t *cols,
+                                  int32_t n_shifts, const double *shifts, const double *c,
+                                  const elses_opts *opts, double *rho_out, double *traces_out,
+                                  double *col_traces_out, double *x_out, int32_t *iters_out,
+                                  double *resid_out);
+
+/*
+ * Kernel timing of the overlap-solve pass (diagnostics for roofline reports).
+ * When enabled, solves time every `stride`-th Chebyshev pass with a pair of
+ * HIP events on the context stream (stride >= 1; 0 disables).  The counters
+ * accumulate over calls until reset.
+ *   launches       passes timed
+ *   avg_us         mean duration of a timed pass (microseconds)
+ *   bytes          algorithmic HBM bytes of one pass: B's values and index
+ *                  arrays once, plus four [M][slots] FP64 blocks (the gathered
+ *                  iterate, the previous iterate, the right-hand side, the new
+ *                  iterate)
+ *   flops          2 * nnz * slots + 6 * M * slots
+ *   total_passes   all passes (A and B products) launched by solves
+ */
+elses_status elses_ctx_set_profiling(elses_ctx ctx, int32_t stride);
+elses_status elses_ctx_pass_stats(elses_ctx ctx, int64_t *launches, double *avg_us, double *bytes, double *flops,
+                                  int64_t *total_passes, int32_t *slots);
+
+/* Sparse products with the uploaded matrices (diagnostics and tests):
+ * y = X x for X = A (which=0) or B (which=1); x, y DEVICE double [M][nvec]
+ * (row-major, nvec contiguous). */
+elses_status elses_spmm(elses_ctx ctx, elses_mat mat, int which, int32_t nvec, const double *x, double *y);
+
+/* Library version string. */
+const char *elses_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ELSES_H */

@@ -90,8 +90,8 @@ class CSR:
 
     def matvec(self, x: np.ndarray) -> np.ndarray:
         y = np.zeros(self.n)
-        _c().oracle_spmv(self.n, _p(self.rp), _p(self.ci), _p(self.v), _p(np.ascontiguousarray(x, np.float64)),
-                         _p(y))
+        xc = np.ascontiguousarray(x, np.float64)  # keep the (possibly copied) input alive during the call
+        _c().oracle_spmv(self.n, _p(self.rp), _p(self.ci), _p(self.v), _p(xc), _p(y))
         return y
 
 
@@ -179,8 +179,8 @@ def shifted_solve(A: CSR, B: CSR, cols, z, tol: float = 1e-8, max_it: int = 2000
 
 def cg_B(B: CSR, s: np.ndarray, tol: float = 1e-13, max_it: int = 1000):
     x = np.zeros(B.n)
-    it = _c().oracle_cg_B(B.n, _p(B.rp), _p(B.ci), _p(B.v), _p(np.ascontiguousarray(s, np.float64)), _p(x), tol,
-                          max_it)
+    sc = np.ascontiguousarray(s, np.float64)
+    it = _c().oracle_cg_B(B.n, _p(B.rp), _p(B.ci), _p(B.v), _p(sc), _p(x), tol, max_it)
     return x, it
 
 

@@ -1,0 +1,297 @@
+"""Python binding of libelses.so, the gfx950 generalized shifted Krylov solver.
+
+Argument marshalling only: every step of a solve runs in the HIP kernels of
+the library.  PyTorch provides device memory (output tensors) and the HIP
+stream.  The entry points mirror the C ABI in include/elses.h:
+
+    Context(device=0, stream=None)
+    Matrix(ctx, n_orb, blk_row_ptr, blk_col, A_val, B_val, pos=None, box=0.0, precision="fp64")
+    shifted_solve(ctx, mat, cols, shifts, ...)     -> dict(x, iters, resid, pat_off)
+    density_matrix(ctx, mat, cols, shifts, c, ...) -> dict(rho, traces, col_traces, ...)
+    pattern(mat, cols)                             -> (pat_off, rows)
+    spmm(ctx, mat, which, x)                       -> y = A x or B x
+
+The library must have been built (python -m paper_1609_08377_amd.build);
+importing the binding without it raises ImportError: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libelses.so")
+
+ELSES_OK = 0
+ELSES_ERR_INVALID_ARG = 1
+ELSES_ERR_HIP = 2
+ELSES_ERR_OOM = 3
+ELSES_ERR_NOT_SPD = 4
+ELSES_WARN_NOT_CONVERGED = 5
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "HIP", 3: "OOM", 4: "NOT_SPD", 5: "NOT_CONVERGED"}
+
+ELSES_FP64 = 0
+ELSES_MIXED = 1
+ELSES_OUT_PATTERN = 0
+ELSES_OUT_FULL = 1
+
+
+class ElsesError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"elses {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class NotConverged(ElsesError):
+    pass
+
+
+class _System(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("n_orb", ctypes.c_void_p), ("blk_row_ptr", ctypes.c_void_p),
+                ("blk_col", ctypes.c_void_p), ("A_val", ctypes.c_void_p), ("B_val", ctypes.c_void_p),
+                ("pos", ctypes.c_void_p), ("box", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+                ("out_mode", ctypes.c_int32), ("slots", ctypes.c_int32), ("use_mixed", ctypes.c_int32),
+                ("audit", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1609_08377_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        L.elses_version.restype = ctypes.c_char_p
+        L.elses_ctx_create.argtypes = [ctypes.c_int, P, ctypes.POINTER(P)]
+        L.elses_ctx_create.restype = ctypes.c_int
+        L.elses_ctx_destroy.argtypes = [P]
+        L.elses_ctx_destroy.restype = None
+        L.elses_last_error.argtypes = [P]
+        L.elses_last_error.restype = ctypes.c_char_p
+        L.elses_mat_create.argtypes = [P, ctypes.POINTER(_System), ctypes.c_int, ctypes.POINTER(P)]
+        L.elses_mat_create.restype = ctypes.c_int
+        L.elses_mat_destroy.argtypes = [P]
+        L.elses_mat_destroy.restype = None
+        L.elses_mat_info.argtypes = [P, P, P, P, P]
+        L.elses_mat_info.restype = ctypes.c_int
+        L.elses_pattern.argtypes = [P, I32, P, P, P]
+        L.elses_pattern.restype = ctypes.c_int
+        L.elses_opts_default.argtypes = [ctypes.POINTER(Opts)]
+        L.elses_opts_default.restype = None
+        L.elses_shifted_solve.argtypes = [P, P, I32, P, I32, P, ctypes.POINTER(Opts), P, P, P]
+        L.elses_shifted_solve.restype = ctypes.c_int
+        L.elses_density_matrix.argtypes = [P, P, I32, P, I32, P, P, ctypes.POINTER(Opts), P, P, P, P, P, P]
+        L.elses_density_matrix.restype = ctypes.c_int
+        L.elses_spmm.argtypes = [P, P, ctypes.c_int, I32, P, P]
+        L.elses_spmm.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def version() -> str:
+    return lib().elses_version().decode()
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _dev_ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """A device + HIP stream; defaults to torch's current stream on `device`."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available")
+        self.device = device
+        with torch.cuda.device(device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        st = lib().elses_ctx_create(device, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != ELSES_OK:
+            raise ElsesError(st, "context creation failed")
+        self._h = h
+
+    def last_error(self) -> str:
+        return lib().elses_last_error(self._h).decode()
+
+    def check(self, st: int, allow_warn: bool = False):
+        if st == ELSES_OK:
+            return
+        if st == ELSES_WARN_NOT_CONVERGED:
+            if allow_warn:
+                return
+            raise NotConverged(st, self.last_error())
+        raise ElsesError(st, self.last_error())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().elses_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Matrix:
+    """Device copy of one (A, B) pencil in atom-block form (see include/elses.h)."""
+
+    def __init__(self, ctx: Context, n_orb, blk_row_ptr, blk_col, A_val, B_val, pos=None, box: float = 0.0,
+                 precision: str = "fp64"):
+        self.ctx = ctx
+        self._keep = [np.ascontiguousarray(n_orb, dtype=np.int8), np.ascontiguousarray(blk_row_ptr, np.int64),
+                      np.ascontiguousarray(blk_col, np.int32), np.ascontiguousarray(A_val, np.float64),
+                      np.ascontiguousarray(B_val, np.float64),
+                      None if pos is None else np.ascontiguousarray(pos, np.float64).reshape(-1)]
+        no, rp, bc, av, bv, ps = self._keep
+        sysd = _System(int(no.shape[0]), _np_ptr(no), _np_ptr(rp), _np_ptr(bc), _np_ptr(av), _np_ptr(bv),
+                       _np_ptr(ps), float(box))
+        prec = {"fp64": ELSES_FP64, "mixed": ELSES_MIXED}[precision]
+        h = ctypes.c_void_p()
+        st = lib().elses_mat_create(ctx._h, ctypes.byref(sysd), prec, ctypes.byref(h))
+        ctx.check(st)
+        self._h = h
+        self.precision = precision
+        M = ctypes.c_int64()
+        pmax = ctypes.c_int64()
+        lo = ctypes.c_double()
+        hi = ctypes.c_double()
+        lib().elses_mat_info(h, ctypes.byref(M), ctypes.byref(pmax), ctypes.byref(lo), ctypes.byref(hi))
+        self.M = int(M.value)
+        self.pmax = int(pmax.value)
+        self.b_interval = (lo.value, hi.value)
+        self._keep = None
+
+    @classmethod
+    def from_system(cls, ctx: Context, sysm, precision: str = "fp64") -> "Matrix":
+        return cls(ctx, sysm.n_orb, sysm.blk_row_ptr, sysm.blk_col, sysm.A_val, sysm.B_val, pos=sysm.pos,
+                   box=sysm.L, precision=precision)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().elses_mat_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pattern(mat: Matrix, cols) -> tuple[np.ndarray, np.ndarray]:
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    off = np.zeros(cols.shape[0] + 1, dtype=np.int64)
+    mat.ctx.check(lib().elses_pattern(mat._h, cols.shape[0], _np_ptr(cols), _np_ptr(off), None))
+    rows = np.zeros(int(off[-1]), dtype=np.int32)
+    mat.ctx.check(lib().elses_pattern(mat._h, cols.shape[0], _np_ptr(cols), _np_ptr(off), _np_ptr(rows)))
+    return off, rows
+
+
+def make_opts(tol=1e-8, max_outer=20000, inner_tol=1e-13, full=False, slots=0, mixed=False, audit=False) -> Opts:
+    o = Opts()
+    lib().elses_opts_default(ctypes.byref(o))
+    o.tol = tol
+    o.max_outer = max_outer
+    o.inner_tol = inner_tol
+    o.out_mode = ELSES_OUT_FULL if full else ELSES_OUT_PATTERN
+    o.slots = slots
+    o.use_mixed = 1 if mixed else 0
+    o.audit = 1 if audit else 0
+    return o
+
+
+def _shifts_ri(shifts) -> np.ndarray:
+    z = np.asarray(shifts, dtype=np.complex128)
+    return np.ascontiguousarray(np.stack([z.real, z.imag], axis=1).reshape(-1))
+
+
+def shifted_solve(ctx: Context, mat: Matrix, cols, shifts, *, tol=1e-8, max_outer=20000, inner_tol=1e-13,
+                  full=False, slots=0, mixed=False, audit=False, want_x=True, allow_not_converged=False):
+    """(z_k B - A) x = e_j for j in cols and every shift; returns torch tensors on the device."""
+    torch = _torch()
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    z = _shifts_ri(shifts)
+    K = z.shape[0] // 2
+    nc = cols.shape[0]
+    dev = torch.device("cuda", ctx.device)
+    if full:
+        pat_off = None
+        nx = nc * K * mat.M
+    else:
+        pat_off, _ = pattern(mat, cols)
+        nx = int(pat_off[-1]) * K
+    x = torch.empty(2 * nx, dtype=torch.float64, device=dev) if want_x else None
+    iters = torch.empty(nc, dtype=torch.int32, device=dev)
+    resid = torch.empty(nc * K, dtype=torch.float64, device=dev)
+    opts = make_opts(tol, max_outer, inner_tol, full, slots, mixed, audit)
+    st = lib().elses_shifted_solve(ctx._h, mat._h, nc, _np_ptr(cols), K, _np_ptr(z), ctypes.byref(opts),
+                                   _dev_ptr(x), _dev_ptr(iters), _dev_ptr(resid))
+    ctx.check(st, allow_warn=allow_not_converged)
+    xc = None
+    if x is not None:
+        xc = torch.view_as_complex(x.view(-1, 2))
+        if full:
+            xc = xc.view(nc, K, mat.M)
+    return dict(x=xc, iters=iters, resid=resid.view(nc, K), pat_off=pat_off, status=st)
+
+
+def density_matrix(ctx: Context, mat: Matrix, cols, shifts, c, *, tol=1e-8, max_outer=20000, inner_tol=1e-13,
+                   slots=0, mixed=False, want_x=False, allow_not_converged=False):
+    """rho_ij = sum_k Im(c_k x_{j,k,i}) on the pattern, plus the traces Tr[rho B], Tr[rho A] over cols."""
+    torch = _torch()
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    z = _shifts_ri(shifts)
+    cw = _shifts_ri(c)
+    K = z.shape[0] // 2
+    if cw.shape[0] != 2 * K:
+        raise ValueError("one weight per shift")
+    nc = cols.shape[0]
+    dev = torch.device("cuda", ctx.device)
+    pat_off, _ = pattern(mat, cols)
+    rho = torch.empty(int(pat_off[-1]), dtype=torch.float64, device=dev)
+    col_tr = torch.empty(2 * nc, dtype=torch.float64, device=dev)
+    x = torch.empty(2 * int(pat_off[-1]) * K, dtype=torch.float64, device=dev) if want_x else None
+    iters = torch.empty(nc, dtype=torch.int32, device=dev)
+    resid = torch.empty(nc * K, dtype=torch.float64, device=dev)
+    traces = np.zeros(2)
+    opts = make_opts(tol, max_outer, inner_tol, False, slots, mixed, False)
+    st = lib().elses_density_matrix(ctx._h, mat._h, nc, _np_ptr(cols), K, _np_ptr(z), _np_ptr(cw),
+                                    ctypes.byref(opts), _dev_ptr(rho), _np_ptr(traces), _dev_ptr(col_tr),
+                                    _dev_ptr(x), _dev_ptr(iters), _dev_ptr(resid))
+    ctx.check(st, allow_warn=allow_not_converged)
+    return dict(rho=rho, traces=traces, col_traces=col_tr.view(nc, 2), pat_off=pat_off, iters=iters,
+                resid=resid.view(nc, K), x=None if x is None else torch.view_as_complex(x.view(-1, 2)), status=st)
+
+
+def spmm(ctx: Context, mat: Matrix, which: str, x):
+    """y = A x or B x for x a float64 device tensor of shape (M, nvec)."""
+    torch = _torch()
+    x = x.contiguous()
+    y = torch.empty_like(x)
+    nvec = 1 if x.dim() == 1 else x.shape[1]
+    st = lib().elses_spmm(ctx._h, mat._h, {"A": 0, "B": 1}[which], nvec, _dev_ptr(x), _dev_ptr(y))
+    ctx.check(st)
+    return y

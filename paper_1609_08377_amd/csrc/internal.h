@@ -1,0 +1,183 @@
+// Internal declarations of the gfx950 generalized shifted Krylov solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/elses.h"
+
+namespace elses {
+
+constexpr int kWave = 64;         // CDNA wavefront width
+constexpr int kBlock = 256;       // threads per workgroup for the vector passes
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// Atom-block sparse matrix on the device.  Atoms carry 4 or 1 orbitals, in
+// any order.  Internally the blocks of row atom I are reordered so that the
+// 4-orbital neighbours come first: a 4-wide part [brow[I], bsplit[I]) and a
+// 1-wide part [bsplit[I], brow[I+1]), each in ascending neighbour order.  The
+// values of row I are contiguous from voff[I] in that order, each block
+// n_I x n_J row-major.  The asc_* arrays describe the same blocks in the
+// caller's (ascending) order, for output patterns.
+struct DevMatrix {
+    int n_atoms = 0, M = 0;
+    int nnzb = 0;
+    int64_t nnz = 0;
+    int *atom_off = nullptr;  // [n_atoms+1] first orbital of each atom
+    int *orb_atom = nullptr;  // [M] atom of each orbital
+    int *brow = nullptr;      // [n_atoms+1]
+    int *bsplit = nullptr;    // [n_atoms]
+    int *borb = nullptr;      // [nnzb] first orbital of the coupled atom (internal order)
+    int64_t *voff = nullptr;  // [n_atoms]
+    int *asc_borb = nullptr;  // [nnzb] ascending order: first orbital of the coupled atom
+    int *asc_n = nullptr;     // [nnzb] ascending order: its orbital count
+    int64_t *asc_voff = nullptr;  // [nnzb] ascending order: value offset of the block
+    double *A = nullptr, *B = nullptr;  // [nnz] internal layout
+    float *A32 = nullptr, *B32 = nullptr;
+};
+
+struct HostMatrix {
+    int n_atoms = 0, M = 0;
+    std::vector<int> atom_off, brow, bcol;  // caller's ascending block order
+    std::vector<double> pos;
+    double box = 0;
+    int pmax = 0;                     // max over atoms of the coupled-orbital count
+    std::vector<int> atom_plen;       // coupled-orbital count per atom
+};
+
+}  // namespace elses
+
+struct elses_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int n_cu = 256;
+    // sampled timing of the Chebyshev pass
+    int prof_stride = 0;
+    int64_t prof_launches = 0;
+    double prof_ms = 0.0;
+    double prof_bytes = 0.0;
+    double prof_flops = 0.0;
+    int64_t total_passes = 0;
+    int prof_slots = 0;
+};
+
+struct elses_mat_s {
+    elses_ctx ctx = nullptr;
+    int precision = ELSES_FP64;
+    elses::HostMatrix h;
+    elses::DevMatrix d;
+    double b_lo = 0, b_hi = 0;  // interval enclosing the spectrum of B
+};
+
+namespace elses {
+
+// ---------------------------------------------------------------------------
+// Vector passes over the atom-block matrix (lanes = right-hand sides).
+// ---------------------------------------------------------------------------
+enum PassKind { PASS_LANCZOS_A = 0, PASS_CHEB = 1, PASS_CHEB_LAST = 2, PASS_PLAIN = 3 };
+
+struct PassArgs {
+    // matrix
+    const int *atom_off;
+    const int *brow;
+    const int *bsplit;
+    const int *borb;
+    const int64_t *voff;
+    const double *vals;
+    int n_atoms;
+    // layout: vectors are [M][ld] doubles, ld = slot count.  Slabs are groups
+    // of atoms_per_slab consecutive atoms (one per wave); n_slabs is a
+    // multiple of 8 (trailing slabs may be empty).
+    int ld;
+    int n_slabs, atoms_per_slab, n_tiles;
+    // vectors
+    const double *Xg;   // gathered operand
+    double *Xio;        // CHEB: in x_{k-1} (if has_prev), out x_{k+1}; LANCZOS_A: out x_1; PLAIN: out y
+    double *S;          // LANCZOS_A: in t_{n-1} / out s'; CHEB: in s; CHEB_LAST: in s', out s
+    const double *Vq;   // CHEB_LAST / LANCZOS_A: q_n (unnormalised, own rows)
+    const double *Tn;   // CHEB_LAST: t_n (unnormalised, own rows)
+    // per-slot scalars
+    const double *inv_beta;   // 1/beta_{n-1}
+    const double *coefT;      // beta_{n-1}/beta_{n-2}
+    const double *alpha;      // alpha_n (reduced)
+    const int *slot_n;        // iteration counter (0 = start vector)
+    const int *slot_row;      // e_j row of the slot's column (-1 idle)
+    // Chebyshev step x_{k+1} = x_k + omega (x_k - x_{k-1}) + gamma (s - B x_k)
+    double omega, gamma;
+    int has_prev;
+    double g0;                // x_1 = g0 * s
+    // dot partials [n_slabs][ld]
+    double *part0, *part1;
+};
+
+void launch_pass(PassKind kind, const PassArgs &a, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Per-slot shift recurrences and bookkeeping.
+// ---------------------------------------------------------------------------
+struct ShiftArgs {
+    int ld;          // slot count
+    int n_slabs;
+    int K;           // shifts
+    int M;
+    const double *z; // [K] complex
+    const double *cw; // [K] complex weights for rho (density mode) or null
+    // per-slot state
+    int *slot_n;
+    int *slot_row;    // e_j row (-1 idle)
+    int *slot_cidx;   // index into the column list
+    double *beta_prev;
+    double *inv_beta;
+    double *coefT;
+    const double *alpha;
+    const double *part0, *part1;   // v.s, s.s partials
+    double *eta, *zeta;            // [ld][K] complex
+    int *conv;                     // [ld][K] iteration of convergence, 0 active
+    double *res;                   // [ld][K]
+    double *xs, *ps;               // [ld][K][rmax] complex
+    int rmax;                      // row capacity per slot
+    const double *Vq;              // q_n buffer (unnormalised)
+    // column bookkeeping
+    int n_cols;
+    const int *cols;               // [n_cols] global column (orbital) index
+    const int64_t *row_off;        // [n_cols+1] offsets into rows (pattern mode)
+    const int *rows;               // pattern rows (pattern mode) or null (full: 0..M-1)
+    const int64_t *vidx;           // value index of B_ji / A_ji per pattern entry (density)
+    const double *Bv, *Av;         // FP64 values (density traces)
+    int full;                      // 1: rows are 0..M-1
+    double tol;
+    int max_outer;
+    int *queue;                    // next column to start
+    int *remaining;                // columns not yet finished
+    int *n_notconv;                // columns finished without convergence
+    // outputs
+    double *x_out;                 // may be null
+    int *iters_out;                // may be null
+    double *resid_out;             // may be null
+    double *rho_out;               // density mode (may be null)
+    double *ctr_out;               // [n_cols][2] per-column traces (may be null)
+};
+
+void launch_alpha_reduce(const double *part, int n_slabs, int ld, const int *slot_n, const int *slot_row,
+                         double *alpha, hipStream_t st);
+void launch_shift_update(const ShiftArgs &a, hipStream_t st);
+void launch_pattern_setup(const DevMatrix &m, int n_cols, const int *cols, const int64_t *row_off, int *rows,
+                          int64_t *vidx, hipStream_t st);
+void launch_slot_init(const ShiftArgs &a, int n_active, hipStream_t st);
+
+// Generic products used by setup, audits and diagnostics: y = X x (nvec vectors, [M][ld]).
+void launch_spmm_generic(const DevMatrix &m, const double *vals, int nvec, int ld, const double *x, double *y,
+                         hipStream_t st);
+// Complex true residual ||e_j - (z_k B - A) x_{c,k}||_2 for full-mode outputs.
+void launch_true_residual(const DevMatrix &m, int n_cols, const int *cols, int K, const double *z,
+                          const double *x_full, double *res_out, hipStream_t st);
+void launch_sum_pairs(const double *v, int n, double *out2, hipStream_t st);
+
+// Partial dot products (deterministic two-stage): out[b] = sum over block b
+void launch_dot_partial(const double *a, const double *b, int n, double *part, int nblocks, hipStream_t st);
+
+}  // namespace elses

@@ -14,8 +14,8 @@ recipe with the same structure:
 * N_C = round(N/3) carbons, N_H = N - N_C hydrogens (C:H = 1:2).
 * Periodic cube at 1.0 g/cm^3; random sequential addition with a minimum
   pair distance of 1.0 A (minimum image); the first N_C accepted points are C.
-* Atoms are emitted species-sorted (all C, then all H) and, within a
-  species, in Morton order of a ~2 A cell grid (spatial locality).
+* Atoms are emitted in Morton order of a ~2 A cell grid (spatial locality),
+  C and H interleaved as they fall.
 * Pairs I != J with minimum-image distance r <= 4 A are coupled.  Every
   orbital pair of a coupled atom pair gets A = exp(-r/1.5) * g and
   B = 0.1 * exp(-r/1.5) * g' with g, g' ~ N(1, 0.1) drawn independently, once
@@ -152,13 +152,15 @@ def make_system(n_atoms: int, seed: int, r_cut: float = R_CUT, density: float = 
         raise RuntimeError(f"random sequential addition failed ({rc})")
     species_c = np.zeros(n_atoms, dtype=bool)
     species_c[:n_c] = True
-    # species-sorted, Morton order inside a species
+    # Morton order of a ~2 A cell grid over all atoms (spatial locality); the
+    # placement index breaks ties
     g = max(1, int(L // 2.0))
     cell = np.minimum((pos / (L / g)).astype(np.int64), g - 1)
     code = _morton3(cell[:, 0], cell[:, 1], cell[:, 2])
-    order = np.lexsort((np.arange(n_atoms), code, ~species_c))
+    order = np.lexsort((np.arange(n_atoms), code))
     pos = np.ascontiguousarray(pos[order])
-    n_orb = np.where(np.arange(n_atoms) < n_c, 4, 1).astype(np.int8)
+    species_c = species_c[order]
+    n_orb = np.where(species_c, 4, 1).astype(np.int8)
     orb_off = np.zeros(n_atoms + 1, dtype=np.int64)
     np.cumsum(n_orb, out=orb_off[1:])
 

@@ -50,8 +50,8 @@ def test_generator_shapes(c1_system):
     assert s.n_c == 43 and s.n_atoms - s.n_c == 85
     assert s.M == 4 * 43 + 85 == 257
     assert abs(s.L - 10.0) < 1e-3
-    # species-sorted: C first
-    assert np.all(s.n_orb[:43] == 4) and np.all(s.n_orb[43:] == 1)
+    assert int((s.n_orb == 4).sum()) == 43 and int((s.n_orb == 1).sum()) == 85
+    assert np.array_equal(np.diff(s.orb_off), s.n_orb)
     # minimum pair distance and cutoff
     pi, pj, pr, pd = s.extra["pairs"]
     assert pr.min() >= 1.0 and pr.max() <= 4.0
@@ -75,6 +75,10 @@ def test_csr_matvec(c1_csr):
     A, _ = c1_csr
     x = np.random.default_rng(0).standard_normal(A.n)
     assert np.allclose(A.matvec(x), A.dense() @ x, rtol=0, atol=1e-13)
+    # strided column views are copied; the copy must outlive the C call
+    X = np.random.default_rng(1).standard_normal((A.n, 3))
+    for v in range(3):
+        assert np.allclose(A.matvec(X[:, v]), A.dense() @ X[:, v], rtol=0, atol=1e-13)
 
 
 def test_cg_B(c1_csr):
@@ -297,7 +301,7 @@ def test_region_whole_box_is_global(c1_system, c1_csr):
 
 def test_region_small_vs_dense(c1_system, c1_csr):
     A, B = c1_csr
-    centre = 10  # a carbon atom: 4 columns
+    centre = int(np.nonzero(c1_system.n_orb == 4)[0][3])  # a carbon atom: 4 columns
     atoms = oracle.region_atoms(c1_system, centre, radius=4.5)
     Ar, Br, omap = oracle.carve_region(c1_system, atoms)
     # the test's own principal submatrix of the global dense matrices
