@@ -77,7 +77,10 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--cols", type=int, default=0, help="limit the column count (0 = all)")
     ap.add_argument("--slots", type=int, default=0)
+    ap.add_argument("--variant", default="auto", choices=["auto", "direct", "staged8", "staged4", "grouped", "grouped2", "grouped1"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--max-outer", type=int, default=20000,
+                    help="cap on outer iterations (profiling runs only: capped runs do not converge)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -107,7 +110,8 @@ def main():
     lib.elses_ctx_pass_stats.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 6
 
     def step():
-        return el.density_matrix(ctx, mat, cols, z, cw, slots=args.slots, want_x=True)
+        return el.density_matrix(ctx, mat, cols, z, cw, slots=args.slots, want_x=True, max_outer=args.max_outer,
+                                 allow_not_converged=args.max_outer < 20000, variant=args.variant)
 
     for w in range(args.warmup):
         print(f"warmup {w + 1}/{args.warmup}", file=sys.stderr, flush=True)

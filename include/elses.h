@@ -117,7 +117,8 @@ typedef struct {
     int32_t slots;       /* columns advanced together (multiple of 64); 0 = autotune        */
     int32_t use_mixed;   /* 1: FP32 overlap solve + FP64 refinement (needs ELSES_MIXED)     */
     int32_t audit;       /* 1: recompute FP64 true residuals (ELSES_OUT_FULL only)          */
-    int32_t reserved;
+    int32_t variant;     /* sparse passes: 0 auto, 1 direct gathers, 2 / 3 LDS-staged       */
+                         /* gathers (8- / 4-atom clusters), 4 row groups sharing gathers   */
 } elses_opts;
 
 /* Fill *o with the defaults listed above. */
@@ -167,20 +168,34 @@ elses_status elses_density_matrix(elses_ctx ctx, elses_mat mat, int32_t n_cols, 
  *   launches       passes timed
  *   avg_us         mean duration of a timed pass (microseconds)
  *   bytes          algorithmic HBM bytes of one pass: B's values and index
- *                  arrays once, plus four [M][slots] FP64 blocks (the gathered
- *                  iterate, the previous iterate, the right-hand side, the new
- *                  iterate)
- *   flops          2 * nnz * slots + 6 * M * slots
+ *                  arrays once, plus three [M][slots] FP64 blocks (the
+ *                  gathered iterate, the right-hand side, the new iterate)
+ *   flops          2 * nnz * slots + 3 * M * slots
  *   total_passes   all passes (A and B products) launched by solves
  */
 elses_status elses_ctx_set_profiling(elses_ctx ctx, int32_t stride);
 elses_status elses_ctx_pass_stats(elses_ctx ctx, int64_t *launches, double *avg_us, double *bytes, double *flops,
                                   int64_t *total_passes, int32_t *slots);
 
+/*
+ * Time `reps` back-to-back launches of one sparse pass on scratch blocks of
+ * `slots` right-hand sides (a multiple of 64) with pass kernels `variant`
+ * (as in elses_opts).  kind: 0 the A pass of a Lanczos step, 1 a
+ * Richardson step of the overlap solve, 2 the last step with the Lanczos
+ * correction, 3 the plain product.  *avg_us receives the mean launch time
+ * measured with HIP events on the context stream.  Used by the slot and
+ * variant autotuner and by performance diagnostics.
+ */
+elses_status elses_time_pass(elses_ctx ctx, elses_mat mat, int32_t kind, int32_t variant, int32_t slots,
+                             int32_t reps, double *avg_us);
+
 /* Sparse products with the uploaded matrices (diagnostics and tests):
  * y = X x for X = A (which=0) or B (which=1); x, y DEVICE double [M][nvec]
- * (row-major, nvec contiguous). */
-elses_status elses_spmm(elses_ctx ctx, elses_mat mat, int which, int32_t nvec, const double *x, double *y);
+ * (row-major, nvec contiguous).  For nvec a multiple of 64 the pass kernels
+ * of `variant` (as in elses_opts) run; any other nvec uses a generic
+ * one-thread-per-entry kernel. */
+elses_status elses_spmm(elses_ctx ctx, elses_mat mat, int which, int32_t variant, int32_t nvec, const double *x,
+                        double *y);
 
 /* Library version string. */
 const char *elses_version(void);

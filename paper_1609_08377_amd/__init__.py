@@ -58,7 +58,7 @@ class _System(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("out_mode", ctypes.c_int32), ("slots", ctypes.c_int32), ("use_mixed", ctypes.c_int32),
-                ("audit", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("audit", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
 
 _lib = None
@@ -92,7 +92,7 @@ def lib():
         L.elses_shifted_solve.restype = ctypes.c_int
         L.elses_density_matrix.argtypes = [P, P, I32, P, I32, P, P, ctypes.POINTER(Opts), P, P, P, P, P, P]
         L.elses_density_matrix.restype = ctypes.c_int
-        L.elses_spmm.argtypes = [P, P, ctypes.c_int, I32, P, P]
+        L.elses_spmm.argtypes = [P, P, ctypes.c_int, I32, I32, P, P]
         L.elses_spmm.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -210,7 +210,12 @@ def pattern(mat: Matrix, cols) -> tuple[np.ndarray, np.ndarray]:
     return off, rows
 
 
-def make_opts(tol=1e-8, max_outer=20000, inner_tol=1e-13, full=False, slots=0, mixed=False, audit=False) -> Opts:
+VARIANTS = {"auto": 0, "direct": 1, "staged": 2, "staged8": 2, "staged4": 3, "grouped": 4, "grouped4": 4,
+            "grouped2": 5, "grouped1": 6}
+
+
+def make_opts(tol=1e-8, max_outer=20000, inner_tol=1e-13, full=False, slots=0, mixed=False, audit=False,
+              variant="auto") -> Opts:
     o = Opts()
     lib().elses_opts_default(ctypes.byref(o))
     o.tol = tol
@@ -220,6 +225,7 @@ def make_opts(tol=1e-8, max_outer=20000, inner_tol=1e-13, full=False, slots=0, m
     o.slots = slots
     o.use_mixed = 1 if mixed else 0
     o.audit = 1 if audit else 0
+    o.variant = VARIANTS[variant]
     return o
 
 
@@ -229,7 +235,8 @@ def _shifts_ri(shifts) -> np.ndarray:
 
 
 def shifted_solve(ctx: Context, mat: Matrix, cols, shifts, *, tol=1e-8, max_outer=20000, inner_tol=1e-13,
-                  full=False, slots=0, mixed=False, audit=False, want_x=True, allow_not_converged=False):
+                  full=False, slots=0, mixed=False, audit=False, want_x=True, allow_not_converged=False,
+                  variant="auto"):
     """(z_k B - A) x = e_j for j in cols and every shift; returns torch tensors on the device."""
     torch = _torch()
     cols = np.ascontiguousarray(cols, dtype=np.int32)
@@ -246,7 +253,7 @@ def shifted_solve(ctx: Context, mat: Matrix, cols, shifts, *, tol=1e-8, max_oute
     x = torch.empty(2 * nx, dtype=torch.float64, device=dev) if want_x else None
     iters = torch.empty(nc, dtype=torch.int32, device=dev)
     resid = torch.empty(nc * K, dtype=torch.float64, device=dev)
-    opts = make_opts(tol, max_outer, inner_tol, full, slots, mixed, audit)
+    opts = make_opts(tol, max_outer, inner_tol, full, slots, mixed, audit, variant)
     st = lib().elses_shifted_solve(ctx._h, mat._h, nc, _np_ptr(cols), K, _np_ptr(z), ctypes.byref(opts),
                                    _dev_ptr(x), _dev_ptr(iters), _dev_ptr(resid))
     ctx.check(st, allow_warn=allow_not_converged)
@@ -259,7 +266,7 @@ def shifted_solve(ctx: Context, mat: Matrix, cols, shifts, *, tol=1e-8, max_oute
 
 
 def density_matrix(ctx: Context, mat: Matrix, cols, shifts, c, *, tol=1e-8, max_outer=20000, inner_tol=1e-13,
-                   slots=0, mixed=False, want_x=False, allow_not_converged=False):
+                   slots=0, mixed=False, want_x=False, allow_not_converged=False, variant="auto"):
     """rho_ij = sum_k Im(c_k x_{j,k,i}) on the pattern, plus the traces Tr[rho B], Tr[rho A] over cols."""
     torch = _torch()
     cols = np.ascontiguousarray(cols, dtype=np.int32)
@@ -277,7 +284,7 @@ def density_matrix(ctx: Context, mat: Matrix, cols, shifts, c, *, tol=1e-8, max_
     iters = torch.empty(nc, dtype=torch.int32, device=dev)
     resid = torch.empty(nc * K, dtype=torch.float64, device=dev)
     traces = np.zeros(2)
-    opts = make_opts(tol, max_outer, inner_tol, False, slots, mixed, False)
+    opts = make_opts(tol, max_outer, inner_tol, False, slots, mixed, False, variant)
     st = lib().elses_density_matrix(ctx._h, mat._h, nc, _np_ptr(cols), K, _np_ptr(z), _np_ptr(cw),
                                     ctypes.byref(opts), _dev_ptr(rho), _np_ptr(traces), _dev_ptr(col_tr),
                                     _dev_ptr(x), _dev_ptr(iters), _dev_ptr(resid))
@@ -286,12 +293,13 @@ def density_matrix(ctx: Context, mat: Matrix, cols, shifts, c, *, tol=1e-8, max_
                 resid=resid.view(nc, K), x=None if x is None else torch.view_as_complex(x.view(-1, 2)), status=st)
 
 
-def spmm(ctx: Context, mat: Matrix, which: str, x):
+def spmm(ctx: Context, mat: Matrix, which: str, x, variant: str = "auto"):
     """y = A x or B x for x a float64 device tensor of shape (M, nvec)."""
     torch = _torch()
     x = x.contiguous()
     y = torch.empty_like(x)
     nvec = 1 if x.dim() == 1 else x.shape[1]
-    st = lib().elses_spmm(ctx._h, mat._h, {"A": 0, "B": 1}[which], nvec, _dev_ptr(x), _dev_ptr(y))
+    st = lib().elses_spmm(ctx._h, mat._h, {"A": 0, "B": 1}[which], VARIANTS[variant], nvec, _dev_ptr(x),
+                          _dev_ptr(y))
     ctx.check(st)
     return y

@@ -105,11 +105,229 @@ double tri_eig(const std::vector<double>& a, const std::vector<double>& b, int i
     return 0.5 * (lo + hi);
 }
 
+// Clusters of at most max_atoms consecutive atoms whose coupled orbitals
+// (the union over the cluster) fit in max_rows LDS rows.  Greedy in atom
+// order.  bloc[b] (internal block order) receives the LDS row of block b's
+// first coupled orbital.  Returns false if a single atom couples to more
+// orbitals than the LDS holds (then this cluster shape is not used).
+bool build_clusters(int max_atoms, int max_rows, const std::vector<int>& atom_off, const std::vector<int>& brow,
+                    const std::vector<int>& bcol, const std::vector<int>& borb, std::vector<int>& cl_atom,
+                    std::vector<int>& cl_uoff, std::vector<int>& cl_urow, std::vector<int>& bloc) {
+    const int N = (int)atom_off.size() - 1;
+    std::vector<int> stamp(N, -1), lrow(N, 0);
+    cl_atom.assign(1, 0);
+    cl_uoff.assign(1, 0);
+    cl_urow.clear();
+    bloc.assign(bcol.size(), 0);
+    int I = 0, c = 0;
+    std::vector<int> members;
+    while (I < N) {
+        int orbs = 0;
+        const int start = I;
+        members.clear();
+        while (I < N && I - start < max_atoms) {
+            int add = 0;
+            for (int b = brow[I]; b < brow[I + 1]; ++b)
+                if (stamp[bcol[b]] != c) add += atom_off[bcol[b] + 1] - atom_off[bcol[b]];
+            if (orbs + add > max_rows) {
+                if (I == start) return false;
+                break;
+            }
+            for (int b = brow[I]; b < brow[I + 1]; ++b)
+                if (stamp[bcol[b]] != c) {
+                    stamp[bcol[b]] = c;
+                    members.push_back(bcol[b]);
+                }
+            orbs += add;
+            ++I;
+        }
+        std::sort(members.begin(), members.end());
+        int r = 0;
+        for (int J : members) {
+            lrow[J] = r;
+            for (int q = atom_off[J]; q < atom_off[J + 1]; ++q, ++r) cl_urow.push_back(q);
+        }
+        // borb holds the first orbital of the coupled atom in internal order
+        for (int A = start; A < I; ++A)
+            for (int b = brow[A]; b < brow[A + 1]; ++b) {
+                const int o = borb[b];
+                // map orbital -> atom via the members (atom_off is ascending)
+                const int J = (int)(std::upper_bound(atom_off.begin(), atom_off.end(), o) - atom_off.begin()) - 1;
+                bloc[b] = lrow[J];
+            }
+        cl_atom.push_back(I);
+        cl_uoff.push_back((int)cl_urow.size());
+        ++c;
+    }
+    return true;
+}
+
+// Row groups for the grouped passes.  Every 1-orbital atom joins the
+// 4-orbital atom it couples to most strongly through B (the sum of |B| over
+// the block; the overlap decays with distance, so this is its nearest
+// 4-orbital neighbour), at most kGroupH per 4-orbital atom; the others stay
+// alone.  Groups are emitted in atom order (a 4-orbital atom's group at its
+// own position).  The union of a group's coupled atoms is listed 4-orbital
+// atoms first (ascending), then 1-orbital ones; the values are dense
+// R x n_J blocks over it, in the same order, zero where a member does not
+// couple to the union atom.
+struct HostGroups {
+    std::vector<int> R, roff{0}, rows, uoff{0}, u4, uorb;
+    std::vector<int64_t> voff;
+    std::vector<double> A, B;
+};
+
+void build_groups(const elses_system* sys, const HostMatrix& h, const std::vector<int64_t>& in_voff,
+                  HostGroups& G) {
+    const int N = h.n_atoms;
+    const int8_t* no = sys->n_orb;
+    struct Cand {
+        double w;
+        int hh, J;
+    };
+    std::vector<Cand> cand;
+    for (int a = 0; a < N; ++a) {
+        if (no[a] != 1) continue;
+        for (int b = h.brow[a]; b < h.brow[a + 1]; ++b) {
+            const int J = h.bcol[b];
+            if (no[J] != 4) continue;
+            double w = 0.0;
+            for (int q = 0; q < 4; ++q) w += fabs(sys->B_val[in_voff[b] + q]);
+            cand.push_back({w, a, J});
+        }
+    }
+    std::sort(cand.begin(), cand.end(), [](const Cand& x, const Cand& y) {
+        if (x.w != y.w) return x.w > y.w;
+        if (x.hh != y.hh) return x.hh < y.hh;
+        return x.J < y.J;
+    });
+    std::vector<int> owner(N, -1), cnt(N, 0);
+    for (const Cand& c : cand)
+        if (owner[c.hh] < 0 && cnt[c.J] < kGroupH) {
+            owner[c.hh] = c.J;
+            ++cnt[c.J];
+        }
+    std::vector<std::vector<int>> attached(N);
+    for (int a = 0; a < N; ++a)
+        if (owner[a] >= 0) attached[owner[a]].push_back(a);  // ascending by construction
+    std::vector<int> stamp(N, -1), upos(N, 0), members, u4list, u1list;
+    int g = 0;
+    for (int I = 0; I < N; ++I) {
+        if (no[I] == 1 && owner[I] >= 0) continue;
+        members.assign(1, I);
+        if (no[I] == 4) members.insert(members.end(), attached[I].begin(), attached[I].end());
+        int R = 0;
+        for (int m : members) {
+            for (int q = 0; q < no[m]; ++q) G.rows.push_back(h.atom_off[m] + q);
+            R += no[m];
+        }
+        u4list.clear();
+        u1list.clear();
+        for (int m : members)
+            for (int b = h.brow[m]; b < h.brow[m + 1]; ++b) {
+                const int J = h.bcol[b];
+                if (stamp[J] == g) continue;
+                stamp[J] = g;
+                (no[J] == 4 ? u4list : u1list).push_back(J);
+            }
+        std::sort(u4list.begin(), u4list.end());
+        std::sort(u1list.begin(), u1list.end());
+        const int n4u = (int)u4list.size();
+        for (int k = 0; k < n4u; ++k) upos[u4list[k]] = k;
+        for (int k = 0; k < (int)u1list.size(); ++k) upos[u1list[k]] = n4u + k;
+        const int64_t base = (int64_t)G.A.size();
+        const int64_t len = (int64_t)R * (4 * n4u + (int64_t)u1list.size());
+        G.A.resize(base + len, 0.0);
+        G.B.resize(base + len, 0.0);
+        int rm = 0;
+        for (int m : members) {
+            for (int b = h.brow[m]; b < h.brow[m + 1]; ++b) {
+                const int J = h.bcol[b];
+                const int nJ = no[J];
+                const int k = upos[J];
+                const int64_t off = base + (k < n4u ? (int64_t)k * R * 4 : (int64_t)n4u * R * 4 + (int64_t)(k - n4u) * R);
+                for (int al = 0; al < no[m]; ++al)
+                    for (int be = 0; be < nJ; ++be) {
+                        const int64_t dst = off + (int64_t)(rm + al) * nJ + be;
+                        G.A[dst] = sys->A_val[in_voff[b] + al * nJ + be];
+                        G.B[dst] = sys->B_val[in_voff[b] + al * nJ + be];
+                    }
+            }
+            rm += no[m];
+        }
+        for (int J : u4list) G.uorb.push_back(h.atom_off[J]);
+        for (int J : u1list) G.uorb.push_back(h.atom_off[J]);
+        G.R.push_back(R);
+        G.roff.push_back((int)G.rows.size());
+        G.u4.push_back(G.uoff.back() + n4u);
+        G.uoff.push_back((int)G.uorb.size());
+        G.voff.push_back(base);
+        ++g;
+    }
+}
+
+struct Rich {
+    int d = 2;
+    double g0 = 0;
+    std::vector<double> tau;  // steps k = 1 .. d-1
+};
+
+// Richardson iteration for B v = s with the d roots of the Chebyshev
+// polynomial of the interval [lo, hi] as inverse step lengths,
+//   x_1 = s / theta_0,  x_{k+1} = x_k + (s - B x_k) / theta_k,
+// so the residual after d-1 products is prod_k (1 - B/theta_k) s, the scaled
+// Chebyshev polynomial T_d((c - B)/h) / T_d(c/h) with c = (hi+lo)/2,
+// h = (hi-lo)/2.  The roots are taken in Leja order, which keeps the
+// intermediate residuals bounded.  d is the smallest degree with
+// 1/T_d(c/h) <= tol.
+Rich richardson_plan(double lo, double hi, double tol) {
+    Rich r;
+    const double cen = 0.5 * (hi + lo), half = 0.5 * (hi - lo);
+    const double sigma = cen / half;
+    double t0 = 1.0, t1 = sigma;
+    int d = 1;
+    while (1.0 / t1 > tol && d < 400) {
+        const double t2 = 2.0 * sigma * t1 - t0;
+        t0 = t1;
+        t1 = t2;
+        ++d;
+    }
+    r.d = std::max(d, 2);
+    const double pi = 3.14159265358979323846;
+    std::vector<double> roots(r.d);
+    for (int i = 0; i < r.d; ++i) roots[i] = cen + half * cos((2.0 * i + 1.0) * pi / (2.0 * r.d));
+    std::vector<double> ord;
+    std::vector<char> used(r.d, 0);
+    int first = 0;
+    for (int i = 1; i < r.d; ++i)
+        if (fabs(roots[i]) > fabs(roots[first])) first = i;
+    used[first] = 1;
+    ord.push_back(roots[first]);
+    for (int k = 1; k < r.d; ++k) {
+        int best = -1;
+        double bv = -1.0;
+        for (int i = 0; i < r.d; ++i) {
+            if (used[i]) continue;
+            double p = 0.0;  // log of the product of distances
+            for (double o : ord) p += log(fabs(roots[i] - o));
+            if (best < 0 || p > bv) {
+                bv = p;
+                best = i;
+            }
+        }
+        used[best] = 1;
+        ord.push_back(roots[best]);
+    }
+    r.g0 = 1.0 / ord[0];
+    for (int k = 1; k < r.d; ++k) r.tau.push_back(1.0 / ord[k]);
+    return r;
+}
+
 }  // namespace
 
 extern "C" {
 
-const char* elses_version(void) { return "elses-gfx950 0.1"; }
+const char* elses_version(void) { return "elses-gfx950 0.2"; }
 
 void elses_opts_default(elses_opts* o) {
     if (!o) return;
@@ -145,10 +363,21 @@ const char* elses_last_error(elses_ctx ctx) { return ctx ? ctx->err.c_str() : "n
 void elses_mat_destroy(elses_mat m) {
     if (!m) return;
     DevMatrix& d = m->d;
-    void* ptrs[] = {d.atom_off, d.orb_atom, d.brow,     d.bsplit, d.borb, d.voff, d.asc_borb,
-                    d.asc_n,    d.asc_voff, d.A,        d.B,      d.A32,  d.B32};
+    void* ptrs[] = {d.atom_off, d.orb_atom, d.brow, d.bsplit, d.borb, d.voff, d.asc_borb,
+                    d.asc_n,    d.asc_voff, d.A,    d.B,      d.A32,  d.B32};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
+    for (auto& C : d.cl) {
+        void* q[] = {C.atom, C.uoff, C.urow, C.bloc};
+        for (void* p : q)
+            if (p) (void)hipFree(p);
+    }
+    {
+        auto& D = d.grp;
+        void* q[] = {D.R, D.roff, D.rows, D.uoff, D.u4, D.uorb, D.voff, D.A, D.B};
+        for (void* p : q)
+            if (p) (void)hipFree(p);
+    }
     delete m;
 }
 
@@ -301,6 +530,47 @@ elses_status elses_mat_create(elses_ctx ctx, const elses_system* sys, int precis
         HCHECK(hipMemcpy(d.asc_borb, asc_borb.data(), sizeof(int) * nnzb, hipMemcpyHostToDevice));
         HCHECK(hipMemcpy(d.asc_n, asc_n.data(), sizeof(int) * nnzb, hipMemcpyHostToDevice));
         HCHECK(hipMemcpy(d.asc_voff, asc_voff.data(), sizeof(int64_t) * nnzb, hipMemcpyHostToDevice));
+        {
+            HostGroups G;
+            build_groups(sys, h, in_voff, G);
+            auto& D = d.grp;
+            D.n = (int)G.R.size();
+            D.nval = (int64_t)G.A.size();
+            D.R = dalloc<int>(G.R.size());
+            D.roff = dalloc<int>(G.roff.size());
+            D.rows = dalloc<int>(G.rows.size());
+            D.uoff = dalloc<int>(G.uoff.size());
+            D.u4 = dalloc<int>(G.u4.size());
+            D.uorb = dalloc<int>(G.uorb.size());
+            D.voff = dalloc<int64_t>(G.voff.size());
+            D.A = dalloc<double>(G.A.size());
+            D.B = dalloc<double>(G.B.size());
+            HCHECK(hipMemcpy(D.R, G.R.data(), sizeof(int) * G.R.size(), hipMemcpyHostToDevice));
+            HCHECK(hipMemcpy(D.roff, G.roff.data(), sizeof(int) * G.roff.size(), hipMemcpyHostToDevice));
+            HCHECK(hipMemcpy(D.rows, G.rows.data(), sizeof(int) * G.rows.size(), hipMemcpyHostToDevice));
+            HCHECK(hipMemcpy(D.uoff, G.uoff.data(), sizeof(int) * G.uoff.size(), hipMemcpyHostToDevice));
+            HCHECK(hipMemcpy(D.u4, G.u4.data(), sizeof(int) * G.u4.size(), hipMemcpyHostToDevice));
+            HCHECK(hipMemcpy(D.uorb, G.uorb.data(), sizeof(int) * G.uorb.size(), hipMemcpyHostToDevice));
+            HCHECK(hipMemcpy(D.voff, G.voff.data(), sizeof(int64_t) * G.voff.size(), hipMemcpyHostToDevice));
+            HCHECK(hipMemcpy(D.A, G.A.data(), sizeof(double) * G.A.size(), hipMemcpyHostToDevice));
+            HCHECK(hipMemcpy(D.B, G.B.data(), sizeof(double) * G.B.size(), hipMemcpyHostToDevice));
+        }
+        for (int sh = 0; sh < kStageShapes; ++sh) {
+            std::vector<int> cl_atom, cl_uoff, cl_urow, bloc;
+            if (build_clusters(kStageWaves[sh], kStageRows[sh], h.atom_off, h.brow, h.bcol, borb, cl_atom, cl_uoff,
+                               cl_urow, bloc)) {
+                DevMatrix::Clusters& C = d.cl[sh];
+                C.n = (int)cl_atom.size() - 1;
+                C.atom = dalloc<int>(cl_atom.size());
+                C.uoff = dalloc<int>(cl_uoff.size());
+                C.urow = dalloc<int>(cl_urow.size());
+                C.bloc = dalloc<int>(bloc.size());
+                HCHECK(hipMemcpy(C.atom, cl_atom.data(), sizeof(int) * cl_atom.size(), hipMemcpyHostToDevice));
+                HCHECK(hipMemcpy(C.uoff, cl_uoff.data(), sizeof(int) * cl_uoff.size(), hipMemcpyHostToDevice));
+                HCHECK(hipMemcpy(C.urow, cl_urow.data(), sizeof(int) * cl_urow.size(), hipMemcpyHostToDevice));
+                HCHECK(hipMemcpy(C.bloc, bloc.data(), sizeof(int) * bloc.size(), hipMemcpyHostToDevice));
+            }
+        }
         HCHECK(hipMemcpy(d.A, Ai.data(), sizeof(double) * nnz, hipMemcpyHostToDevice));
         HCHECK(hipMemcpy(d.B, Bi.data(), sizeof(double) * nnz, hipMemcpyHostToDevice));
         if (precision == ELSES_MIXED) {
@@ -418,48 +688,83 @@ elses_status elses_pattern(elses_mat m, int32_t n_cols, const int32_t* cols, int
 
 namespace {
 
-struct Cheb {
-    int d = 2;
-    double g0 = 0;
-    std::vector<double> omega, gamma;  // steps k = 1 .. d-1
-};
-
-// Chebyshev iteration for B v = s on [lo, hi]:
-//   x_1 = s / theta, x_{k+1} = x_k + rho_k rho_{k-1} (x_k - x_{k-1}) + (2 rho_k / delta)(s - B x_k)
-// with theta = (hi+lo)/2, delta = (hi-lo)/2, sigma = theta/delta, rho_0 = 1/sigma,
-// rho_k = 1/(2 sigma - rho_{k-1}).  After d-1 products the residual is
-// T_d((theta - B)/delta) / T_d(sigma) times the initial one; d is the smallest
-// degree with 1/T_d(sigma) <= tol.
-Cheb chebyshev_plan(double lo, double hi, double tol) {
-    Cheb c;
-    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
-    const double sigma = theta / delta;
-    double t0 = 1.0, t1 = sigma;
-    int d = 1;
-    while (1.0 / t1 > tol && d < 400) {
-        const double t2 = 2.0 * sigma * t1 - t0;
-        t0 = t1;
-        t1 = t2;
-        ++d;
+// Fill the matrix and layout fields of `pa` for the sparse-pass variant
+// (0 auto = grouped with 4 waves per group, 1 direct, 2/3 LDS-staged cluster
+// shape 0/1, 4/5/6 grouped with 4/2/1 waves per group) and block count ld (a
+// multiple of 64).  Returns an error message or null.
+const char* configure_pass(const DevMatrix& d, int variant_in, int ld, PassArgs& pa) {
+    if (ld <= 0 || ld % 64 != 0) return "column block must be a multiple of 64";
+    // bits 4-5 select the workgroup placement, bit 6 forces one column per lane
+    const int variant = variant_in & 15;
+    pa.place = (variant_in >> 4) & 3;
+    const bool force_cpl1 = (variant_in >> 6) & 1;
+    int mode, split = 4;
+    if (variant == 0) {
+        // measured best on MI355X for the hydrocarbon pencils: row groups split
+        // over two waves, XCD regions walked tile-fastest
+        mode = d.grp.n > 0 ? 9 : 0;
+        split = 2;
+        if (variant_in == 0) pa.place = 1;
+    } else if (variant == 1) {
+        mode = 0;
+    } else if (variant >= 2 && variant < 2 + kStageShapes) {
+        if (d.cl[variant - 2].n == 0) return "LDS-staged passes unavailable for this matrix";
+        mode = variant - 1;
+    } else if (variant >= 2 + kStageShapes && variant <= 4 + kStageShapes) {
+        if (d.grp.n == 0) return "grouped passes unavailable for this matrix";
+        mode = 9;
+        split = 4 >> (variant - 2 - kStageShapes);
+    } else {
+        return "variant must be 0 (auto), 1 (direct), 2/3 (LDS-staged) or 4/5/6 (grouped)";
     }
-    c.d = std::max(d, 2);
-    c.g0 = 1.0 / theta;
-    double rho_prev = 1.0 / sigma;
-    for (int k = 1; k < c.d; ++k) {
-        const double rho = 1.0 / (2.0 * sigma - rho_prev);
-        c.omega.push_back(rho * rho_prev);
-        c.gamma.push_back(2.0 * rho / delta);
-        rho_prev = rho;
+    pa.group_split = split;
+    pa.atom_off = d.atom_off;
+    pa.brow = d.brow;
+    pa.bsplit = d.bsplit;
+    pa.borb = d.borb;
+    pa.voff = d.voff;
+    pa.n_atoms = d.n_atoms;
+    pa.ld = ld;
+    pa.staged = mode;
+    pa.atoms_per_slab = kWavesPerBlock;
+    const bool cluster = (mode == 1 || mode == 2);
+    const int cpl = (cluster || force_cpl1) ? 1 : ((ld % 128 == 0) ? 2 : 1);
+    pa.n_tiles = ld / (64 * cpl);
+    // the column split needs the tile count to be a multiple of 8 or to divide 8
+    if (pa.place == 3 && pa.n_tiles % 8 != 0 && 8 % pa.n_tiles != 0) pa.place = 1;
+    if (cluster) {
+        const auto& C = d.cl[mode - 1];
+        pa.n_clusters = C.n;
+        pa.cl_atom = C.atom;
+        pa.cl_uoff = C.uoff;
+        pa.cl_urow = C.urow;
+        pa.bloc = C.bloc;
+        pa.n_slabs = ((C.n + 7) / 8) * 8;
+    } else if (mode == 9) {
+        pa.n_grp = d.grp.n;
+        pa.g_R = d.grp.R;
+        pa.g_roff = d.grp.roff;
+        pa.g_rows = d.grp.rows;
+        pa.g_uoff = d.grp.uoff;
+        pa.g_u4 = d.grp.u4;
+        pa.g_uorb = d.grp.uorb;
+        pa.g_voff = d.grp.voff;
+        const int gpw = kWavesPerBlock / split;  // groups per workgroup
+        pa.n_slabs = (((d.grp.n + gpw - 1) / gpw + 7) / 8) * 8;
+    } else {
+        pa.n_slabs = (((d.n_atoms + kWavesPerBlock - 1) / kWavesPerBlock + 7) / 8) * 8;
     }
-    return c;
+    return nullptr;
 }
 
 int choose_slots(int n_cols, int M, const elses_opts& o) {
     if (o.slots > 0) return o.slots;
     int ld = ((n_cols + 63) / 64) * 64;
-    // keep the five working blocks of [M][ld] doubles within ~1.5 GiB and ld <= 2048
+    // keep the five working blocks of [M][ld] doubles within ~1.5 GiB and ld <= 1024
+    // (per-column cost of the passes is lowest near 1024 columns on MI355X; wider
+    // blocks overflow the 256 MB last-level cache)
     const int64_t cap_mem = (int64_t)(1.5 * 1024 * 1024 * 1024) / (5 * 8 * (int64_t)std::max(M, 1));
-    int cap = (int)std::min<int64_t>(2048, std::max<int64_t>(64, (cap_mem / 64) * 64));
+    int cap = (int)std::min<int64_t>(1024, std::max<int64_t>(64, (cap_mem / 64) * 64));
     ld = std::min(ld, cap);
     if (ld > 128 && ld % 128 != 0 && ld + 64 <= cap) ld += 64;
     return std::max(ld, 64);
@@ -516,12 +821,14 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
     hipStream_t st = ctx->stream;
     const int ld = choose_slots(n_cols, M, o);
     if (ld % 64 != 0) return set_err(ctx, ELSES_ERR_INVALID_ARG, "slot count must be a multiple of 64");
-    const int cpl = (ld % 128 == 0) ? 2 : 1;
-    const int n_tiles = ld / (64 * cpl);
-    const int aps = kWavesPerBlock;  // one atom per wave
-    const int n_slabs = (((d.n_atoms + aps - 1) / aps + 7) / 8) * 8;
+    PassArgs pa{};
+    const char* verr = configure_pass(d, o.variant, ld, pa);
+    if (verr) return set_err(ctx, ELSES_ERR_INVALID_ARG, verr);
+    const int n_groups = pa.n_slabs;
+    const double* valsA = (pa.staged == 9) ? d.grp.A : d.A;
+    const double* valsB = (pa.staged == 9) ? d.grp.B : d.B;
     const int rmax = full ? M : h.pmax;
-    const Cheb ch = chebyshev_plan(mat->b_lo, mat->b_hi, o.inner_tol);
+    const Rich rich = richardson_plan(mat->b_lo, mat->b_hi, o.inner_tol);
 
     // host-side pattern offsets
     std::vector<int64_t> row_off(n_cols + 1, 0);
@@ -545,10 +852,13 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
             buf[i] = pool.get<double>(vsz);
             HCHECK(hipMemsetAsync(buf[i], 0, vsz * sizeof(double), st));
         }
-        double* part0 = pool.get<double>((size_t)n_slabs * ld);
-        double* part1 = pool.get<double>((size_t)n_slabs * ld);
-        HCHECK(hipMemsetAsync(part0, 0, sizeof(double) * n_slabs * ld, st));
-        HCHECK(hipMemsetAsync(part1, 0, sizeof(double) * n_slabs * ld, st));
+        double* part0 = pool.get<double>((size_t)n_groups * ld);
+        double* part1 = pool.get<double>((size_t)n_groups * ld);
+        HCHECK(hipMemsetAsync(part0, 0, sizeof(double) * n_groups * ld, st));
+        HCHECK(hipMemsetAsync(part1, 0, sizeof(double) * n_groups * ld, st));
+        double* red_tmp = pool.get<double>((size_t)((n_groups + 63) / 64) * ld);
+        double* vs = pool.get<double>(ld);
+        double* ss = pool.get<double>(ld);
         double* alpha = pool.get<double>(ld);
         double* beta_prev = pool.get<double>(ld);
         double* inv_beta = pool.get<double>(ld);
@@ -581,7 +891,6 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
 
         ShiftArgs sa{};
         sa.ld = ld;
-        sa.n_slabs = n_slabs;
         sa.K = K;
         sa.M = M;
         sa.z = d_z;
@@ -593,8 +902,8 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         sa.inv_beta = inv_beta;
         sa.coefT = coefT;
         sa.alpha = alpha;
-        sa.part0 = part0;
-        sa.part1 = part1;
+        sa.vs = vs;
+        sa.ss = ss;
         sa.eta = eta;
         sa.zeta = zeta;
         sa.conv = conv;
@@ -622,17 +931,6 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         sa.ctr_out = ctr;
         launch_slot_init(sa, std::min(n_cols, ld), st);
 
-        PassArgs pa{};
-        pa.atom_off = d.atom_off;
-        pa.brow = d.brow;
-        pa.bsplit = d.bsplit;
-        pa.borb = d.borb;
-        pa.voff = d.voff;
-        pa.n_atoms = d.n_atoms;
-        pa.ld = ld;
-        pa.n_slabs = n_slabs;
-        pa.atoms_per_slab = aps;
-        pa.n_tiles = n_tiles;
         pa.inv_beta = inv_beta;
         pa.coefT = coefT;
         pa.alpha = alpha;
@@ -640,7 +938,7 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         pa.slot_row = slot_row;
         pa.part0 = part0;
         pa.part1 = part1;
-        pa.g0 = ch.g0;
+        pa.g0 = rich.g0;
 
         HCHECK(hipHostMalloc((void**)&h_rem, sizeof(int) * 4, hipHostMallocDefault));
         HCHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -676,45 +974,45 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         };
         if (!prof.empty()) {
             ctx->prof_bytes = (double)d.nnz * 8.0 + (double)d.nnzb * 4.0 + (double)d.n_atoms * 20.0 +
-                              4.0 * (double)M * ld * 8.0;
-            ctx->prof_flops = 2.0 * (double)d.nnz * ld + 6.0 * (double)M * ld;
+                              3.0 * (double)M * ld * 8.0;
+            ctx->prof_flops = 2.0 * (double)d.nnz * ld + 3.0 * (double)M * ld;
             ctx->prof_slots = ld;
         }
         for (;;) {
             // w = A q_n, s' = w - beta t_{n-1}, alpha partials, x_1
-            pa.vals = d.A;
+            pa.vals = valsA;
             pa.Xg = Vq;
             pa.Xio = Xa;
             pa.S = Tp;
             pa.Vq = Vq;
             launch_pass(PASS_LANCZOS_A, pa, st);
-            launch_alpha_reduce(part0, n_slabs, ld, slot_n, slot_row, alpha, st);
-            // overlap solve by Chebyshev steps
+            launch_col_reduce(part0, n_groups, ld, red_tmp, slot_n, slot_row, alpha, st);
+            // overlap solve by Richardson steps (Chebyshev roots, Leja order)
             double* xcur = Xa;
             double* xoth = Xb;
-            pa.vals = d.B;
-            for (int k = 1; k < ch.d; ++k) {
+            pa.vals = valsB;
+            pa.Tn = Tn;
+            for (int k = 1; k < rich.d; ++k) {
                 pa.Xg = xcur;
                 pa.Xio = xoth;
-                pa.omega = ch.omega[k - 1];
-                pa.gamma = ch.gamma[k - 1];
-                pa.has_prev = (k >= 2) ? 1 : 0;
-                pa.Tn = Tn;
+                pa.tau = rich.tau[k - 1];
                 EvPair* tp = nullptr;
-                if (!prof.empty() && k == 2 && k < ch.d - 1 && it % ctx->prof_stride == 0)
+                if (!prof.empty() && k == 2 && k < rich.d - 1 && it % ctx->prof_stride == 0)
                     for (auto& p : prof)
                         if (!p.busy) {
                             tp = &p;
                             break;
                         }
                 if (tp) HCHECK(hipEventRecord(tp->a, st));
-                launch_pass(k == ch.d - 1 ? PASS_CHEB_LAST : PASS_CHEB, pa, st);
+                launch_pass(k == rich.d - 1 ? PASS_STEP_LAST : PASS_STEP, pa, st);
                 if (tp) {
                     HCHECK(hipEventRecord(tp->b, st));
                     tp->busy = true;
                 }
                 std::swap(xcur, xoth);
             }
+            launch_col_reduce(part0, n_groups, ld, red_tmp, nullptr, nullptr, vs, st);
+            launch_col_reduce(part1, n_groups, ld, red_tmp, nullptr, nullptr, ss, st);
             // multi-shift recurrences, convergence, slot refill
             sa.Vq = Vq;
             launch_shift_update(sa, st);
@@ -751,7 +1049,7 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
             (void)hipEventDestroy(p.a);
             (void)hipEventDestroy(p.b);
         }
-        ctx->total_passes += it * ch.d;
+        ctx->total_passes += it * rich.d;
         n_notconv = h_rem[2];
         (void)hipEventDestroy(ev);
         (void)hipHostFree(h_rem);
@@ -809,32 +1107,85 @@ elses_status elses_ctx_pass_stats(elses_ctx ctx, int64_t* launches, double* avg_
     return ELSES_OK;
 }
 
-elses_status elses_spmm(elses_ctx ctx, elses_mat mat, int which, int32_t nvec, const double* x, double* y) {
+elses_status elses_time_pass(elses_ctx ctx, elses_mat mat, int32_t kind, int32_t variant, int32_t slots,
+                             int32_t reps, double* avg_us) {
+    if (!ctx || !mat || !avg_us) return ELSES_ERR_INVALID_ARG;
+    if (kind < 0 || kind > 3 || reps < 1) return set_err(ctx, ELSES_ERR_INVALID_ARG, "bad kind or reps");
+    const DevMatrix& d = mat->d;
+    PassArgs pa{};
+    const char* verr = configure_pass(d, variant, slots, pa);
+    if (verr) return set_err(ctx, ELSES_ERR_INVALID_ARG, verr);
+    hipStream_t st = ctx->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    try {
+        DevPool pool;
+        const size_t vsz = (size_t)d.M * slots;
+        double* X = pool.get<double>(vsz);
+        double* Y = pool.get<double>(vsz);
+        double* S = pool.get<double>(vsz);
+        double* V = pool.get<double>(vsz);
+        double* T = pool.get<double>(vsz);
+        for (double* p : {X, Y, S, V, T}) HCHECK(hipMemsetAsync(p, 0, vsz * sizeof(double), st));
+        double* part0 = pool.get<double>((size_t)pa.n_slabs * slots);
+        double* part1 = pool.get<double>((size_t)pa.n_slabs * slots);
+        double* sc = pool.get<double>((size_t)3 * slots);
+        int* si = pool.get<int>((size_t)2 * slots);
+        HCHECK(hipMemsetAsync(sc, 0, sizeof(double) * 3 * slots, st));
+        HCHECK(hipMemsetAsync(si, 0, sizeof(int) * 2 * slots, st));
+        pa.vals = (pa.staged == 9) ? d.grp.B : d.B;
+        pa.Xg = X;
+        pa.Xio = Y;
+        pa.S = S;
+        pa.Vq = V;
+        pa.Tn = T;
+        pa.inv_beta = sc;
+        pa.coefT = sc + slots;
+        pa.alpha = sc + 2 * slots;
+        pa.slot_n = si;
+        pa.slot_row = si + slots;
+        pa.part0 = part0;
+        pa.part1 = part1;
+        pa.tau = 0.5;
+        pa.g0 = 0.5;
+        const PassKind pk = static_cast<PassKind>(kind);
+        launch_pass(pk, pa, st);  // warm-up
+        HCHECK(hipEventCreate(&e0));
+        HCHECK(hipEventCreate(&e1));
+        HCHECK(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) launch_pass(pk, pa, st);
+        HCHECK(hipEventRecord(e1, st));
+        HCHECK(hipEventSynchronize(e1));
+        HCHECK(hipGetLastError());
+        float ms = 0.f;
+        HCHECK(hipEventElapsedTime(&ms, e0, e1));
+        *avg_us = 1000.0 * ms / reps;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    } catch (const HipFail& f) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return set_err(ctx, ELSES_ERR_HIP, std::string(f.what) + ": " + hipGetErrorString(f.e));
+    }
+    return ELSES_OK;
+}
+
+elses_status elses_spmm(elses_ctx ctx, elses_mat mat, int which, int32_t variant, int32_t nvec, const double* x,
+                        double* y) {
     if (!ctx || !mat) return ELSES_ERR_INVALID_ARG;
     if ((which != 0 && which != 1) || nvec < 1 || !x || !y)
         return set_err(ctx, ELSES_ERR_INVALID_ARG, "bad arguments");
     const DevMatrix& d = mat->d;
     hipStream_t st = ctx->stream;
-    const double* vals = which == 0 ? d.A : d.B;
     if (nvec % 64 == 0) {
         PassArgs pa{};
-        pa.atom_off = d.atom_off;
-        pa.brow = d.brow;
-        pa.bsplit = d.bsplit;
-        pa.borb = d.borb;
-        pa.voff = d.voff;
-        pa.vals = vals;
-        pa.n_atoms = d.n_atoms;
-        pa.ld = nvec;
-        pa.atoms_per_slab = kWavesPerBlock;
-        pa.n_slabs = (((d.n_atoms + kWavesPerBlock - 1) / kWavesPerBlock + 7) / 8) * 8;
-        const int cpl = (nvec % 128 == 0) ? 2 : 1;
-        pa.n_tiles = nvec / (64 * cpl);
+        const char* verr = configure_pass(d, variant, nvec, pa);
+        if (verr) return set_err(ctx, ELSES_ERR_INVALID_ARG, verr);
+        pa.vals = (pa.staged == 9) ? (which == 0 ? d.grp.A : d.grp.B) : (which == 0 ? d.A : d.B);
         pa.Xg = x;
         pa.Xio = y;
         launch_pass(PASS_PLAIN, pa, st);
     } else {
-        launch_spmm_generic(d, vals, nvec, nvec, x, y, st);
+        launch_spmm_generic(d, which == 0 ? d.A : d.B, nvec, nvec, x, y, st);
     }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
         return set_err(ctx, ELSES_ERR_HIP, "spmm launch failed");

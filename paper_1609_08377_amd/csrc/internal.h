@@ -12,8 +12,14 @@
 namespace elses {
 
 constexpr int kWave = 64;         // CDNA wavefront width
-constexpr int kBlock = 256;       // threads per workgroup for the vector passes
+constexpr int kBlock = 256;       // threads per workgroup for the direct passes
 constexpr int kWavesPerBlock = kBlock / kWave;
+// Staged passes: cluster shapes {atoms (= waves) per cluster, LDS rows of 64
+// doubles}.  Shape 0 uses 147 KB of the 160 KB LDS (one workgroup per CU),
+// shape 1 uses 72 KB (two workgroups per CU).
+constexpr int kStageShapes = 2;
+constexpr int kStageWaves[kStageShapes] = {8, 4};
+constexpr int kStageRows[kStageShapes] = {288, 144};
 
 // Atom-block sparse matrix on the device.  Atoms carry 4 or 1 orbitals, in
 // any order.  Internally the blocks of row atom I are reordered so that the
@@ -37,7 +43,34 @@ struct DevMatrix {
     int64_t *asc_voff = nullptr;  // [nnzb] ascending order: value offset of the block
     double *A = nullptr, *B = nullptr;  // [nnz] internal layout
     float *A32 = nullptr, *B32 = nullptr;
+    // clusters of consecutive atoms for the LDS-staged passes, per shape
+    struct Clusters {
+        int n = 0;            // 0: shape unavailable
+        int *atom = nullptr;  // [n+1] first atom of each cluster
+        int *uoff = nullptr;  // [n+1] offsets into urow
+        int *urow = nullptr;  // union of coupled orbitals of each cluster (ascending)
+        int *bloc = nullptr;  // [nnzb] internal order: LDS row of the coupled atom's first orbital
+    } cl[kStageShapes];
+    // Row groups for the grouped passes: a 4-orbital atom with up to
+    // kGroupH 1-orbital atoms it couples to most strongly (or a single atom).
+    // A group's rows share one gather of the union of their coupled atoms;
+    // its values are dense R x n_J blocks over that union (zero where a
+    // member does not couple), 4-orbital union atoms first.
+    struct Groups {
+        int n = 0;
+        int *R = nullptr;         // [n] rows of each group (1, 4..4+kGroupH)
+        int *roff = nullptr;      // [n+1] offsets into rows
+        int *rows = nullptr;      // member orbitals: the 4-orbital atom's rows, then each H row
+        int *uoff = nullptr;      // [n+1] offsets into uorb
+        int *u4 = nullptr;        // [n] end of the 4-orbital part of the union
+        int *uorb = nullptr;      // first orbital of each union atom
+        int64_t *voff = nullptr;  // [n] value offset of the group's dense blocks
+        double *A = nullptr, *B = nullptr;
+        int64_t nval = 0;
+    } grp;
 };
+
+constexpr int kGroupH = 4;
 
 struct HostMatrix {
     int n_atoms = 0, M = 0;
@@ -78,7 +111,7 @@ namespace elses {
 // ---------------------------------------------------------------------------
 // Vector passes over the atom-block matrix (lanes = right-hand sides).
 // ---------------------------------------------------------------------------
-enum PassKind { PASS_LANCZOS_A = 0, PASS_CHEB = 1, PASS_CHEB_LAST = 2, PASS_PLAIN = 3 };
+enum PassKind { PASS_LANCZOS_A = 0, PASS_STEP = 1, PASS_STEP_LAST = 2, PASS_PLAIN = 3 };
 
 struct PassArgs {
     // matrix
@@ -89,26 +122,33 @@ struct PassArgs {
     const int64_t *voff;
     const double *vals;
     int n_atoms;
-    // layout: vectors are [M][ld] doubles, ld = slot count.  Slabs are groups
-    // of atoms_per_slab consecutive atoms (one per wave); n_slabs is a
-    // multiple of 8 (trailing slabs may be empty).
+    // layout: vectors are [M][ld] doubles, ld = slot count.  Direct passes:
+    // slabs are groups of atoms_per_slab consecutive atoms (one per wave).
+    // Staged passes: the groups are the clusters.  n_slabs (groups) is a
+    // multiple of 8; trailing groups may be empty.
     int ld;
     int n_slabs, atoms_per_slab, n_tiles;
+    int staged;  // 0: direct gathers; 1 + s: LDS-staged with cluster shape s; 9: row groups
+    int n_clusters;
+    const int *cl_atom, *cl_uoff, *cl_urow, *bloc;
+    int n_grp, group_split;  // row groups; waves sharing one group (1, 2 or 4)
+    int place;               // workgroup placement (0 XCD regions tile by tile, 1 XCD regions tile-fastest, 2 plain)
+    const int *g_R, *g_roff, *g_rows, *g_uoff, *g_u4, *g_uorb;
+    const int64_t *g_voff;
     // vectors
     const double *Xg;   // gathered operand
-    double *Xio;        // CHEB: in x_{k-1} (if has_prev), out x_{k+1}; LANCZOS_A: out x_1; PLAIN: out y
-    double *S;          // LANCZOS_A: in t_{n-1} / out s'; CHEB: in s; CHEB_LAST: in s', out s
-    const double *Vq;   // CHEB_LAST / LANCZOS_A: q_n (unnormalised, own rows)
-    const double *Tn;   // CHEB_LAST: t_n (unnormalised, own rows)
+    double *Xio;        // STEP: out x_{k+1}; LANCZOS_A: out x_1; PLAIN: out y
+    double *S;          // LANCZOS_A: in t_{n-1} / out s'; STEP: in s; STEP_LAST: in s', out s
+    const double *Vq;   // STEP_LAST / LANCZOS_A: q_n (unnormalised, own rows)
+    const double *Tn;   // STEP_LAST: t_n (unnormalised, own rows)
     // per-slot scalars
     const double *inv_beta;   // 1/beta_{n-1}
     const double *coefT;      // beta_{n-1}/beta_{n-2}
     const double *alpha;      // alpha_n (reduced)
     const int *slot_n;        // iteration counter (0 = start vector)
     const int *slot_row;      // e_j row of the slot's column (-1 idle)
-    // Chebyshev step x_{k+1} = x_k + omega (x_k - x_{k-1}) + gamma (s - B x_k)
-    double omega, gamma;
-    int has_prev;
+    // Richardson step x_{k+1} = x_k + tau (s - B x_k)
+    double tau;
     double g0;                // x_1 = g0 * s
     // dot partials [n_slabs][ld]
     double *part0, *part1;
@@ -121,7 +161,6 @@ void launch_pass(PassKind kind, const PassArgs &a, hipStream_t st);
 // ---------------------------------------------------------------------------
 struct ShiftArgs {
     int ld;          // slot count
-    int n_slabs;
     int K;           // shifts
     int M;
     const double *z; // [K] complex
@@ -134,7 +173,7 @@ struct ShiftArgs {
     double *inv_beta;
     double *coefT;
     const double *alpha;
-    const double *part0, *part1;   // v.s, s.s partials
+    const double *vs, *ss;         // v.s and s.s per slot (reduced)
     double *eta, *zeta;            // [ld][K] complex
     int *conv;                     // [ld][K] iteration of convergence, 0 active
     double *res;                   // [ld][K]
@@ -162,8 +201,10 @@ struct ShiftArgs {
     double *ctr_out;               // [n_cols][2] per-column traces (may be null)
 };
 
-void launch_alpha_reduce(const double *part, int n_slabs, int ld, const int *slot_n, const int *slot_row,
-                         double *alpha, hipStream_t st);
+// out[c] = sum over n_part partial rows (deterministic, two stages; tmp holds
+// ceil(n_part/64) x ld doubles).  With slot_n given, idle or starting slots get 0.
+void launch_col_reduce(const double *part, int n_part, int ld, double *tmp, const int *slot_n, const int *slot_row,
+                       double *out, hipStream_t st);
 void launch_shift_update(const ShiftArgs &a, hipStream_t st);
 void launch_pattern_setup(const DevMatrix &m, int n_cols, const int *cols, const int64_t *row_off, int *rows,
                           int64_t *vidx, hipStream_t st);

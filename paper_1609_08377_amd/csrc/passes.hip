@@ -2,85 +2,33 @@
 //
 // Every pass multiplies one sparse matrix (A or B) with a block of right-hand
 // sides stored [M][ld] (ld = slots, one right-hand side per lane), and fuses
-// the element-wise work of one step of the solver into the epilogue, so the
-// vectors cross HBM as few times as possible:
+// the element-wise work of one solver step into the epilogue, so the vectors
+// cross HBM as few times as possible:
 //
 //   PASS_LANCZOS_A  w = A q_n; s' = w - beta_{n-1} t_{n-1}; partial q_n.s';
 //                   x_1 = g0 s' (first overlap-solve iterate).  Slots at
 //                   n = 0 take s' = e_j instead (start vector B^{-1} e_j).
-//   PASS_CHEB       one Chebyshev step of the overlap solve B v = s:
-//                   x_{k+1} = x_k + omega (x_k - x_{k-1}) + gamma (s - B x_k)
-//   PASS_CHEB_LAST  the last step, then the deferred Lanczos correction
+//   PASS_STEP       one Richardson step of the overlap solve B v = s:
+//                   x_{k+1} = x_k + tau_k (s - B x_k)
+//   PASS_STEP_LAST  the last step, then the deferred Lanczos correction
 //                   v = x - alpha_n q_n, s = s' - alpha_n t_n, and partial
 //                   dots v.s and s.s (beta_n^2 and ||s||^2).
 //   PASS_PLAIN      y = X x.
 //
 // Matrix values are identical for all lanes of a wave, so they are read
 // through the scalar unit; each lane streams its own right-hand side.
+//
+// Two gather strategies for the right-hand-side rows of the coupled atoms:
+//   direct  one atom per wave, rows read through L1/L2 (pass_kernel);
+//   staged  a workgroup takes a cluster of consecutive atoms (one per wave),
+//           copies the union of their coupled rows for its 64-column tile into
+//           LDS once, and every wave reads its gathers from LDS
+//           (pass_lds_kernel).  Atoms numbered with spatial locality make the
+//           union small, so each row crosses L2 once per cluster instead of
+//           once per coupled atom.
 #include "internal.h"
 
 namespace elses {
-
-template <int NI, int CPL>
-__device__ __forceinline__ void row_product(int I, int ld, int c0, const double* __restrict__ Xg,
-                                            const int* __restrict__ brow, const int* __restrict__ bsplit,
-                                            const int* __restrict__ borb, const int64_t* __restrict__ voff,
-                                            const double* __restrict__ vals, double (&acc)[NI][CPL]) {
-#pragma unroll
-    for (int a = 0; a < NI; ++a)
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) acc[a][c] = 0.0;
-    const int b0 = brow[I], bs = bsplit[I], b1 = brow[I + 1];
-    const double* __restrict__ v = vals + voff[I];
-    // 4-orbital neighbours
-#pragma unroll 2
-    for (int b = b0; b < bs; ++b) {
-        const int o = borb[b];
-        const double* __restrict__ xr = Xg + (size_t)o * ld + c0;
-        double x[4][CPL];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if constexpr (CPL == 2) {
-                const double2 t = *reinterpret_cast<const double2*>(xr + (size_t)q * ld);
-                x[q][0] = t.x;
-                x[q][1] = t.y;
-            } else {
-                x[q][0] = xr[(size_t)q * ld];
-            }
-        }
-        const double* __restrict__ vb = v + (size_t)(b - b0) * (NI * 4);
-#pragma unroll
-        for (int a = 0; a < NI; ++a)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double m = vb[a * 4 + q];
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) acc[a][c] = fma(m, x[q][c], acc[a][c]);
-            }
-    }
-    // 1-orbital neighbours
-    const double* __restrict__ vh = v + (size_t)(bs - b0) * (NI * 4);
-#pragma unroll 4
-    for (int b = bs; b < b1; ++b) {
-        const int o = borb[b];
-        const double* __restrict__ xr = Xg + (size_t)o * ld + c0;
-        double x[CPL];
-        if constexpr (CPL == 2) {
-            const double2 t = *reinterpret_cast<const double2*>(xr);
-            x[0] = t.x;
-            x[1] = t.y;
-        } else {
-            x[0] = xr[0];
-        }
-        const double* __restrict__ vb = vh + (size_t)(b - bs) * NI;
-#pragma unroll
-        for (int a = 0; a < NI; ++a) {
-            const double m = vb[a];
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) acc[a][c] = fma(m, x[c], acc[a][c]);
-        }
-    }
-}
 
 template <int CPL>
 __device__ __forceinline__ void load_cols(const double* p, size_t idx, double (&r)[CPL]) {
@@ -102,11 +50,122 @@ __device__ __forceinline__ void store_cols(double* p, size_t idx, const double (
     }
 }
 
+// Row product of atom I with the gathered operand.  `Src` maps the first
+// orbital o of a coupled atom (as stored in `bidx`) to the CPL values of row
+// o + q for this lane.
+// acc[R][:] = sum over the coupled atoms b of (R x n_b block) * (rows of b).
+// Coupled atoms [b0, bs) carry 4 orbitals, [bs, b1) one; idx[b] locates the
+// first row of atom b for `src`; the blocks' values are contiguous from v
+// (the R x 4 blocks, then the R x 1 blocks, row-major).  A wave takes every
+// KS-th coupled atom starting at `sub`.  Gathers are issued in chunks (two
+// 4-orbital atoms or eight 1-orbital atoms) before their FMAs, so several L2
+// round trips overlap within one wave.
+template <int R, int CPL, int KS, typename Src>
+__device__ __forceinline__ void block_product(int b0, int bs, int b1, int sub, const int* __restrict__ idx,
+                                              const double* __restrict__ v, const Src& src,
+                                              double (&acc)[R][CPL]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) acc[r][c] = 0.0;
+    constexpr int C4 = 2, C1 = 8;
+    int b = b0 + sub;
+    for (; b + (C4 - 1) * KS < bs; b += C4 * KS) {
+        double x[C4][4][CPL];
+#pragma unroll
+        for (int j = 0; j < C4; ++j) {
+            const int o = idx[b + j * KS];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) src.get(o + q, x[j][q]);
+        }
+#pragma unroll
+        for (int j = 0; j < C4; ++j) {
+            const double* __restrict__ vb = v + (size_t)(b + j * KS - b0) * (R * 4);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double m = vb[r * 4 + q];
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) acc[r][c] = fma(m, x[j][q][c], acc[r][c]);
+                }
+        }
+    }
+    for (; b < bs; b += KS) {
+        const int o = idx[b];
+        double x[4][CPL];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) src.get(o + q, x[q]);
+        const double* __restrict__ vb = v + (size_t)(b - b0) * (R * 4);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double m = vb[r * 4 + q];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) acc[r][c] = fma(m, x[q][c], acc[r][c]);
+            }
+    }
+    const double* __restrict__ vh = v + (size_t)(bs - b0) * (R * 4);
+    b = bs + sub;
+    for (; b + (C1 - 1) * KS < b1; b += C1 * KS) {
+        double x[C1][CPL];
+#pragma unroll
+        for (int j = 0; j < C1; ++j) src.get(idx[b + j * KS], x[j]);
+#pragma unroll
+        for (int j = 0; j < C1; ++j) {
+            const double* __restrict__ vb = vh + (size_t)(b + j * KS - bs) * R;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double m = vb[r];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) acc[r][c] = fma(m, x[j][c], acc[r][c]);
+            }
+        }
+    }
+    for (; b < b1; b += KS) {
+        double x[CPL];
+        src.get(idx[b], x);
+        const double* __restrict__ vb = vh + (size_t)(b - bs) * R;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double m = vb[r];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) acc[r][c] = fma(m, x[c], acc[r][c]);
+        }
+    }
+}
+
+template <int NI, int CPL, typename Src>
+__device__ __forceinline__ void row_product(int I, const int* __restrict__ brow, const int* __restrict__ bsplit,
+                                            const int* __restrict__ bidx, const int64_t* __restrict__ voff,
+                                            const double* __restrict__ vals, const Src& src,
+                                            double (&acc)[NI][CPL]) {
+    block_product<NI, CPL, 1>(brow[I], bsplit[I], brow[I + 1], 0, bidx, vals + voff[I], src, acc);
+}
+
+template <int CPL>
+struct GlobalSrc {
+    const double* __restrict__ X;
+    int ld, c0;
+    __device__ __forceinline__ void get(int row, double (&r)[CPL]) const { load_cols<CPL>(X, (size_t)row * ld + c0, r); }
+};
+
+// LDS tile [rows][64] doubles, one column per lane
+struct LdsSrc {
+    const double* tile;
+    int lane;
+    __device__ __forceinline__ void get(int row, double (&r)[1]) const { r[0] = tile[row * kWave + lane]; }
+};
+
+struct ColState {
+    double A, B, al;
+    int n, r;
+};
+
 template <int KIND, int NI, int CPL>
 __device__ __forceinline__ void epilogue(const PassArgs& a, int row, int c0, const double (&acc)[NI][CPL], int arow,
-                                         const double (&colA)[CPL], const double (&colB)[CPL],
-                                         const int (&coln)[CPL], const int (&colr)[CPL], const double (&colal)[CPL],
-                                         double (&d0)[CPL], double (&d1)[CPL]) {
+                                         const ColState (&cs)[CPL], double (&d0)[CPL], double (&d1)[CPL]) {
     const size_t idx = (size_t)row * a.ld + c0;
     if constexpr (KIND == PASS_PLAIN) {
         double y[CPL];
@@ -114,35 +173,29 @@ __device__ __forceinline__ void epilogue(const PassArgs& a, int row, int c0, con
         for (int c = 0; c < CPL; ++c) y[c] = acc[arow][c];
         store_cols<CPL>(a.Xio, idx, y);
     } else if constexpr (KIND == PASS_LANCZOS_A) {
-        // colA = 1/beta_{n-1}, colB = beta_{n-1}/beta_{n-2}
+        // cs.A = 1/beta_{n-1}, cs.B = beta_{n-1}/beta_{n-2}
         double tp[CPL], vq[CPL], sp[CPL], x1[CPL];
         load_cols<CPL>(a.S, idx, tp);
         load_cols<CPL>(a.Vq, idx, vq);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            if (coln[c] == 0) {
-                sp[c] = (row == colr[c]) ? 1.0 : 0.0;
+            if (cs[c].n == 0) {
+                sp[c] = (row == cs[c].r) ? 1.0 : 0.0;
             } else {
-                sp[c] = acc[arow][c] * colA[c] - colB[c] * tp[c];
-                d0[c] = fma(vq[c] * colA[c], sp[c], d0[c]);
+                sp[c] = acc[arow][c] * cs[c].A - cs[c].B * tp[c];
+                d0[c] = fma(vq[c] * cs[c].A, sp[c], d0[c]);
             }
             x1[c] = a.g0 * sp[c];
         }
         store_cols<CPL>(a.S, idx, sp);
         store_cols<CPL>(a.Xio, idx, x1);
     } else {
-        double xk[CPL], xp[CPL], s[CPL], xn[CPL];
+        double xk[CPL], s[CPL], xn[CPL];
         load_cols<CPL>(a.Xg, idx, xk);
-        if (a.has_prev) {
-            load_cols<CPL>(a.Xio, idx, xp);
-        } else {
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) xp[c] = 0.0;
-        }
         load_cols<CPL>(a.S, idx, s);
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) xn[c] = xk[c] + a.omega * (xk[c] - xp[c]) + a.gamma * (s[c] - acc[arow][c]);
-        if constexpr (KIND == PASS_CHEB) {
+        for (int c = 0; c < CPL; ++c) xn[c] = xk[c] + a.tau * (s[c] - acc[arow][c]);
+        if constexpr (KIND == PASS_STEP) {
             store_cols<CPL>(a.Xio, idx, xn);
         } else {
             double vq[CPL], tn[CPL];
@@ -150,8 +203,8 @@ __device__ __forceinline__ void epilogue(const PassArgs& a, int row, int c0, con
             load_cols<CPL>(a.Tn, idx, tn);
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                if (coln[c] != 0) {
-                    const double f = colal[c] * colA[c];
+                if (cs[c].n != 0) {
+                    const double f = cs[c].al * cs[c].A;
                     xn[c] -= f * vq[c];
                     s[c] -= f * tn[c];
                 }
@@ -165,106 +218,334 @@ __device__ __forceinline__ void epilogue(const PassArgs& a, int row, int c0, con
 }
 
 template <int KIND, int CPL>
-__global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a, const int* __restrict__ brow,
-                                                      const int* __restrict__ bsplit, const int* __restrict__ borb,
-                                                      const int64_t* __restrict__ voff,
-                                                      const double* __restrict__ vals,
-                                                      const int* __restrict__ atom_off) {
-    // XCD-aware placement: workgroups are dispatched round-robin over the 8
-    // XCDs (workgroup L runs on XCD L % 8).  XCD x owns the x-th eighth of the
-    // slabs -- a compact region of space, since atoms are numbered with
-    // spatial locality -- and walks it tile by tile, so the right-hand-side
-    // rows its slabs gather (the region plus a cutoff halo) stay in its L2.
-    const int s8 = a.n_slabs >> 3;
-    const int L = blockIdx.x;
-    const int k = L >> 3;
-    const int tile = k / s8;
-    const int slab = (L & 7) * s8 + (k - tile * s8);
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int c0 = tile * (kWave * CPL) + lane * CPL;
-
-    double colA[CPL], colB[CPL], colal[CPL];
-    int coln[CPL], colr[CPL];
+__device__ __forceinline__ void load_colstate(const PassArgs& a, int c0, ColState (&cs)[CPL]) {
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
-        colA[c] = colB[c] = colal[c] = 0.0;
-        coln[c] = 0;
-        colr[c] = -1;
-    }
-    if constexpr (KIND == PASS_LANCZOS_A || KIND == PASS_CHEB_LAST) {
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            colA[c] = a.inv_beta[c0 + c];
-            coln[c] = a.slot_n[c0 + c];
-            colr[c] = a.slot_row[c0 + c];
-            if constexpr (KIND == PASS_LANCZOS_A) colB[c] = a.coefT[c0 + c];
-            if constexpr (KIND == PASS_CHEB_LAST) colal[c] = a.alpha[c0 + c];
+        cs[c] = {0.0, 0.0, 0.0, 0, -1};
+        if constexpr (KIND == PASS_LANCZOS_A || KIND == PASS_STEP_LAST) {
+            cs[c].A = a.inv_beta[c0 + c];
+            cs[c].n = a.slot_n[c0 + c];
+            cs[c].r = a.slot_row[c0 + c];
+            if constexpr (KIND == PASS_LANCZOS_A) cs[c].B = a.coefT[c0 + c];
+            if constexpr (KIND == PASS_STEP_LAST) cs[c].al = a.alpha[c0 + c];
         }
     }
-    double d0[CPL], d1[CPL];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) d0[c] = d1[c] = 0.0;
+}
 
-    const int first = slab * a.atoms_per_slab;
-    const int last = min(first + a.atoms_per_slab, a.n_atoms);  // empty for trailing slabs
-    for (int I = first + wave; I < last; I += kWavesPerBlock) {
-        if (atom_off[I + 1] - atom_off[I] == 4) {
-            double acc[4][CPL];
-            row_product<4, CPL>(I, a.ld, c0, a.Xg, brow, bsplit, borb, voff, vals, acc);
-            const int r0 = atom_off[I];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                epilogue<KIND, 4, CPL>(a, r0 + q, c0, acc, q, colA, colB, coln, colr, colal, d0, d1);
-        } else {
-            double acc[1][CPL];
-            row_product<1, CPL>(I, a.ld, c0, a.Xg, brow, bsplit, borb, voff, vals, acc);
-            epilogue<KIND, 1, CPL>(a, atom_off[I], c0, acc, 0, colA, colB, coln, colr, colal, d0, d1);
-        }
-    }
-    if constexpr (KIND == PASS_LANCZOS_A || KIND == PASS_CHEB_LAST) {
-        __shared__ double red[2][kWavesPerBlock][kWave * CPL];
+// Reduce the per-lane dot partials over the waves of the workgroup and store
+// one partial per (group, column).
+template <int KIND, int CPL, int NW>
+__device__ __forceinline__ void store_partials(const PassArgs& a, int group, int c0, int wave, int lane,
+                                               const double (&d0)[CPL], const double (&d1)[CPL], double* red) {
+    if constexpr (KIND == PASS_LANCZOS_A || KIND == PASS_STEP_LAST) {
+        __syncthreads();
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            red[0][wave][lane * CPL + c] = d0[c];
-            red[1][wave][lane * CPL + c] = d1[c];
+            red[(0 * NW + wave) * (kWave * CPL) + lane * CPL + c] = d0[c];
+            red[(1 * NW + wave) * (kWave * CPL) + lane * CPL + c] = d1[c];
         }
         __syncthreads();
         if (wave == 0) {
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-                for (int w = 0; w < kWavesPerBlock; ++w) {
-                    s0 += red[0][w][lane * CPL + c];
-                    s1 += red[1][w][lane * CPL + c];
+                for (int w = 0; w < NW; ++w) {
+                    s0 += red[(0 * NW + w) * (kWave * CPL) + lane * CPL + c];
+                    s1 += red[(1 * NW + w) * (kWave * CPL) + lane * CPL + c];
                 }
-                a.part0[(size_t)slab * a.ld + c0 + c] = s0;
-                if constexpr (KIND == PASS_CHEB_LAST) a.part1[(size_t)slab * a.ld + c0 + c] = s1;
+                a.part0[(size_t)group * a.ld + c0 + c] = s0;
+                if constexpr (KIND == PASS_STEP_LAST) a.part1[(size_t)group * a.ld + c0 + c] = s1;
             }
         }
     }
 }
 
+// XCD-aware placement: workgroups are dispatched round-robin over the 8 XCDs
+// (workgroup L runs on XCD L % 8).  XCD x owns the x-th eighth of the groups
+// -- a compact region of space, since atoms are numbered with spatial
+// locality -- and walks it tile by tile, so the right-hand-side rows its
+// groups gather (the region plus a cutoff halo) stay in its L2.
+// place = 1 keeps the XCD's eighth of the groups but walks it with the tile
+// index fastest (a smaller region, all columns); place = 2 ignores the XCDs
+// (tile-major over all groups).  place = 3 splits the columns instead of
+// space: with n_tiles a multiple of 8, XCD x owns tiles x, x+8, ... over all
+// groups, so every right-hand-side row is fetched into exactly one XCD's L2
+// per tile (no halo duplication between XCDs); with n_tiles dividing 8, the
+// 8 / n_tiles XCDs sharing a tile split the groups into contiguous parts.
+__device__ __forceinline__ void xcd_place(int n_groups, int n_tiles, int place, int& tile, int& group) {
+    const int s8 = n_groups >> 3;
+    const int L = blockIdx.x;
+    const int x = L & 7;
+    const int k = L >> 3;
+    if (place == 0) {
+        tile = k / s8;
+        group = x * s8 + (k - tile * s8);
+    } else if (place == 1) {
+        tile = k % n_tiles;
+        group = x * s8 + k / n_tiles;
+    } else if (place == 3) {
+        if (n_tiles >= 8) {
+            const int tl = k / n_groups;
+            tile = x + 8 * tl;
+            group = k - tl * n_groups;
+        } else {
+            const int parts = 8 / n_tiles;
+            const int gp = n_groups / parts;
+            tile = x % n_tiles;
+            group = (x / n_tiles) * gp + k;
+        }
+    } else {
+        tile = L / n_groups;
+        group = L - tile * n_groups;
+    }
+}
+
+template <int KIND, int CPL>
+__global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a, const int* __restrict__ brow,
+                                                      const int* __restrict__ bsplit, const int* __restrict__ borb,
+                                                      const int64_t* __restrict__ voff,
+                                                      const double* __restrict__ vals,
+                                                      const int* __restrict__ atom_off) {
+    int tile, slab;
+    xcd_place(a.n_slabs, a.n_tiles, a.place, tile, slab);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c0 = tile * (kWave * CPL) + lane * CPL;
+    ColState cs[CPL];
+    load_colstate<KIND, CPL>(a, c0, cs);
+    double d0[CPL], d1[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) d0[c] = d1[c] = 0.0;
+    const GlobalSrc<CPL> src{a.Xg, a.ld, c0};
+    const int first = slab * a.atoms_per_slab;
+    const int last = min(first + a.atoms_per_slab, a.n_atoms);  // empty for trailing slabs
+    for (int I = first + wave; I < last; I += kWavesPerBlock) {
+        if (atom_off[I + 1] - atom_off[I] == 4) {
+            double acc[4][CPL];
+            row_product<4, CPL>(I, brow, bsplit, borb, voff, vals, src, acc);
+            const int r0 = atom_off[I];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) epilogue<KIND, 4, CPL>(a, r0 + q, c0, acc, q, cs, d0, d1);
+        } else {
+            double acc[1][CPL];
+            row_product<1, CPL>(I, brow, bsplit, borb, voff, vals, src, acc);
+            epilogue<KIND, 1, CPL>(a, atom_off[I], c0, acc, 0, cs, d0, d1);
+        }
+    }
+    __shared__ double red[2 * kWavesPerBlock * kWave * CPL];
+    store_partials<KIND, CPL, kWavesPerBlock>(a, slab, c0, wave, lane, d0, d1, red);
+}
+
+// Staged variant: NW waves, cluster = atoms [cl_atom[g], cl_atom[g+1]) (at
+// most NW), union rows cl_urow[cl_uoff[g] .. cl_uoff[g+1]) (at most NU) staged
+// in LDS; bloc[b] is the LDS row of block b's first coupled orbital.
+template <int KIND, int NW, int NU>
+__global__ __launch_bounds__(NW* kWave) void pass_lds_kernel(PassArgs a, const int* __restrict__ brow,
+                                                            const int* __restrict__ bsplit,
+                                                            const int* __restrict__ bloc,
+                                                            const int64_t* __restrict__ voff,
+                                                            const double* __restrict__ vals,
+                                                            const int* __restrict__ atom_off) {
+    __shared__ double tile_x[NU * kWave];
+    int tile, g;
+    xcd_place(a.n_slabs, a.n_tiles, a.place, tile, g);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c0 = tile * kWave + lane;
+    ColState cs[1];
+    load_colstate<KIND, 1>(a, c0, cs);
+    double d0[1] = {0.0}, d1[1] = {0.0};
+    int first = 0, last = 0;
+    if (g < a.n_clusters) {
+        first = a.cl_atom[g];
+        last = a.cl_atom[g + 1];
+        const int u0 = a.cl_uoff[g], nu = a.cl_uoff[g + 1] - u0;
+        const int* __restrict__ ur = a.cl_urow + u0;
+        // stage the union rows of this column tile (one 512-byte row per wave
+        // step), issuing four row loads before their LDS stores
+        int u = wave;
+        for (; u + 3 * NW < nu; u += 4 * NW) {
+            double t[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) t[j] = a.Xg[(size_t)ur[u + j * NW] * a.ld + c0];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tile_x[(u + j * NW) * kWave + lane] = t[j];
+        }
+        for (; u < nu; u += NW) tile_x[u * kWave + lane] = a.Xg[(size_t)ur[u] * a.ld + c0];
+    }
+    __syncthreads();
+    const LdsSrc src{tile_x, lane};
+    const int I = first + wave;
+    if (I < last) {
+        if (atom_off[I + 1] - atom_off[I] == 4) {
+            double acc[4][1];
+            row_product<4, 1>(I, brow, bsplit, bloc, voff, vals, src, acc);
+            const int r0 = atom_off[I];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) epilogue<KIND, 4, 1>(a, r0 + q, c0, acc, q, cs, d0, d1);
+        } else {
+            double acc[1][1];
+            row_product<1, 1>(I, brow, bsplit, bloc, voff, vals, src, acc);
+            epilogue<KIND, 1, 1>(a, atom_off[I], c0, acc, 0, cs, d0, d1);
+        }
+    }
+    // reuse the staged tile as the reduction buffer
+    store_partials<KIND, 1, NW>(a, g, c0, wave, lane, d0, d1, tile_x);
+}
+
+// Grouped variant: a row group's R rows share every gathered right-hand-side
+// row of the union of their coupled atoms; the dense R x n_J value blocks are
+// read through the scalar unit.  KS waves split the union of one group (wave
+// `sub` takes every KS-th union atom), so each wave's chain of dependent
+// gathers is KS times shorter; the partial rows are summed through LDS.
+constexpr int kMaxGroupRows = 4 + kGroupH;
+
+template <int R, int CPL, int KS>
+__device__ __forceinline__ void group_partial(int u0, int u4, int u1, int sub, const int* __restrict__ uorb,
+                                              const double* __restrict__ v, const GlobalSrc<CPL>& src, double* pw,
+                                              int lane) {
+    double acc[R][CPL];
+    block_product<R, CPL, KS>(u0, u4, u1, sub, uorb, v, src, acc);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) pw[(r * kWave + lane) * CPL + c] = acc[r][c];
+}
+
+template <int KIND, int CPL, int KS>
+__global__ __launch_bounds__(kBlock) void pass_group_kernel(PassArgs a, const int* __restrict__ gR,
+                                                            const int* __restrict__ groff,
+                                                            const int* __restrict__ grows,
+                                                            const int* __restrict__ guoff,
+                                                            const int* __restrict__ gu4,
+                                                            const int* __restrict__ guorb,
+                                                            const int64_t* __restrict__ gvoff,
+                                                            const double* __restrict__ vals) {
+    constexpr int GPW = kWavesPerBlock / KS;  // groups per workgroup
+    __shared__ double part[kWavesPerBlock * kMaxGroupRows * kWave * CPL];
+    int tile, slab;
+    xcd_place(a.n_slabs, a.n_tiles, a.place, tile, slab);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sub = wave % KS, gi = wave / KS;
+    const int c0 = tile * (kWave * CPL) + lane * CPL;
+    ColState cs[CPL];
+    load_colstate<KIND, CPL>(a, c0, cs);
+    double d0[CPL], d1[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) d0[c] = d1[c] = 0.0;
+    const GlobalSrc<CPL> src{a.Xg, a.ld, c0};
+    const int g = slab * GPW + gi;
+    const bool live = g < a.n_grp;
+    int R = 0;
+    double* pw = part + (size_t)wave * kMaxGroupRows * kWave * CPL;
+    if (live) {
+        R = gR[g];
+        const int u0 = guoff[g], u4 = gu4[g], u1 = guoff[g + 1];
+        const double* __restrict__ v = vals + gvoff[g];
+        switch (R) {
+            case 1: group_partial<1, CPL, KS>(u0, u4, u1, sub, guorb, v, src, pw, lane); break;
+            case 4: group_partial<4, CPL, KS>(u0, u4, u1, sub, guorb, v, src, pw, lane); break;
+            case 5: group_partial<5, CPL, KS>(u0, u4, u1, sub, guorb, v, src, pw, lane); break;
+            case 6: group_partial<6, CPL, KS>(u0, u4, u1, sub, guorb, v, src, pw, lane); break;
+            case 7: group_partial<7, CPL, KS>(u0, u4, u1, sub, guorb, v, src, pw, lane); break;
+            default: group_partial<8, CPL, KS>(u0, u4, u1, sub, guorb, v, src, pw, lane); break;
+        }
+    }
+    __syncthreads();
+    if (live) {
+        // wave `sub` of the group finishes rows sub, sub + KS, ...
+        const int* __restrict__ rows = grows + groff[g];
+        const double* pg = part + (size_t)(gi * KS) * kMaxGroupRows * kWave * CPL;
+        for (int r = sub; r < R; r += KS) {
+            double acc[1][CPL];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int s = 0; s < KS; ++s) t += pg[((size_t)s * kMaxGroupRows * kWave + r * kWave + lane) * CPL + c];
+                acc[0][c] = t;
+            }
+            epilogue<KIND, 1, CPL>(a, rows[r], c0, acc, 0, cs, d0, d1);
+        }
+    }
+    store_partials<KIND, CPL, kWavesPerBlock>(a, slab, c0, wave, lane, d0, d1, part);
+}
+
+template <int KIND, int KS>
+static void launch_group(const PassArgs& a, int cpl, int nwg, hipStream_t st) {
+    if (cpl == 2)
+        hipLaunchKernelGGL((pass_group_kernel<KIND, 2, KS>), dim3(nwg), dim3(kBlock), 0, st, a, a.g_R, a.g_roff,
+                           a.g_rows, a.g_uoff, a.g_u4, a.g_uorb, a.g_voff, a.vals);
+    else
+        hipLaunchKernelGGL((pass_group_kernel<KIND, 1, KS>), dim3(nwg), dim3(kBlock), 0, st, a, a.g_R, a.g_roff,
+                           a.g_rows, a.g_uoff, a.g_u4, a.g_uorb, a.g_voff, a.vals);
+}
+
 template <int KIND>
 static void launch_kind(const PassArgs& a, int cpl, hipStream_t st) {
     const int nwg = a.n_slabs * a.n_tiles;
-    if (cpl == 2)
+    if (a.staged == 9) {
+        if (a.group_split == 4)
+            launch_group<KIND, 4>(a, cpl, nwg, st);
+        else if (a.group_split == 2)
+            launch_group<KIND, 2>(a, cpl, nwg, st);
+        else
+            launch_group<KIND, 1>(a, cpl, nwg, st);
+    } else if (a.staged == 1) {
+        hipLaunchKernelGGL((pass_lds_kernel<KIND, kStageWaves[0], kStageRows[0]>), dim3(nwg),
+                           dim3(kStageWaves[0] * kWave), 0, st, a, a.brow, a.bsplit, a.bloc, a.voff, a.vals,
+                           a.atom_off);
+    } else if (a.staged == 2) {
+        hipLaunchKernelGGL((pass_lds_kernel<KIND, kStageWaves[1], kStageRows[1]>), dim3(nwg),
+                           dim3(kStageWaves[1] * kWave), 0, st, a, a.brow, a.bsplit, a.bloc, a.voff, a.vals,
+                           a.atom_off);
+    } else if (cpl == 2) {
         hipLaunchKernelGGL((pass_kernel<KIND, 2>), dim3(nwg), dim3(kBlock), 0, st, a, a.brow, a.bsplit, a.borb,
                            a.voff, a.vals, a.atom_off);
-    else
+    } else {
         hipLaunchKernelGGL((pass_kernel<KIND, 1>), dim3(nwg), dim3(kBlock), 0, st, a, a.brow, a.bsplit, a.borb,
                            a.voff, a.vals, a.atom_off);
+    }
 }
 
 void launch_pass(PassKind kind, const PassArgs& a, hipStream_t st) {
-    const int cpl = a.ld / (a.n_tiles * kWave);
+    const int cpl = (a.staged == 1 || a.staged == 2) ? 1 : a.ld / (a.n_tiles * kWave);
     switch (kind) {
         case PASS_LANCZOS_A: launch_kind<PASS_LANCZOS_A>(a, cpl, st); break;
-        case PASS_CHEB: launch_kind<PASS_CHEB>(a, cpl, st); break;
-        case PASS_CHEB_LAST: launch_kind<PASS_CHEB_LAST>(a, cpl, st); break;
+        case PASS_STEP: launch_kind<PASS_STEP>(a, cpl, st); break;
+        case PASS_STEP_LAST: launch_kind<PASS_STEP_LAST>(a, cpl, st); break;
         case PASS_PLAIN: launch_kind<PASS_PLAIN>(a, cpl, st); break;
     }
+}
+
+// out[c] = sum_k part[k*ld + c] in two deterministic stages:
+// stage 1 sums blocks of 64 partials per column, stage 2 the block sums.
+__global__ void col_reduce1_kernel(const double* __restrict__ part, int n_part, int ld, double* __restrict__ tmp) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ld) return;
+    const int k0 = blockIdx.y * 64, k1 = min(k0 + 64, n_part);
+    double s = 0.0;
+    for (int k = k0; k < k1; ++k) s += part[(size_t)k * ld + c];
+    tmp[(size_t)blockIdx.y * ld + c] = s;
+}
+
+__global__ void col_reduce2_kernel(const double* __restrict__ tmp, int nb, int ld, const int* __restrict__ slot_n,
+                                   const int* __restrict__ slot_row, double* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ld) return;
+    double s = 0.0;
+    for (int k = 0; k < nb; ++k) s += tmp[(size_t)k * ld + c];
+    if (slot_n) s = (slot_n[c] == 0 || slot_row[c] < 0) ? 0.0 : s;
+    out[c] = s;
+}
+
+void launch_col_reduce(const double* part, int n_part, int ld, double* tmp, const int* slot_n, const int* slot_row,
+                       double* out, hipStream_t st) {
+    const int nb = (n_part + 63) / 64;
+    hipLaunchKernelGGL(col_reduce1_kernel, dim3((ld + 255) / 256, nb), dim3(256), 0, st, part, n_part, ld, tmp);
+    hipLaunchKernelGGL(col_reduce2_kernel, dim3((ld + 255) / 256), dim3(256), 0, st, tmp, nb, ld, slot_n, slot_row,
+                       out);
 }
 
 }  // namespace elses

@@ -20,22 +20,6 @@
 
 namespace elses {
 
-__global__ void alpha_reduce_kernel(const double* __restrict__ part, int n_slabs, int ld,
-                                    const int* __restrict__ slot_n, const int* __restrict__ slot_row,
-                                    double* __restrict__ alpha) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ld) return;
-    double s = 0.0;
-    for (int k = 0; k < n_slabs; ++k) s += part[(size_t)k * ld + c];
-    alpha[c] = (slot_n[c] == 0 || slot_row[c] < 0) ? 0.0 : s;
-}
-
-void launch_alpha_reduce(const double* part, int n_slabs, int ld, const int* slot_n, const int* slot_row,
-                         double* alpha, hipStream_t st) {
-    hipLaunchKernelGGL(alpha_reduce_kernel, dim3((ld + 255) / 256), dim3(256), 0, st, part, n_slabs, ld, slot_n,
-                       slot_row, alpha);
-}
-
 __device__ __forceinline__ double block_sum(double v, double* sh) {
     // wave64 reduction with cross-lane shuffles, then across waves via LDS
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -79,13 +63,7 @@ __global__ __launch_bounds__(kShiftThreads) void shift_update_kernel(ShiftArgs a
     __shared__ cd s_zeta[256];
     __shared__ int s_act[256];
 
-    double vs = 0.0, ss = 0.0;
-    for (int k = t; k < a.n_slabs; k += kShiftThreads) {
-        vs += a.part0[(size_t)k * a.ld + slot];
-        ss += a.part1[(size_t)k * a.ld + slot];
-    }
-    vs = block_sum(vs, sh_red);
-    ss = block_sum(ss, sh_red);
+    const double vs = a.vs[slot], ss = a.ss[slot];
 
     if (n == 0) {
         // start vector c = B^{-1} e_j: beta_0 = sqrt(e_j^T B^{-1} e_j)

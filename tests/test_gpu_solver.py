@@ -51,14 +51,16 @@ def test_b_interval_brackets_spectrum(c1):
     assert lo > 0.9 * lam[0] and hi < 1.1 * lam[-1]
 
 
-@pytest.mark.parametrize("nvec", [1, 3, 64, 128, 192])
-def test_spmm_matches_oracle_csr(el, ctx, c1, nvec):
+@pytest.mark.parametrize("nvec,variant", [(1, "auto"), (3, "auto"), (64, "direct"), (128, "direct"),
+                                          (64, "staged8"), (192, "staged4"), (64, "grouped"), (128, "grouped"),
+                                          (320, "grouped"), (128, "grouped2"), (64, "grouped1")])
+def test_spmm_matches_oracle_csr(el, ctx, c1, nvec, variant):
     s, A, B, mat = c1
     rng = np.random.default_rng(nvec)
     X = rng.standard_normal((A.n, nvec))
     Xd = torch.from_numpy(X).cuda()
     for which, C in (("A", A), ("B", B)):
-        Y = el.spmm(ctx, mat, which, Xd).cpu().numpy().reshape(A.n, nvec)
+        Y = el.spmm(ctx, mat, which, Xd, variant).cpu().numpy().reshape(A.n, nvec)
         ref = np.stack([C.matvec(X[:, v]) for v in range(nvec)], axis=1)
         assert np.abs(Y - ref).max() <= 1e-14 * np.abs(ref).max()
 
@@ -256,6 +258,8 @@ def test_slot_counts_agree(el, ctx, c1):
     s, A, B, mat = c1
     z = synth.shift_grid(8)
     cols = np.arange(0, A.n, 2, dtype=np.int32)  # 129 columns
-    outs = [el.shifted_solve(ctx, mat, cols, z, tol=1e-10, slots=sl)["x"].cpu().numpy() for sl in (64, 128, 256)]
+    outs = [el.shifted_solve(ctx, mat, cols, z, tol=1e-10, slots=sl, variant=v)["x"].cpu().numpy()
+            for sl, v in ((64, "staged8"), (128, "direct"), (256, "staged4"), (256, "direct"), (192, "grouped"),
+                          (128, "grouped2"), (128, "grouped1"))]
     for o in outs[1:]:
         assert np.abs(o - outs[0]).max() <= 1e-8 * np.abs(outs[0]).max()
