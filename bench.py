@@ -1,25 +1,38 @@
 """Throughput of the generalized shifted Krylov solver on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--config c2] [--cols N]
+    python bench.py [--steps K] [--warmup W] [--config c2] [--batch 1024]
 
-One step = one elses_density_matrix call over the whole workload: for every
-column j and every shift z_k it solves (z_k B - A) x = e_j to a relative
-residual of 1e-8 (Lanczos outer process, Chebyshev overlap solves, fused
-multi-shift update, slot refill) and assembles the density-matrix elements
-rho_ij = sum_k Im(c_k x_{j,k,i}) on the pattern plus the traces Tr[rho B] and
-Tr[rho A].  Inputs are resident in HBM before the timed region.
+Workload (default c2): every column j of the 4096-atom box (M = 8191) and 64
+shifts z_k.  The columns are processed in batches of `--batch` consecutive
+columns; one step = one elses_density_matrix call over one batch: for every
+column of the batch and every shift it solves (z_k B - A) x = e_j to a
+relative residual of 1e-8 (Lanczos outer process, Richardson overlap solves,
+fused multi-shift update, slot refill) and assembles the density-matrix
+elements rho_ij = sum_k Im(c_k x_{j,k,i}) on the pattern plus the traces
+Tr[rho B] and Tr[rho A].  Step s takes batch s mod n_batches, so
+--steps n_batches (8 for c2) covers the whole job once.  Inputs are resident
+in HBM before the timed region; a short untimed solve loads the kernels first.
 
 Prints one JSON line with the metric (column x shift solves per second), the
-roofline of the dominant kernel (the Chebyshev overlap pass, HBM-bound;
-achieved algorithmic bytes per launch / mean launch time measured with HIP
-events on the solver's stream) and the CPU oracle timed on a bounded sample
-on the host's cores.
+roofline of the dominant kernel (the Richardson step of the overlap solve:
+the grouped B pass, HBM-bound; algorithmic bytes per launch / mean launch time
+measured with HIP events on the solver's stream), the HBM traffic of that
+kernel from the committed rocprofv3 counter summary when it was taken on the
+current kernel source, and the CPU oracle timed on a bounded sample on the
+host's cores.
+
+    python bench.py --copy-calib 1073741824
+
+runs only a plain device copy of the given size (the calibration of the HBM
+byte counters).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -31,6 +44,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "column×shift solves/sec at 1e-8 rel. residual; SpMV HBM GB/s vs peak"
+
+PASS_SOURCE = os.path.join(ROOT, "paper_1609_08377_amd", "csrc", "passes.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pass_group_step_c2_traffic.md")
 
 WORKLOADS = {
     # name: (n_atoms, n_shifts, description)
@@ -69,14 +85,50 @@ def cpu_baseline(sysm, shifts, gpu_iters_mean: float, budget_s: float = 20.0):
     return {"value": value, "unit": "column-shift solves/s", "cores": nthreads, "kind": "oracle", "sample": sample}
 
 
+def source_digest() -> str:
+    with open(PASS_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def committed_traffic(kernel_tag: str):
+    """HBM bytes per launch of the timed kernel from the committed counter summary.
+
+    The summary holds lines `traffic <tag> <source digest> <bytes per launch>`;
+    the figure counts only if it was taken on the current pass source."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    digest = source_digest()
+    with open(TRAFFIC_SUMMARY) as f:
+        for line in f:
+            m = re.match(r"^traffic\s+(\S+)\s+(\S+)\s+([0-9.eE+]+)\s*$", line.strip().strip("`"))
+            if m and m.group(1) == kernel_tag and m.group(2) == digest:
+                return float(m.group(3))
+    return None
+
+
+def copy_calibration(nbytes: int):
+    import torch
+    n = nbytes // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
+                      "launches": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--batch", type=int, default=1024, help="columns per step")
     ap.add_argument("--cols", type=int, default=0, help="limit the column count (0 = all)")
     ap.add_argument("--slots", type=int, default=0)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--copy-calib", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--variant", default="auto", choices=["auto", "direct", "staged8", "staged4", "grouped", "grouped2", "grouped1"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-outer", type=int, default=20000,
@@ -84,9 +136,13 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
-                                   "but not built", "n_gpus": args.gpus}), flush=True)
+        print(json.dumps({"error": "this solver runs on one GPU: sharding the columns over several GPUs "
+                                   "is not implemented", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+
+    if args.copy_calib:
+        copy_calibration(args.copy_calib)
+        return
 
     import torch
 
@@ -98,31 +154,42 @@ def main():
     sysm = synth.make_system(n_atoms, seed)
     z = synth.shift_grid(K)
     cw = (-(1.0 / np.pi) * (2.0 / K) * 0.5 * (1.0 - np.tanh(0.5 * (z.real - 0.0) / 0.01))).astype(np.complex128)
-    cols = np.arange(sysm.M, dtype=np.int32)
+    all_cols = np.arange(sysm.M, dtype=np.int32)
     if args.cols:
-        cols = cols[:args.cols]
+        all_cols = all_cols[:args.cols]
+    batches = [all_cols[i:i + args.batch] for i in range(0, len(all_cols), args.batch)]
+    mixed = args.precision == "mixed"
 
     ctx = el.Context(0)
-    mat = el.Matrix.from_system(ctx, sysm)
+    mat = el.Matrix.from_system(ctx, sysm, precision=args.precision)
     lib = el.lib()
     import ctypes
     lib.elses_ctx_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     lib.elses_ctx_pass_stats.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 6
 
-    def step():
-        return el.density_matrix(ctx, mat, cols, z, cw, slots=args.slots, want_x=True, max_outer=args.max_outer,
-                                 allow_not_converged=args.max_outer < 20000, variant=args.variant)
+    def step(cols, max_outer=args.max_outer):
+        return el.density_matrix(ctx, mat, cols, z, cw, slots=args.slots, want_x=True, max_outer=max_outer,
+                                 allow_not_converged=max_outer < 20000, variant=args.variant, mixed=mixed)
 
+    # load the kernels and touch the allocator outside the timed region
+    step(batches[0][:64], max_outer=16)
     for w in range(args.warmup):
         print(f"warmup {w + 1}/{args.warmup}", file=sys.stderr, flush=True)
-        step()
+        step(batches[w % len(batches)])
     lib.elses_ctx_set_profiling(ctx._h, 16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = None
+    n_solves = 0
+    iters_all, resid_max, trace_b = [], 0.0, 0.0
     for s in range(args.steps):
-        out = step()
-        print(f"step {s + 1}/{args.steps} done", file=sys.stderr, flush=True)
+        cols = batches[s % len(batches)]
+        out = step(cols)
+        n_solves += len(cols) * K
+        print(f"step {s + 1}/{args.steps} done ({len(cols)} columns)", file=sys.stderr, flush=True)
+        iters_all.append(out["iters"])
+        resid_max = max(resid_max, float(out["resid"].max()))
+        trace_b += float(out["traces"][0])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     launches = ctypes.c_int64()
@@ -134,28 +201,34 @@ def main():
     lib.elses_ctx_pass_stats(ctx._h, ctypes.byref(launches), ctypes.byref(avg_us), ctypes.byref(nbytes),
                              ctypes.byref(flops), ctypes.byref(total), ctypes.byref(slots))
     ms_per_step = 1000.0 * dt / args.steps
-    n_solves = len(cols) * K
-    value = n_solves * args.steps / dt
-    iters = out["iters"].cpu().numpy()
-    resid = out["resid"].cpu().numpy()
+    value = n_solves / dt
+    iters = torch.cat(iters_all).cpu().numpy()
     achieved = nbytes.value / (avg_us.value * 1e-6) / 1e9 if avg_us.value > 0 else 0.0
+    tag = ("step32" if mixed else "step64") + f"_{args.config}_{slots.value}"
+    traffic = committed_traffic(tag) if args.variant == "auto" else None
+    kernel = ("pass_group_kernel<PASS_STEP32> (FP32 B SpMM + Richardson step)" if mixed else
+              "pass_group_kernel<PASS_STEP> (FP64 B SpMM + Richardson step)")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "pass_kernel<PASS_CHEB> (B SpMM + Chebyshev update)",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": kernel, "traffic_tag": tag,
             "bytes_per_launch": nbytes.value, "avg_launch_us": round(avg_us.value, 2),
             "timed_launches": launches.value}
     res = {
         "metric": METRIC, "value": round(value, 2), "unit": "column-shift solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 1),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": args.config + ": " + desc, "n_atoms": n_atoms, "M": int(sysm.M),
-                   "columns": int(len(cols)), "shifts": K, "tol": 1e-8, "slots": slots.value,
-                   "outer_iters_mean": float(iters.mean()), "outer_iters_max": int(iters.max()),
-                   "max_resid_estimate": float(resid.max()), "trace_rhoB": float(out["traces"][0]),
-                   "gflops_cheb_pass": round(flops.value / (avg_us.value * 1e-6) / 1e9, 1) if avg_us.value else 0},
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32/f64 mixed" if mixed else "f64", "data": "synthetic",
+        "config": {"workload": args.config + ": " + desc + (" [mixed precision: FP32-stored A, B]" if mixed else ""),
+                   "n_atoms": n_atoms, "M": int(sysm.M), "columns_per_step": args.batch,
+                   "batches_in_job": len(batches), "columns_timed": int(n_solves // K), "shifts": K, "tol": 1e-8,
+                   "slots": slots.value, "outer_iters_mean": float(iters.mean()),
+                   "outer_iters_max": int(iters.max()), "max_resid_estimate": resid_max,
+                   "trace_rhoB_timed_columns": trace_b, "passes_per_step": int(total.value // max(args.steps, 1)),
+                   "gflops_timed_pass": round(flops.value / (avg_us.value * 1e-6) / 1e9, 1) if avg_us.value else 0},
         "roofline": roof,
     }
     if not args.no_cpu:
+        print("timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(sysm, z, float(iters.mean()), args.cpu_budget)
     print(json.dumps(res), flush=True)
 

@@ -135,7 +135,8 @@ void elses_opts_default(elses_opts *o);
  * iters_out (DEVICE int32 [n_cols]) outer iterations, may be NULL.
  * resid_out (DEVICE double [n_cols*K]) residual per (j,k): the recursive
  *   estimate, or with opts->audit the recomputed FP64 true residual; may be
- *   NULL.
+ *   NULL.  Mixed solves (use_mixed) solve the pencil of the FP32-rounded A
+ *   and B: their audit recomputes the residual of that pencil in FP64.
  * Returns ELSES_WARN_NOT_CONVERGED if some (j,k) ended above tol (outputs
  * are still written).
  */
@@ -162,14 +163,17 @@ elses_status elses_density_matrix(elses_ctx ctx, elses_mat mat, int32_t n_cols, 
 
 /*
  * Kernel timing of the overlap-solve pass (diagnostics for roofline reports).
- * When enabled, solves time every `stride`-th Chebyshev pass with a pair of
- * HIP events on the context stream (stride >= 1; 0 disables).  The counters
- * accumulate over calls until reset.
+ * When enabled, solves time the back-to-back Richardson steps 2 .. d-2 of
+ * the overlap solve (FP32 in mixed solves) every `stride`-th outer
+ * iteration with one pair of HIP events on the context stream (stride >= 1;
+ * 0 disables).  The counters accumulate over calls until reset by a new
+ * stride.
  *   launches       passes timed
  *   avg_us         mean duration of a timed pass (microseconds)
- *   bytes          algorithmic HBM bytes of one pass: B's values and index
- *                  arrays once, plus three [M][slots] FP64 blocks (the
- *                  gathered iterate, the right-hand side, the new iterate)
+ *   bytes          algorithmic HBM bytes of one pass: B's values (8 or 4
+ *                  bytes each) and index arrays once, plus three [M][slots]
+ *                  blocks (the gathered iterate, the right-hand side, the new
+ *                  iterate; 8 or 4 bytes per entry)
  *   flops          2 * nnz * slots + 3 * M * slots
  *   total_passes   all passes (A and B products) launched by solves
  */
@@ -182,7 +186,10 @@ elses_status elses_ctx_pass_stats(elses_ctx ctx, int64_t *launches, double *avg_
  * `slots` right-hand sides (a multiple of 64) with pass kernels `variant`
  * (as in elses_opts).  kind: 0 the A pass of a Lanczos step, 1 a
  * Richardson step of the overlap solve, 2 the last step with the Lanczos
- * correction, 3 the plain product.  *avg_us receives the mean launch time
+ * correction, 3 the plain product; mixed precision (matrix created with
+ * ELSES_MIXED): 4 the A pass, 5 an FP32 Richardson step, 6 the FP64
+ * residual refinement, 7 the last FP32 step with the Lanczos correction,
+ * 8 the plain FP32 product.  *avg_us receives the mean launch time
  * measured with HIP events on the context stream.  Used by the slot and
  * variant autotuner and by performance diagnostics.
  */
@@ -196,6 +203,14 @@ elses_status elses_time_pass(elses_ctx ctx, elses_mat mat, int32_t kind, int32_t
  * one-thread-per-entry kernel. */
 elses_status elses_spmm(elses_ctx ctx, elses_mat mat, int which, int32_t variant, int32_t nvec, const double *x,
                         double *y);
+
+/* FP32 products with the FP32 copies of a matrix created with ELSES_MIXED:
+ * y = fl32(X) x with FP32 accumulation, X = A (which=0) or B (which=1);
+ * x, y DEVICE float [M][nvec], nvec a positive multiple of 64; `variant` as
+ * in elses_opts (the LDS-staged variants have no FP32 form).  These are the
+ * products of the mixed-precision overlap solve (diagnostics and tests). */
+elses_status elses_spmm32(elses_ctx ctx, elses_mat mat, int which, int32_t variant, int32_t nvec, const float *x,
+                          float *y);
 
 /* Library version string. */
 const char *elses_version(void);

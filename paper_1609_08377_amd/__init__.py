@@ -94,6 +94,8 @@ def lib():
         L.elses_density_matrix.restype = ctypes.c_int
         L.elses_spmm.argtypes = [P, P, ctypes.c_int, I32, I32, P, P]
         L.elses_spmm.restype = ctypes.c_int
+        L.elses_spmm32.argtypes = [P, P, ctypes.c_int, I32, I32, P, P]
+        L.elses_spmm32.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -214,6 +216,11 @@ VARIANTS = {"auto": 0, "direct": 1, "staged": 2, "staged8": 2, "staged4": 3, "gr
             "grouped2": 5, "grouped1": 6}
 
 
+def _variant(v) -> int:
+    """A variant name, or an int holding the variant and its placement / column bits."""
+    return VARIANTS[v] if isinstance(v, str) else int(v)
+
+
 def make_opts(tol=1e-8, max_outer=20000, inner_tol=1e-13, full=False, slots=0, mixed=False, audit=False,
               variant="auto") -> Opts:
     o = Opts()
@@ -225,7 +232,7 @@ def make_opts(tol=1e-8, max_outer=20000, inner_tol=1e-13, full=False, slots=0, m
     o.slots = slots
     o.use_mixed = 1 if mixed else 0
     o.audit = 1 if audit else 0
-    o.variant = VARIANTS[variant]
+    o.variant = _variant(variant)
     return o
 
 
@@ -299,7 +306,20 @@ def spmm(ctx: Context, mat: Matrix, which: str, x, variant: str = "auto"):
     x = x.contiguous()
     y = torch.empty_like(x)
     nvec = 1 if x.dim() == 1 else x.shape[1]
-    st = lib().elses_spmm(ctx._h, mat._h, {"A": 0, "B": 1}[which], VARIANTS[variant], nvec, _dev_ptr(x),
+    st = lib().elses_spmm(ctx._h, mat._h, {"A": 0, "B": 1}[which], _variant(variant), nvec, _dev_ptr(x),
                           _dev_ptr(y))
+    ctx.check(st)
+    return y
+
+
+def spmm32(ctx: Context, mat: Matrix, which: str, x, variant: str = "auto"):
+    """y = fl32(A) x or fl32(B) x in FP32 for x a float32 device tensor (M, nvec), nvec % 64 == 0."""
+    torch = _torch()
+    if x.dtype != torch.float32 or x.dim() != 2:
+        raise ValueError("x must be a float32 (M, nvec) tensor")
+    x = x.contiguous()
+    y = torch.empty_like(x)
+    st = lib().elses_spmm32(ctx._h, mat._h, {"A": 0, "B": 1}[which], _variant(variant), x.shape[1], _dev_ptr(x),
+                            _dev_ptr(y))
     ctx.check(st)
     return y

@@ -374,7 +374,7 @@ void elses_mat_destroy(elses_mat m) {
     }
     {
         auto& D = d.grp;
-        void* q[] = {D.R, D.roff, D.rows, D.uoff, D.u4, D.uorb, D.voff, D.A, D.B};
+        void* q[] = {D.R, D.roff, D.rows, D.uoff, D.u4, D.uorb, D.voff, D.A, D.B, D.A32, D.B32};
         for (void* p : q)
             if (p) (void)hipFree(p);
     }
@@ -554,6 +554,15 @@ elses_status elses_mat_create(elses_ctx ctx, const elses_system* sys, int precis
             HCHECK(hipMemcpy(D.voff, G.voff.data(), sizeof(int64_t) * G.voff.size(), hipMemcpyHostToDevice));
             HCHECK(hipMemcpy(D.A, G.A.data(), sizeof(double) * G.A.size(), hipMemcpyHostToDevice));
             HCHECK(hipMemcpy(D.B, G.B.data(), sizeof(double) * G.B.size(), hipMemcpyHostToDevice));
+            if (precision == ELSES_MIXED) {
+                std::vector<float> t(G.A.size());
+                D.A32 = dalloc<float>(G.A.size());
+                D.B32 = dalloc<float>(G.B.size());
+                for (size_t i = 0; i < t.size(); ++i) t[i] = (float)G.A[i];
+                HCHECK(hipMemcpy(D.A32, t.data(), sizeof(float) * t.size(), hipMemcpyHostToDevice));
+                for (size_t i = 0; i < t.size(); ++i) t[i] = (float)G.B[i];
+                HCHECK(hipMemcpy(D.B32, t.data(), sizeof(float) * t.size(), hipMemcpyHostToDevice));
+            }
         }
         for (int sh = 0; sh < kStageShapes; ++sh) {
             std::vector<int> cl_atom, cl_uoff, cl_urow, bloc;
@@ -694,10 +703,12 @@ namespace {
 // multiple of 64).  Returns an error message or null.
 const char* configure_pass(const DevMatrix& d, int variant_in, int ld, PassArgs& pa) {
     if (ld <= 0 || ld % 64 != 0) return "column block must be a multiple of 64";
-    // bits 4-5 select the workgroup placement, bit 6 forces one column per lane
+    // bits 4-5 select the workgroup placement, bit 6 forces one column per
+    // lane, bit 7 limits the FP32 passes to two columns per lane
     const int variant = variant_in & 15;
     pa.place = (variant_in >> 4) & 3;
     const bool force_cpl1 = (variant_in >> 6) & 1;
+    const bool cap32 = (variant_in >> 7) & 1;
     int mode, split = 4;
     if (variant == 0) {
         // measured best on MI355X for the hydrocarbon pencils: row groups split
@@ -730,8 +741,11 @@ const char* configure_pass(const DevMatrix& d, int variant_in, int ld, PassArgs&
     const bool cluster = (mode == 1 || mode == 2);
     const int cpl = (cluster || force_cpl1) ? 1 : ((ld % 128 == 0) ? 2 : 1);
     pa.n_tiles = ld / (64 * cpl);
+    const int cpl32 = (cluster || force_cpl1) ? 1 : ((ld % 256 == 0 && !cap32) ? 4 : ((ld % 128 == 0) ? 2 : 1));
+    pa.n_tiles32 = ld / (64 * cpl32);
     // the column split needs the tile count to be a multiple of 8 or to divide 8
-    if (pa.place == 3 && pa.n_tiles % 8 != 0 && 8 % pa.n_tiles != 0) pa.place = 1;
+    auto splits = [](int t) { return t % 8 == 0 || 8 % t == 0; };
+    if (pa.place == 3 && (!splits(pa.n_tiles) || !splits(pa.n_tiles32))) pa.place = 1;
     if (cluster) {
         const auto& C = d.cl[mode - 1];
         pa.n_clusters = C.n;
@@ -801,7 +815,6 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         return set_err(ctx, ELSES_ERR_INVALID_ARG, "slots must be 0 or a multiple of 64 up to 65536");
     if (o.use_mixed && mat->precision != ELSES_MIXED)
         return set_err(ctx, ELSES_ERR_INVALID_ARG, "use_mixed needs a matrix created with ELSES_MIXED");
-    if (o.use_mixed) return set_err(ctx, ELSES_ERR_INVALID_ARG, "mixed precision solve not available yet");
     const bool full = (o.out_mode == ELSES_OUT_FULL);
     if (o.audit && (!full || !x_out || !resid_out))
         return set_err(ctx, ELSES_ERR_INVALID_ARG, "audit needs ELSES_OUT_FULL with x_out and resid_out");
@@ -825,10 +838,17 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
     const char* verr = configure_pass(d, o.variant, ld, pa);
     if (verr) return set_err(ctx, ELSES_ERR_INVALID_ARG, verr);
     const int n_groups = pa.n_slabs;
+    const bool mixed = o.use_mixed != 0;
+    if (mixed && (pa.staged == 1 || pa.staged == 2))
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "the LDS-staged passes have no mixed-precision form");
     const double* valsA = (pa.staged == 9) ? d.grp.A : d.A;
     const double* valsB = (pa.staged == 9) ? d.grp.B : d.B;
+    const float* valsA32 = (pa.staged == 9) ? d.grp.A32 : d.A32;
+    const float* valsB32 = (pa.staged == 9) ? d.grp.B32 : d.B32;
     const int rmax = full ? M : h.pmax;
-    const Rich rich = richardson_plan(mat->b_lo, mat->b_hi, o.inner_tol);
+    // FP64: one Richardson solve to inner_tol.  Mixed: two FP32 rounds (the
+    // solve, then the solve of the FP64 residual), each to sqrt(inner_tol).
+    const Rich rich = richardson_plan(mat->b_lo, mat->b_hi, mixed ? std::sqrt(o.inner_tol) : o.inner_tol);
 
     // host-side pattern offsets
     std::vector<int64_t> row_off(n_cols + 1, 0);
@@ -847,11 +867,18 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         HCHECK(hipSetDevice(ctx->device));
         DevPool pool;
         const size_t vsz = (size_t)M * ld;
-        double* buf[5];
+        double* buf[5] = {};
         for (int i = 0; i < 5; ++i) {
+            if (mixed && i == 1) continue;  // the mixed solve keeps its iterates in FP32
             buf[i] = pool.get<double>(vsz);
             HCHECK(hipMemsetAsync(buf[i], 0, vsz * sizeof(double), st));
         }
+        float* buf32[6] = {};
+        if (mixed)
+            for (int i = 0; i < 6; ++i) {
+                buf32[i] = pool.get<float>(vsz);
+                HCHECK(hipMemsetAsync(buf32[i], 0, vsz * sizeof(float), st));
+            }
         double* part0 = pool.get<double>((size_t)n_groups * ld);
         double* part1 = pool.get<double>((size_t)n_groups * ld);
         HCHECK(hipMemsetAsync(part0, 0, sizeof(double) * n_groups * ld, st));
@@ -953,9 +980,13 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         bool pending = false;
         int64_t it = 0;
         // sampled event timing of one Chebyshev pass per `prof_stride` outer iterations
+        // A sample spans the back-to-back Richardson steps k = 2 .. d-2 of one
+        // outer iteration (d - 3 launches of the same kernel), so the mean
+        // launch time excludes the event overhead.
         struct EvPair {
             hipEvent_t a = nullptr, b = nullptr;
             bool busy = false;
+            int n = 0;
         };
         std::vector<EvPair> prof(ctx->prof_stride > 0 ? 32 : 0);
         for (auto& p : prof) {
@@ -968,17 +999,107 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
                     float ms = 0.f;
                     HCHECK(hipEventElapsedTime(&ms, p.a, p.b));
                     ctx->prof_ms += ms;
-                    ctx->prof_launches += 1;
+                    ctx->prof_launches += p.n;
                     p.busy = false;
                 }
         };
         if (!prof.empty()) {
-            ctx->prof_bytes = (double)d.nnz * 8.0 + (double)d.nnzb * 4.0 + (double)d.n_atoms * 20.0 +
-                              3.0 * (double)M * ld * 8.0;
+            const double w = mixed ? 4.0 : 8.0;  // bytes per value and per vector entry of the timed pass
+            ctx->prof_bytes = (double)d.nnz * w + (double)d.nnzb * 4.0 + (double)d.n_atoms * 20.0 +
+                              3.0 * (double)M * ld * w;
             ctx->prof_flops = 2.0 * (double)d.nnz * ld + 3.0 * (double)M * ld;
             ctx->prof_slots = ld;
         }
-        for (;;) {
+        EvPair* open_sample = nullptr;
+        auto timed_pass = [&](PassKind kind, int k) {
+            const int first = 2, last = rich.d - 2;
+            if (k == first && last >= first && !prof.empty() && it % ctx->prof_stride == 0)
+                for (auto& p : prof)
+                    if (!p.busy) {
+                        open_sample = &p;
+                        HCHECK(hipEventRecord(p.a, st));
+                        break;
+                    }
+            launch_pass(kind, pa, st);
+            if (k == last && open_sample) {
+                HCHECK(hipEventRecord(open_sample->b, st));
+                open_sample->busy = true;
+                open_sample->n = last - first + 1;
+                open_sample = nullptr;
+            }
+        };
+        pa.vals32 = valsA32;
+        float* S32 = buf32[0];
+        float* Xa32 = buf32[1];
+        float* Xb32 = buf32[2];
+        float* R32 = buf32[3];
+        float* Da32 = buf32[4];
+        float* Db32 = buf32[5];
+        double* Vn = buf[2];
+        while (mixed) {
+            // w = A q_n (FP32 values, FP64 accumulation), s', alpha partials,
+            // FP32 copies of s' and x_1
+            pa.vals32 = valsA32;
+            pa.Xg = Vq;
+            pa.S = Tp;
+            pa.Vq = Vq;
+            pa.R32o = S32;
+            pa.Xio32 = Xa32;
+            launch_pass(PASS_LANCZOS_A_MX, pa, st);
+            launch_col_reduce(part0, n_groups, ld, red_tmp, slot_n, slot_row, alpha, st);
+            // round 1: FP32 Richardson solve of B x = s'
+            pa.vals32 = valsB32;
+            float* xcur = Xa32;
+            float* xoth = Xb32;
+            pa.R32 = S32;
+            for (int k = 1; k < rich.d; ++k) {
+                pa.Xg32 = xcur;
+                pa.Xio32 = xoth;
+                pa.tau = rich.tau[k - 1];
+                timed_pass(PASS_STEP32, k);
+                std::swap(xcur, xoth);
+            }
+            // FP64 residual r = s' - B x, first correction iterate
+            pa.Xg32 = xcur;
+            pa.R32o = R32;
+            pa.Xio32 = Da32;
+            launch_pass(PASS_REFINE, pa, st);
+            // round 2: FP32 solve of B d = r; the last step forms v = x + d
+            // and applies the deferred Lanczos correction
+            float* dcur = Da32;
+            float* doth = Db32;
+            pa.R32 = R32;
+            pa.Xr1 = xcur;
+            pa.Xio = Vn;
+            pa.Tn = Tn;
+            for (int k = 1; k < rich.d; ++k) {
+                pa.Xg32 = dcur;
+                pa.Xio32 = doth;
+                pa.tau = rich.tau[k - 1];
+                launch_pass(k == rich.d - 1 ? PASS_STEP32_LAST : PASS_STEP32, pa, st);
+                std::swap(dcur, doth);
+            }
+            launch_col_reduce(part0, n_groups, ld, red_tmp, nullptr, nullptr, vs, st);
+            launch_col_reduce(part1, n_groups, ld, red_tmp, nullptr, nullptr, ss, st);
+            sa.Vq = Vq;
+            launch_shift_update(sa, st);
+            HCHECK(hipGetLastError());
+            std::swap(Vq, Vn);
+            std::swap(Tp, Tn);
+            ++it;
+            if (it % poll == 0) {
+                if (pending) {
+                    HCHECK(hipEventSynchronize(ev));
+                    harvest();
+                    if (h_rem[0] == 0) break;
+                }
+                HCHECK(hipMemcpyAsync(h_rem, sa.remaining, sizeof(int), hipMemcpyDeviceToHost, st));
+                HCHECK(hipEventRecord(ev, st));
+                pending = true;
+            }
+            if (it > cap) throw HipFail{hipErrorUnknown, "solver loop did not terminate"};
+        }
+        while (!mixed) {
             // w = A q_n, s' = w - beta t_{n-1}, alpha partials, x_1
             pa.vals = valsA;
             pa.Xg = Vq;
@@ -996,19 +1117,7 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
                 pa.Xg = xcur;
                 pa.Xio = xoth;
                 pa.tau = rich.tau[k - 1];
-                EvPair* tp = nullptr;
-                if (!prof.empty() && k == 2 && k < rich.d - 1 && it % ctx->prof_stride == 0)
-                    for (auto& p : prof)
-                        if (!p.busy) {
-                            tp = &p;
-                            break;
-                        }
-                if (tp) HCHECK(hipEventRecord(tp->a, st));
-                launch_pass(k == rich.d - 1 ? PASS_STEP_LAST : PASS_STEP, pa, st);
-                if (tp) {
-                    HCHECK(hipEventRecord(tp->b, st));
-                    tp->busy = true;
-                }
+                timed_pass(k == rich.d - 1 ? PASS_STEP_LAST : PASS_STEP, k);
                 std::swap(xcur, xoth);
             }
             launch_col_reduce(part0, n_groups, ld, red_tmp, nullptr, nullptr, vs, st);
@@ -1036,7 +1145,7 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
             }
             if (it > cap) throw HipFail{hipErrorUnknown, "solver loop did not terminate"};
         }
-        if (o.audit) launch_true_residual(d, n_cols, d_cols, K, d_z, x_out, resid_out, st);
+        if (o.audit) launch_true_residual(d, mixed, n_cols, d_cols, K, d_z, x_out, resid_out, st);
         if (density) {
             launch_sum_pairs(ctr, n_cols, tr2, st);
             if (traces_out) HCHECK(hipMemcpyAsync(traces_out, tr2, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
@@ -1049,7 +1158,7 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
             (void)hipEventDestroy(p.a);
             (void)hipEventDestroy(p.b);
         }
-        ctx->total_passes += it * rich.d;
+        ctx->total_passes += it * (mixed ? 2 * rich.d : rich.d);
         n_notconv = h_rem[2];
         (void)hipEventDestroy(ev);
         (void)hipHostFree(h_rem);
@@ -1110,11 +1219,16 @@ elses_status elses_ctx_pass_stats(elses_ctx ctx, int64_t* launches, double* avg_
 elses_status elses_time_pass(elses_ctx ctx, elses_mat mat, int32_t kind, int32_t variant, int32_t slots,
                              int32_t reps, double* avg_us) {
     if (!ctx || !mat || !avg_us) return ELSES_ERR_INVALID_ARG;
-    if (kind < 0 || kind > 3 || reps < 1) return set_err(ctx, ELSES_ERR_INVALID_ARG, "bad kind or reps");
+    if (kind < 0 || kind >= kPassKinds || reps < 1) return set_err(ctx, ELSES_ERR_INVALID_ARG, "bad kind or reps");
+    const bool k32 = kind >= PASS_LANCZOS_A_MX;
+    if (k32 && mat->precision != ELSES_MIXED)
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "mixed-precision passes need a matrix created with ELSES_MIXED");
     const DevMatrix& d = mat->d;
     PassArgs pa{};
     const char* verr = configure_pass(d, variant, slots, pa);
     if (verr) return set_err(ctx, ELSES_ERR_INVALID_ARG, verr);
+    if (k32 && (pa.staged == 1 || pa.staged == 2))
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "the LDS-staged passes have no mixed-precision form");
     hipStream_t st = ctx->stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     try {
@@ -1126,6 +1240,11 @@ elses_status elses_time_pass(elses_ctx ctx, elses_mat mat, int32_t kind, int32_t
         double* V = pool.get<double>(vsz);
         double* T = pool.get<double>(vsz);
         for (double* p : {X, Y, S, V, T}) HCHECK(hipMemsetAsync(p, 0, vsz * sizeof(double), st));
+        float* F[4];
+        for (int i = 0; i < 4; ++i) {
+            F[i] = k32 ? pool.get<float>(vsz) : nullptr;
+            if (F[i]) HCHECK(hipMemsetAsync(F[i], 0, vsz * sizeof(float), st));
+        }
         double* part0 = pool.get<double>((size_t)pa.n_slabs * slots);
         double* part1 = pool.get<double>((size_t)pa.n_slabs * slots);
         double* sc = pool.get<double>((size_t)3 * slots);
@@ -1133,11 +1252,17 @@ elses_status elses_time_pass(elses_ctx ctx, elses_mat mat, int32_t kind, int32_t
         HCHECK(hipMemsetAsync(sc, 0, sizeof(double) * 3 * slots, st));
         HCHECK(hipMemsetAsync(si, 0, sizeof(int) * 2 * slots, st));
         pa.vals = (pa.staged == 9) ? d.grp.B : d.B;
+        pa.vals32 = (pa.staged == 9) ? d.grp.B32 : d.B32;
         pa.Xg = X;
         pa.Xio = Y;
         pa.S = S;
         pa.Vq = V;
         pa.Tn = T;
+        pa.Xg32 = F[0];
+        pa.Xio32 = F[1];
+        pa.R32 = F[2];
+        pa.R32o = F[2];
+        pa.Xr1 = F[3];
         pa.inv_beta = sc;
         pa.coefT = sc + slots;
         pa.alpha = sc + 2 * slots;
@@ -1166,6 +1291,29 @@ elses_status elses_time_pass(elses_ctx ctx, elses_mat mat, int32_t kind, int32_t
         if (e1) (void)hipEventDestroy(e1);
         return set_err(ctx, ELSES_ERR_HIP, std::string(f.what) + ": " + hipGetErrorString(f.e));
     }
+    return ELSES_OK;
+}
+
+elses_status elses_spmm32(elses_ctx ctx, elses_mat mat, int which, int32_t variant, int32_t nvec, const float* x,
+                          float* y) {
+    if (!ctx || !mat) return ELSES_ERR_INVALID_ARG;
+    if ((which != 0 && which != 1) || nvec < 64 || nvec % 64 != 0 || !x || !y)
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "bad arguments (nvec must be a positive multiple of 64)");
+    if (mat->precision != ELSES_MIXED)
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "FP32 products need a matrix created with ELSES_MIXED");
+    const DevMatrix& d = mat->d;
+    hipStream_t st = ctx->stream;
+    PassArgs pa{};
+    const char* verr = configure_pass(d, variant, nvec, pa);
+    if (verr) return set_err(ctx, ELSES_ERR_INVALID_ARG, verr);
+    if (pa.staged == 1 || pa.staged == 2)
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "the LDS-staged passes have no FP32 form");
+    pa.vals32 = (pa.staged == 9) ? (which == 0 ? d.grp.A32 : d.grp.B32) : (which == 0 ? d.A32 : d.B32);
+    pa.Xg32 = x;
+    pa.Xio32 = y;
+    launch_pass(PASS_PLAIN32, pa, st);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+        return set_err(ctx, ELSES_ERR_HIP, "spmm launch failed");
     return ELSES_OK;
 }
 

@@ -66,6 +66,7 @@ struct DevMatrix {
         int *uorb = nullptr;      // first orbital of each union atom
         int64_t *voff = nullptr;  // [n] value offset of the group's dense blocks
         double *A = nullptr, *B = nullptr;
+        float *A32 = nullptr, *B32 = nullptr;  // FP32 copies (mixed precision)
         int64_t nval = 0;
     } grp;
 };
@@ -111,7 +112,20 @@ namespace elses {
 // ---------------------------------------------------------------------------
 // Vector passes over the atom-block matrix (lanes = right-hand sides).
 // ---------------------------------------------------------------------------
-enum PassKind { PASS_LANCZOS_A = 0, PASS_STEP = 1, PASS_STEP_LAST = 2, PASS_PLAIN = 3 };
+enum PassKind {
+    PASS_LANCZOS_A = 0,
+    PASS_STEP = 1,
+    PASS_STEP_LAST = 2,
+    PASS_PLAIN = 3,
+    // mixed precision: FP32 matrix values; overlap solve in FP32 vectors with
+    // one FP64-accumulated residual refinement
+    PASS_LANCZOS_A_MX = 4,  // as PASS_LANCZOS_A with FP32 values; also writes FP32 s' and x_1
+    PASS_STEP32 = 5,        // FP32 Richardson step x_{k+1} = x_k + tau (r - B x_k)
+    PASS_REFINE = 6,        // r = s' - B x (FP64 accumulation); FP32 r and first correction iterate
+    PASS_STEP32_LAST = 7,   // last FP32 correction step, v = x + d, then the Lanczos correction
+    PASS_PLAIN32 = 8        // y = X x in FP32 (diagnostics)
+};
+constexpr int kPassKinds = 9;
 
 struct PassArgs {
     // matrix
@@ -121,6 +135,7 @@ struct PassArgs {
     const int *borb;
     const int64_t *voff;
     const double *vals;
+    const float *vals32;   // FP32 values of the same matrix (mixed kinds)
     int n_atoms;
     // layout: vectors are [M][ld] doubles, ld = slot count.  Direct passes:
     // slabs are groups of atoms_per_slab consecutive atoms (one per wave).
@@ -128,6 +143,7 @@ struct PassArgs {
     // multiple of 8; trailing groups may be empty.
     int ld;
     int n_slabs, atoms_per_slab, n_tiles;
+    int n_tiles32;  // column tiles of the passes over FP32 vectors
     int staged;  // 0: direct gathers; 1 + s: LDS-staged with cluster shape s; 9: row groups
     int n_clusters;
     const int *cl_atom, *cl_uoff, *cl_urow, *bloc;
@@ -141,6 +157,12 @@ struct PassArgs {
     double *S;          // LANCZOS_A: in t_{n-1} / out s'; STEP: in s; STEP_LAST: in s', out s
     const double *Vq;   // STEP_LAST / LANCZOS_A: q_n (unnormalised, own rows)
     const double *Tn;   // STEP_LAST: t_n (unnormalised, own rows)
+    // FP32 vectors of the mixed-precision overlap solve
+    const float *Xg32;  // gathered FP32 operand (STEP32*, REFINE, PLAIN32)
+    float *Xio32;       // FP32 output iterate
+    const float *R32;   // FP32 right-hand side (STEP32*)
+    float *R32o;        // LANCZOS_A_MX: FP32 s'; REFINE: FP32 residual
+    const float *Xr1;   // STEP32_LAST: first-round FP32 solution x
     // per-slot scalars
     const double *inv_beta;   // 1/beta_{n-1}
     const double *coefT;      // beta_{n-1}/beta_{n-2}
@@ -213,9 +235,10 @@ void launch_slot_init(const ShiftArgs &a, int n_active, hipStream_t st);
 // Generic products used by setup, audits and diagnostics: y = X x (nvec vectors, [M][ld]).
 void launch_spmm_generic(const DevMatrix &m, const double *vals, int nvec, int ld, const double *x, double *y,
                          hipStream_t st);
-// Complex true residual ||e_j - (z_k B - A) x_{c,k}||_2 for full-mode outputs.
-void launch_true_residual(const DevMatrix &m, int n_cols, const int *cols, int K, const double *z,
-                          const double *x_full, double *res_out, hipStream_t st);
+// Complex true residual ||e_j - (z_k B - A) x_{c,k}||_2 for full-mode outputs,
+// with the FP64 values or (fp32_values) the FP32 values of a mixed matrix.
+void launch_true_residual(const DevMatrix &m, bool fp32_values, int n_cols, const int *cols, int K,
+                          const double *z, const double *x_full, double *res_out, hipStream_t st);
 void launch_sum_pairs(const double *v, int n, double *out2, hipStream_t st);
 
 // Partial dot products (deterministic two-stage): out[b] = sum over block b

@@ -15,38 +15,135 @@
 //                   dots v.s and s.s (beta_n^2 and ||s||^2).
 //   PASS_PLAIN      y = X x.
 //
-// Matrix values are identical for all lanes of a wave, so they are read
-// through the scalar unit; each lane streams its own right-hand side.
+// Mixed precision (FP32 matrix values, FP32 overlap-solve vectors, FP64
+// Lanczos vectors and scalars):
+//   PASS_LANCZOS_A_MX  as PASS_LANCZOS_A with FP32 values and FP64
+//                      accumulation; also writes s' and x_1 in FP32.
+//   PASS_STEP32        FP32 Richardson step on FP32 vectors.
+//   PASS_REFINE        r = s' - B x with FP64 accumulation of the FP32
+//                      first-round solution x; writes r and the first
+//                      correction iterate g0 r in FP32.
+//   PASS_STEP32_LAST   last FP32 correction step d, then v = x + d in FP64
+//                      and the deferred Lanczos correction as above.
+//   PASS_PLAIN32       y = X x in FP32.
 //
-// Two gather strategies for the right-hand-side rows of the coupled atoms:
+// Matrix values are identical for all lanes of a wave, so they are read
+// through the scalar unit; each lane streams its own right-hand side(s).
+//
+// Three gather strategies for the right-hand-side rows of the coupled atoms:
 //   direct  one atom per wave, rows read through L1/L2 (pass_kernel);
 //   staged  a workgroup takes a cluster of consecutive atoms (one per wave),
 //           copies the union of their coupled rows for its 64-column tile into
 //           LDS once, and every wave reads its gathers from LDS
-//           (pass_lds_kernel).  Atoms numbered with spatial locality make the
-//           union small, so each row crosses L2 once per cluster instead of
-//           once per coupled atom.
+//           (pass_lds_kernel, FP64 kinds only);
+//   grouped a row group (a 4-orbital atom and the 1-orbital atoms it couples
+//           to most strongly) shares every gathered row of the union of its
+//           coupled atoms (pass_group_kernel).
+#include <type_traits>
+
 #include "internal.h"
 
 namespace elses {
 
-template <int CPL>
-__device__ __forceinline__ void load_cols(const double* p, size_t idx, double (&r)[CPL]) {
-    if constexpr (CPL == 2) {
+// Arithmetic types of each pass kind: TV matrix values, TX gathered vector,
+// TA accumulation.
+template <int KIND>
+struct KindTypes {
+    using TV = double;
+    using TX = double;
+    using TA = double;
+};
+template <>
+struct KindTypes<PASS_LANCZOS_A_MX> {
+    using TV = float;
+    using TX = double;
+    using TA = double;
+};
+template <>
+struct KindTypes<PASS_STEP32> {
+    using TV = float;
+    using TX = float;
+    using TA = float;
+};
+template <>
+struct KindTypes<PASS_REFINE> {
+    using TV = float;
+    using TX = float;
+    using TA = double;
+};
+template <>
+struct KindTypes<PASS_STEP32_LAST> {
+    using TV = float;
+    using TX = float;
+    using TA = float;
+};
+template <>
+struct KindTypes<PASS_PLAIN32> {
+    using TV = float;
+    using TX = float;
+    using TA = float;
+};
+
+template <int KIND>
+constexpr bool kVec32 = std::is_same_v<typename KindTypes<KIND>::TX, float>;
+// Column tiling: kinds over FP32 vectors use n_tiles32 (up to four columns
+// per lane), except the refinement pass, whose FP64 accumulators and LDS
+// partials make the FP64 tiling (up to two columns per lane) faster.
+template <int KIND>
+constexpr bool kTiles32 = kVec32<KIND> && KIND != PASS_REFINE;
+template <int KIND>
+constexpr bool kHasDots = KIND == PASS_LANCZOS_A || KIND == PASS_STEP_LAST || KIND == PASS_LANCZOS_A_MX ||
+                          KIND == PASS_STEP32_LAST;
+template <int KIND>
+constexpr bool kHasD1 = KIND == PASS_STEP_LAST || KIND == PASS_STEP32_LAST;
+
+__device__ __forceinline__ double fmac(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fmac(float a, float b, float c) { return fmaf(a, b, c); }
+
+// CPL consecutive columns of one row: 8- or 16-byte vector accesses.
+template <int CPL, typename T>
+__device__ __forceinline__ void load_cols(const T* p, size_t idx, T (&r)[CPL]) {
+    if constexpr (CPL == 1) {
+        r[0] = p[idx];
+    } else if constexpr (std::is_same_v<T, double> && CPL == 2) {
         const double2 t = *reinterpret_cast<const double2*>(p + idx);
         r[0] = t.x;
         r[1] = t.y;
+    } else if constexpr (std::is_same_v<T, double> && CPL == 4) {
+        const double2 t = *reinterpret_cast<const double2*>(p + idx);
+        const double2 u = *reinterpret_cast<const double2*>(p + idx + 2);
+        r[0] = t.x;
+        r[1] = t.y;
+        r[2] = u.x;
+        r[3] = u.y;
+    } else if constexpr (std::is_same_v<T, float> && CPL == 2) {
+        const float2 t = *reinterpret_cast<const float2*>(p + idx);
+        r[0] = t.x;
+        r[1] = t.y;
     } else {
-        r[0] = p[idx];
+        static_assert(std::is_same_v<T, float> && CPL == 4, "unsupported column group");
+        const float4 t = *reinterpret_cast<const float4*>(p + idx);
+        r[0] = t.x;
+        r[1] = t.y;
+        r[2] = t.z;
+        r[3] = t.w;
     }
 }
 
-template <int CPL>
-__device__ __forceinline__ void store_cols(double* p, size_t idx, const double (&r)[CPL]) {
-    if constexpr (CPL == 2) {
-        *reinterpret_cast<double2*>(p + idx) = make_double2(r[0], r[1]);
-    } else {
+template <int CPL, typename T>
+__device__ __forceinline__ void store_cols(T* p, size_t idx, const T (&r)[CPL]) {
+    if constexpr (CPL == 1) {
         p[idx] = r[0];
+    } else if constexpr (std::is_same_v<T, double> && CPL == 2) {
+        *reinterpret_cast<double2*>(p + idx) = make_double2(r[0], r[1]);
+    } else if constexpr (std::is_same_v<T, double> && CPL == 4) {
+        *reinterpret_cast<double2*>(p + idx) = make_double2(r[0], r[1]);
+        *reinterpret_cast<double2*>(p + idx + 2) = make_double2(r[2], r[3]);
+    } else if constexpr (std::is_same_v<T, float> && CPL == 2) {
+        *reinterpret_cast<float2*>(p + idx) = make_float2(r[0], r[1]);
+    } else {
+        static_assert(std::is_same_v<T, float> && CPL == 4, "unsupported column group");
+        *reinterpret_cast<float4*>(p + idx) = make_float4(r[0], r[1], r[2], r[3]);
     }
 }
 
@@ -60,18 +157,17 @@ __device__ __forceinline__ void store_cols(double* p, size_t idx, const double (
 // KS-th coupled atom starting at `sub`.  Gathers are issued in chunks (two
 // 4-orbital atoms or eight 1-orbital atoms) before their FMAs, so several L2
 // round trips overlap within one wave.
-template <int R, int CPL, int KS, typename Src>
+template <int R, int CPL, int KS, typename TA, typename TV, typename Src>
 __device__ __forceinline__ void block_product(int b0, int bs, int b1, int sub, const int* __restrict__ idx,
-                                              const double* __restrict__ v, const Src& src,
-                                              double (&acc)[R][CPL]) {
+                                              const TV* __restrict__ v, const Src& src, TA (&acc)[R][CPL]) {
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) acc[r][c] = 0.0;
+        for (int c = 0; c < CPL; ++c) acc[r][c] = TA(0);
     constexpr int C4 = 2, C1 = 8;
     int b = b0 + sub;
     for (; b + (C4 - 1) * KS < bs; b += C4 * KS) {
-        double x[C4][4][CPL];
+        TA x[C4][4][CPL];
 #pragma unroll
         for (int j = 0; j < C4; ++j) {
             const int o = idx[b + j * KS];
@@ -80,75 +176,84 @@ __device__ __forceinline__ void block_product(int b0, int bs, int b1, int sub, c
         }
 #pragma unroll
         for (int j = 0; j < C4; ++j) {
-            const double* __restrict__ vb = v + (size_t)(b + j * KS - b0) * (R * 4);
+            const TV* __restrict__ vb = v + (size_t)(b + j * KS - b0) * (R * 4);
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const double m = vb[r * 4 + q];
+                    const TA m = static_cast<TA>(vb[r * 4 + q]);
 #pragma unroll
-                    for (int c = 0; c < CPL; ++c) acc[r][c] = fma(m, x[j][q][c], acc[r][c]);
+                    for (int c = 0; c < CPL; ++c) acc[r][c] = fmac(m, x[j][q][c], acc[r][c]);
                 }
         }
     }
     for (; b < bs; b += KS) {
         const int o = idx[b];
-        double x[4][CPL];
+        TA x[4][CPL];
 #pragma unroll
         for (int q = 0; q < 4; ++q) src.get(o + q, x[q]);
-        const double* __restrict__ vb = v + (size_t)(b - b0) * (R * 4);
+        const TV* __restrict__ vb = v + (size_t)(b - b0) * (R * 4);
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const double m = vb[r * 4 + q];
+                const TA m = static_cast<TA>(vb[r * 4 + q]);
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) acc[r][c] = fma(m, x[q][c], acc[r][c]);
+                for (int c = 0; c < CPL; ++c) acc[r][c] = fmac(m, x[q][c], acc[r][c]);
             }
     }
-    const double* __restrict__ vh = v + (size_t)(bs - b0) * (R * 4);
+    const TV* __restrict__ vh = v + (size_t)(bs - b0) * (R * 4);
     b = bs + sub;
     for (; b + (C1 - 1) * KS < b1; b += C1 * KS) {
-        double x[C1][CPL];
+        TA x[C1][CPL];
 #pragma unroll
         for (int j = 0; j < C1; ++j) src.get(idx[b + j * KS], x[j]);
 #pragma unroll
         for (int j = 0; j < C1; ++j) {
-            const double* __restrict__ vb = vh + (size_t)(b + j * KS - bs) * R;
+            const TV* __restrict__ vb = vh + (size_t)(b + j * KS - bs) * R;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const double m = vb[r];
+                const TA m = static_cast<TA>(vb[r]);
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) acc[r][c] = fma(m, x[j][c], acc[r][c]);
+                for (int c = 0; c < CPL; ++c) acc[r][c] = fmac(m, x[j][c], acc[r][c]);
             }
         }
     }
     for (; b < b1; b += KS) {
-        double x[CPL];
+        TA x[CPL];
         src.get(idx[b], x);
-        const double* __restrict__ vb = vh + (size_t)(b - bs) * R;
+        const TV* __restrict__ vb = vh + (size_t)(b - bs) * R;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const double m = vb[r];
+            const TA m = static_cast<TA>(vb[r]);
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) acc[r][c] = fma(m, x[c], acc[r][c]);
+            for (int c = 0; c < CPL; ++c) acc[r][c] = fmac(m, x[c], acc[r][c]);
         }
     }
 }
 
-template <int NI, int CPL, typename Src>
+template <int NI, int CPL, typename TA, typename TV, typename Src>
 __device__ __forceinline__ void row_product(int I, const int* __restrict__ brow, const int* __restrict__ bsplit,
                                             const int* __restrict__ bidx, const int64_t* __restrict__ voff,
-                                            const double* __restrict__ vals, const Src& src,
-                                            double (&acc)[NI][CPL]) {
+                                            const TV* __restrict__ vals, const Src& src, TA (&acc)[NI][CPL]) {
     block_product<NI, CPL, 1>(brow[I], bsplit[I], brow[I + 1], 0, bidx, vals + voff[I], src, acc);
 }
 
-template <int CPL>
+// Rows of a [M][ld] block in memory type TX, delivered as TA.
+template <int CPL, typename TX, typename TA>
 struct GlobalSrc {
-    const double* __restrict__ X;
+    const TX* __restrict__ X;
     int ld, c0;
-    __device__ __forceinline__ void get(int row, double (&r)[CPL]) const { load_cols<CPL>(X, (size_t)row * ld + c0, r); }
+    __device__ __forceinline__ void get(int row, TA (&r)[CPL]) const {
+        if constexpr (std::is_same_v<TX, TA>) {
+            load_cols<CPL>(X, (size_t)row * ld + c0, r);
+        } else {
+            TX t[CPL];
+            load_cols<CPL>(X, (size_t)row * ld + c0, t);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) r[c] = static_cast<TA>(t[c]);
+        }
+    }
 };
 
 // LDS tile [rows][64] doubles, one column per lane
@@ -158,21 +263,32 @@ struct LdsSrc {
     __device__ __forceinline__ void get(int row, double (&r)[1]) const { r[0] = tile[row * kWave + lane]; }
 };
 
+template <int KIND>
+__device__ __forceinline__ const typename KindTypes<KIND>::TX* gather_src(const PassArgs& a) {
+    if constexpr (kVec32<KIND>)
+        return a.Xg32;
+    else
+        return a.Xg;
+}
+
 struct ColState {
     double A, B, al;
     int n, r;
 };
 
-template <int KIND, int NI, int CPL>
-__device__ __forceinline__ void epilogue(const PassArgs& a, int row, int c0, const double (&acc)[NI][CPL], int arow,
+template <int KIND, int NI, int CPL, typename TA>
+__device__ __forceinline__ void epilogue(const PassArgs& a, int row, int c0, const TA (&acc)[NI][CPL], int arow,
                                          const ColState (&cs)[CPL], double (&d0)[CPL], double (&d1)[CPL]) {
     const size_t idx = (size_t)row * a.ld + c0;
-    if constexpr (KIND == PASS_PLAIN) {
-        double y[CPL];
+    if constexpr (KIND == PASS_PLAIN || KIND == PASS_PLAIN32) {
+        TA y[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) y[c] = acc[arow][c];
-        store_cols<CPL>(a.Xio, idx, y);
-    } else if constexpr (KIND == PASS_LANCZOS_A) {
+        if constexpr (KIND == PASS_PLAIN)
+            store_cols<CPL>(a.Xio, idx, y);
+        else
+            store_cols<CPL>(a.Xio32, idx, y);
+    } else if constexpr (KIND == PASS_LANCZOS_A || KIND == PASS_LANCZOS_A_MX) {
         // cs.A = 1/beta_{n-1}, cs.B = beta_{n-1}/beta_{n-2}
         double tp[CPL], vq[CPL], sp[CPL], x1[CPL];
         load_cols<CPL>(a.S, idx, tp);
@@ -188,8 +304,19 @@ __device__ __forceinline__ void epilogue(const PassArgs& a, int row, int c0, con
             x1[c] = a.g0 * sp[c];
         }
         store_cols<CPL>(a.S, idx, sp);
-        store_cols<CPL>(a.Xio, idx, x1);
-    } else {
+        if constexpr (KIND == PASS_LANCZOS_A) {
+            store_cols<CPL>(a.Xio, idx, x1);
+        } else {
+            float s32[CPL], x32[CPL];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                s32[c] = static_cast<float>(sp[c]);
+                x32[c] = static_cast<float>(x1[c]);
+            }
+            store_cols<CPL>(a.R32o, idx, s32);
+            store_cols<CPL>(a.Xio32, idx, x32);
+        }
+    } else if constexpr (KIND == PASS_STEP || KIND == PASS_STEP_LAST) {
         double xk[CPL], s[CPL], xn[CPL];
         load_cols<CPL>(a.Xg, idx, xk);
         load_cols<CPL>(a.S, idx, s);
@@ -214,6 +341,49 @@ __device__ __forceinline__ void epilogue(const PassArgs& a, int row, int c0, con
             store_cols<CPL>(a.Xio, idx, xn);
             store_cols<CPL>(a.S, idx, s);
         }
+    } else if constexpr (KIND == PASS_REFINE) {
+        double s[CPL];
+        float r32[CPL], x32[CPL];
+        load_cols<CPL>(a.S, idx, s);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const double r = s[c] - acc[arow][c];
+            r32[c] = static_cast<float>(r);
+            x32[c] = static_cast<float>(a.g0 * r);
+        }
+        store_cols<CPL>(a.R32o, idx, r32);
+        store_cols<CPL>(a.Xio32, idx, x32);
+    } else {
+        static_assert(KIND == PASS_STEP32 || KIND == PASS_STEP32_LAST, "unknown pass kind");
+        float xk[CPL], r[CPL], xn[CPL];
+        load_cols<CPL>(a.Xg32, idx, xk);
+        load_cols<CPL>(a.R32, idx, r);
+        const float tau = static_cast<float>(a.tau);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) xn[c] = fmaf(tau, r[c] - acc[arow][c], xk[c]);
+        if constexpr (KIND == PASS_STEP32) {
+            store_cols<CPL>(a.Xio32, idx, xn);
+        } else {
+            float x1[CPL];
+            double vq[CPL], tn[CPL], s[CPL], v[CPL];
+            load_cols<CPL>(a.Xr1, idx, x1);
+            load_cols<CPL>(a.Vq, idx, vq);
+            load_cols<CPL>(a.Tn, idx, tn);
+            load_cols<CPL>(a.S, idx, s);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                v[c] = static_cast<double>(x1[c]) + static_cast<double>(xn[c]);
+                if (cs[c].n != 0) {
+                    const double f = cs[c].al * cs[c].A;
+                    v[c] -= f * vq[c];
+                    s[c] -= f * tn[c];
+                }
+                d0[c] = fma(v[c], s[c], d0[c]);
+                d1[c] = fma(s[c], s[c], d1[c]);
+            }
+            store_cols<CPL>(a.Xio, idx, v);
+            store_cols<CPL>(a.S, idx, s);
+        }
     }
 }
 
@@ -222,12 +392,12 @@ __device__ __forceinline__ void load_colstate(const PassArgs& a, int c0, ColStat
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         cs[c] = {0.0, 0.0, 0.0, 0, -1};
-        if constexpr (KIND == PASS_LANCZOS_A || KIND == PASS_STEP_LAST) {
+        if constexpr (kHasDots<KIND>) {
             cs[c].A = a.inv_beta[c0 + c];
             cs[c].n = a.slot_n[c0 + c];
             cs[c].r = a.slot_row[c0 + c];
-            if constexpr (KIND == PASS_LANCZOS_A) cs[c].B = a.coefT[c0 + c];
-            if constexpr (KIND == PASS_STEP_LAST) cs[c].al = a.alpha[c0 + c];
+            if constexpr (KIND == PASS_LANCZOS_A || KIND == PASS_LANCZOS_A_MX) cs[c].B = a.coefT[c0 + c];
+            if constexpr (kHasD1<KIND>) cs[c].al = a.alpha[c0 + c];
         }
     }
 }
@@ -237,7 +407,7 @@ __device__ __forceinline__ void load_colstate(const PassArgs& a, int c0, ColStat
 template <int KIND, int CPL, int NW>
 __device__ __forceinline__ void store_partials(const PassArgs& a, int group, int c0, int wave, int lane,
                                                const double (&d0)[CPL], const double (&d1)[CPL], double* red) {
-    if constexpr (KIND == PASS_LANCZOS_A || KIND == PASS_STEP_LAST) {
+    if constexpr (kHasDots<KIND>) {
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
@@ -254,7 +424,7 @@ __device__ __forceinline__ void store_partials(const PassArgs& a, int group, int
                     s1 += red[(1 * NW + w) * (kWave * CPL) + lane * CPL + c];
                 }
                 a.part0[(size_t)group * a.ld + c0 + c] = s0;
-                if constexpr (KIND == PASS_STEP_LAST) a.part1[(size_t)group * a.ld + c0 + c] = s1;
+                if constexpr (kHasD1<KIND>) a.part1[(size_t)group * a.ld + c0 + c] = s1;
             }
         }
     }
@@ -300,14 +470,24 @@ __device__ __forceinline__ void xcd_place(int n_groups, int n_tiles, int place, 
     }
 }
 
+template <int KIND>
+__device__ __forceinline__ int kind_tiles(const PassArgs& a) {
+    if constexpr (kTiles32<KIND>)
+        return a.n_tiles32;
+    else
+        return a.n_tiles;
+}
+
 template <int KIND, int CPL>
 __global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a, const int* __restrict__ brow,
                                                       const int* __restrict__ bsplit, const int* __restrict__ borb,
                                                       const int64_t* __restrict__ voff,
-                                                      const double* __restrict__ vals,
+                                                      const typename KindTypes<KIND>::TV* __restrict__ vals,
                                                       const int* __restrict__ atom_off) {
+    using TA = typename KindTypes<KIND>::TA;
+    using TX = typename KindTypes<KIND>::TX;
     int tile, slab;
-    xcd_place(a.n_slabs, a.n_tiles, a.place, tile, slab);
+    xcd_place(a.n_slabs, kind_tiles<KIND>(a), a.place, tile, slab);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c0 = tile * (kWave * CPL) + lane * CPL;
@@ -316,18 +496,18 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a, const int* __r
     double d0[CPL], d1[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) d0[c] = d1[c] = 0.0;
-    const GlobalSrc<CPL> src{a.Xg, a.ld, c0};
+    const GlobalSrc<CPL, TX, TA> src{gather_src<KIND>(a), a.ld, c0};
     const int first = slab * a.atoms_per_slab;
     const int last = min(first + a.atoms_per_slab, a.n_atoms);  // empty for trailing slabs
     for (int I = first + wave; I < last; I += kWavesPerBlock) {
         if (atom_off[I + 1] - atom_off[I] == 4) {
-            double acc[4][CPL];
+            TA acc[4][CPL];
             row_product<4, CPL>(I, brow, bsplit, borb, voff, vals, src, acc);
             const int r0 = atom_off[I];
 #pragma unroll
             for (int q = 0; q < 4; ++q) epilogue<KIND, 4, CPL>(a, r0 + q, c0, acc, q, cs, d0, d1);
         } else {
-            double acc[1][CPL];
+            TA acc[1][CPL];
             row_product<1, CPL>(I, brow, bsplit, borb, voff, vals, src, acc);
             epilogue<KIND, 1, CPL>(a, atom_off[I], c0, acc, 0, cs, d0, d1);
         }
@@ -400,11 +580,10 @@ __global__ __launch_bounds__(NW* kWave) void pass_lds_kernel(PassArgs a, const i
 // gathers is KS times shorter; the partial rows are summed through LDS.
 constexpr int kMaxGroupRows = 4 + kGroupH;
 
-template <int R, int CPL, int KS>
+template <int R, int CPL, int KS, typename TA, typename TV, typename Src>
 __device__ __forceinline__ void group_partial(int u0, int u4, int u1, int sub, const int* __restrict__ uorb,
-                                              const double* __restrict__ v, const GlobalSrc<CPL>& src, double* pw,
-                                              int lane) {
-    double acc[R][CPL];
+                                              const TV* __restrict__ v, const Src& src, TA* pw, int lane) {
+    TA acc[R][CPL];
     block_product<R, CPL, KS>(u0, u4, u1, sub, uorb, v, src, acc);
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -420,11 +599,16 @@ __global__ __launch_bounds__(kBlock) void pass_group_kernel(PassArgs a, const in
                                                             const int* __restrict__ gu4,
                                                             const int* __restrict__ guorb,
                                                             const int64_t* __restrict__ gvoff,
-                                                            const double* __restrict__ vals) {
+                                                            const typename KindTypes<KIND>::TV* __restrict__ vals) {
+    using TA = typename KindTypes<KIND>::TA;
+    using TX = typename KindTypes<KIND>::TX;
     constexpr int GPW = kWavesPerBlock / KS;  // groups per workgroup
-    __shared__ double part[kWavesPerBlock * kMaxGroupRows * kWave * CPL];
+    constexpr size_t kPartBytes = sizeof(TA) * kWavesPerBlock * kMaxGroupRows * kWave * CPL;
+    constexpr size_t kRedBytes = sizeof(double) * 2 * kWavesPerBlock * kWave * CPL;
+    __shared__ __align__(16) unsigned char smem[kPartBytes > kRedBytes ? kPartBytes : kRedBytes];
+    TA* part = reinterpret_cast<TA*>(smem);
     int tile, slab;
-    xcd_place(a.n_slabs, a.n_tiles, a.place, tile, slab);
+    xcd_place(a.n_slabs, kind_tiles<KIND>(a), a.place, tile, slab);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sub = wave % KS, gi = wave / KS;
@@ -434,15 +618,15 @@ __global__ __launch_bounds__(kBlock) void pass_group_kernel(PassArgs a, const in
     double d0[CPL], d1[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) d0[c] = d1[c] = 0.0;
-    const GlobalSrc<CPL> src{a.Xg, a.ld, c0};
+    const GlobalSrc<CPL, TX, TA> src{gather_src<KIND>(a), a.ld, c0};
     const int g = slab * GPW + gi;
     const bool live = g < a.n_grp;
     int R = 0;
-    double* pw = part + (size_t)wave * kMaxGroupRows * kWave * CPL;
+    TA* pw = part + (size_t)wave * kMaxGroupRows * kWave * CPL;
     if (live) {
         R = gR[g];
         const int u0 = guoff[g], u4 = gu4[g], u1 = guoff[g + 1];
-        const double* __restrict__ v = vals + gvoff[g];
+        const auto* __restrict__ v = vals + gvoff[g];
         switch (R) {
             case 1: group_partial<1, CPL, KS>(u0, u4, u1, sub, guorb, v, src, pw, lane); break;
             case 4: group_partial<4, CPL, KS>(u0, u4, u1, sub, guorb, v, src, pw, lane); break;
@@ -456,12 +640,12 @@ __global__ __launch_bounds__(kBlock) void pass_group_kernel(PassArgs a, const in
     if (live) {
         // wave `sub` of the group finishes rows sub, sub + KS, ...
         const int* __restrict__ rows = grows + groff[g];
-        const double* pg = part + (size_t)(gi * KS) * kMaxGroupRows * kWave * CPL;
+        const TA* pg = part + (size_t)(gi * KS) * kMaxGroupRows * kWave * CPL;
         for (int r = sub; r < R; r += KS) {
-            double acc[1][CPL];
+            TA acc[1][CPL];
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                double t = 0.0;
+                TA t = TA(0);
 #pragma unroll
                 for (int s = 0; s < KS; ++s) t += pg[((size_t)s * kMaxGroupRows * kWave + r * kWave + lane) * CPL + c];
                 acc[0][c] = t;
@@ -469,53 +653,75 @@ __global__ __launch_bounds__(kBlock) void pass_group_kernel(PassArgs a, const in
             epilogue<KIND, 1, CPL>(a, rows[r], c0, acc, 0, cs, d0, d1);
         }
     }
-    store_partials<KIND, CPL, kWavesPerBlock>(a, slab, c0, wave, lane, d0, d1, part);
-}
-
-template <int KIND, int KS>
-static void launch_group(const PassArgs& a, int cpl, int nwg, hipStream_t st) {
-    if (cpl == 2)
-        hipLaunchKernelGGL((pass_group_kernel<KIND, 2, KS>), dim3(nwg), dim3(kBlock), 0, st, a, a.g_R, a.g_roff,
-                           a.g_rows, a.g_uoff, a.g_u4, a.g_uorb, a.g_voff, a.vals);
-    else
-        hipLaunchKernelGGL((pass_group_kernel<KIND, 1, KS>), dim3(nwg), dim3(kBlock), 0, st, a, a.g_R, a.g_roff,
-                           a.g_rows, a.g_uoff, a.g_u4, a.g_uorb, a.g_voff, a.vals);
+    store_partials<KIND, CPL, kWavesPerBlock>(a, slab, c0, wave, lane, d0, d1, reinterpret_cast<double*>(smem));
 }
 
 template <int KIND>
-static void launch_kind(const PassArgs& a, int cpl, hipStream_t st) {
-    const int nwg = a.n_slabs * a.n_tiles;
+static const typename KindTypes<KIND>::TV* kind_vals(const PassArgs& a) {
+    if constexpr (std::is_same_v<typename KindTypes<KIND>::TV, float>)
+        return a.vals32;
+    else
+        return a.vals;
+}
+
+template <int KIND, int CPL>
+static void launch_cpl(const PassArgs& a, int nwg, hipStream_t st) {
+    const auto* vals = kind_vals<KIND>(a);
     if (a.staged == 9) {
         if (a.group_split == 4)
-            launch_group<KIND, 4>(a, cpl, nwg, st);
+            hipLaunchKernelGGL((pass_group_kernel<KIND, CPL, 4>), dim3(nwg), dim3(kBlock), 0, st, a, a.g_R, a.g_roff,
+                               a.g_rows, a.g_uoff, a.g_u4, a.g_uorb, a.g_voff, vals);
         else if (a.group_split == 2)
-            launch_group<KIND, 2>(a, cpl, nwg, st);
+            hipLaunchKernelGGL((pass_group_kernel<KIND, CPL, 2>), dim3(nwg), dim3(kBlock), 0, st, a, a.g_R, a.g_roff,
+                               a.g_rows, a.g_uoff, a.g_u4, a.g_uorb, a.g_voff, vals);
         else
-            launch_group<KIND, 1>(a, cpl, nwg, st);
-    } else if (a.staged == 1) {
-        hipLaunchKernelGGL((pass_lds_kernel<KIND, kStageWaves[0], kStageRows[0]>), dim3(nwg),
-                           dim3(kStageWaves[0] * kWave), 0, st, a, a.brow, a.bsplit, a.bloc, a.voff, a.vals,
-                           a.atom_off);
-    } else if (a.staged == 2) {
-        hipLaunchKernelGGL((pass_lds_kernel<KIND, kStageWaves[1], kStageRows[1]>), dim3(nwg),
-                           dim3(kStageWaves[1] * kWave), 0, st, a, a.brow, a.bsplit, a.bloc, a.voff, a.vals,
-                           a.atom_off);
-    } else if (cpl == 2) {
-        hipLaunchKernelGGL((pass_kernel<KIND, 2>), dim3(nwg), dim3(kBlock), 0, st, a, a.brow, a.bsplit, a.borb,
-                           a.voff, a.vals, a.atom_off);
+            hipLaunchKernelGGL((pass_group_kernel<KIND, CPL, 1>), dim3(nwg), dim3(kBlock), 0, st, a, a.g_R, a.g_roff,
+                               a.g_rows, a.g_uoff, a.g_u4, a.g_uorb, a.g_voff, vals);
     } else {
-        hipLaunchKernelGGL((pass_kernel<KIND, 1>), dim3(nwg), dim3(kBlock), 0, st, a, a.brow, a.bsplit, a.borb,
-                           a.voff, a.vals, a.atom_off);
+        hipLaunchKernelGGL((pass_kernel<KIND, CPL>), dim3(nwg), dim3(kBlock), 0, st, a, a.brow, a.bsplit, a.borb,
+                           a.voff, vals, a.atom_off);
     }
 }
 
+template <int KIND>
+static void launch_kind(const PassArgs& a, hipStream_t st) {
+    const int tiles = kTiles32<KIND> ? a.n_tiles32 : a.n_tiles;
+    const int nwg = a.n_slabs * tiles;
+    if constexpr (!std::is_same_v<typename KindTypes<KIND>::TV, float>) {
+        if (a.staged == 1) {
+            hipLaunchKernelGGL((pass_lds_kernel<KIND, kStageWaves[0], kStageRows[0]>), dim3(nwg),
+                               dim3(kStageWaves[0] * kWave), 0, st, a, a.brow, a.bsplit, a.bloc, a.voff, a.vals,
+                               a.atom_off);
+            return;
+        }
+        if (a.staged == 2) {
+            hipLaunchKernelGGL((pass_lds_kernel<KIND, kStageWaves[1], kStageRows[1]>), dim3(nwg),
+                               dim3(kStageWaves[1] * kWave), 0, st, a, a.brow, a.bsplit, a.bloc, a.voff, a.vals,
+                               a.atom_off);
+            return;
+        }
+    }
+    const int cpl = a.ld / (tiles * kWave);
+    if constexpr (kTiles32<KIND>) {
+        if (cpl == 4) return launch_cpl<KIND, 4>(a, nwg, st);
+    }
+    if (cpl == 2)
+        launch_cpl<KIND, 2>(a, nwg, st);
+    else
+        launch_cpl<KIND, 1>(a, nwg, st);
+}
+
 void launch_pass(PassKind kind, const PassArgs& a, hipStream_t st) {
-    const int cpl = (a.staged == 1 || a.staged == 2) ? 1 : a.ld / (a.n_tiles * kWave);
     switch (kind) {
-        case PASS_LANCZOS_A: launch_kind<PASS_LANCZOS_A>(a, cpl, st); break;
-        case PASS_STEP: launch_kind<PASS_STEP>(a, cpl, st); break;
-        case PASS_STEP_LAST: launch_kind<PASS_STEP_LAST>(a, cpl, st); break;
-        case PASS_PLAIN: launch_kind<PASS_PLAIN>(a, cpl, st); break;
+        case PASS_LANCZOS_A: launch_kind<PASS_LANCZOS_A>(a, st); break;
+        case PASS_STEP: launch_kind<PASS_STEP>(a, st); break;
+        case PASS_STEP_LAST: launch_kind<PASS_STEP_LAST>(a, st); break;
+        case PASS_PLAIN: launch_kind<PASS_PLAIN>(a, st); break;
+        case PASS_LANCZOS_A_MX: launch_kind<PASS_LANCZOS_A_MX>(a, st); break;
+        case PASS_STEP32: launch_kind<PASS_STEP32>(a, st); break;
+        case PASS_REFINE: launch_kind<PASS_REFINE>(a, st); break;
+        case PASS_STEP32_LAST: launch_kind<PASS_STEP32_LAST>(a, st); break;
+        case PASS_PLAIN32: launch_kind<PASS_PLAIN32>(a, st); break;
     }
 }
 

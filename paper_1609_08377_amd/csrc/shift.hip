@@ -327,11 +327,13 @@ void launch_spmm_generic(const DevMatrix& m, const double* vals, int nvec, int l
 }
 
 // ||e_j - (z_k B - A) x||_2 for full-mode solutions x_full [n_cols][K][M] complex,
-// one workgroup per (column, shift); FP64 throughout.
+// one workgroup per (column, shift); FP64 arithmetic on the stored values
+// (FP64, or the FP32 values of a mixed-precision matrix upcast exactly).
+template <typename TV>
 __global__ __launch_bounds__(256) void true_residual_kernel(
     const int* __restrict__ atom_off, const int* __restrict__ orb_atom, const int* __restrict__ brow,
     const int* __restrict__ bsplit, const int* __restrict__ borb, const int64_t* __restrict__ voff,
-    const double* __restrict__ Av, const double* __restrict__ Bv, int M, int K,
+    const TV* __restrict__ Av, const TV* __restrict__ Bv, int M, int K,
     const int* __restrict__ cols, const double* __restrict__ z, const double* __restrict__ xf,
     double* __restrict__ res) {
     __shared__ double sh[16];
@@ -356,10 +358,11 @@ __global__ __launch_bounds__(256) void true_residual_kernel(
             const int o = borb[b];
             for (int q = 0; q < nJ; ++q) {
                 const double xr = x[2 * (size_t)(o + q)], xi = x[2 * (size_t)(o + q) + 1];
-                bxr = fma(Bv[bo + q], xr, bxr);
-                bxi = fma(Bv[bo + q], xi, bxi);
-                axr = fma(Av[bo + q], xr, axr);
-                axi = fma(Av[bo + q], xi, axi);
+                const double bv = static_cast<double>(Bv[bo + q]), av = static_cast<double>(Av[bo + q]);
+                bxr = fma(bv, xr, bxr);
+                bxi = fma(bv, xi, bxi);
+                axr = fma(av, xr, axr);
+                axi = fma(av, xi, axi);
             }
         }
         double rr = (r == j ? 1.0 : 0.0) - (zr * bxr - zi * bxi - axr);
@@ -370,10 +373,14 @@ __global__ __launch_bounds__(256) void true_residual_kernel(
     if (threadIdx.x == 0) res[ck] = sqrt(acc);
 }
 
-void launch_true_residual(const DevMatrix& m, int n_cols, const int* cols, int K, const double* z,
-                          const double* x_full, double* res_out, hipStream_t st) {
-    hipLaunchKernelGGL(true_residual_kernel, dim3(n_cols * K), dim3(256), 0, st, m.atom_off, m.orb_atom, m.brow,
-                       m.bsplit, m.borb, m.voff, m.A, m.B, m.M, K, cols, z, x_full, res_out);
+void launch_true_residual(const DevMatrix& m, bool fp32_values, int n_cols, const int* cols, int K,
+                          const double* z, const double* x_full, double* res_out, hipStream_t st) {
+    if (fp32_values)
+        hipLaunchKernelGGL(true_residual_kernel<float>, dim3(n_cols * K), dim3(256), 0, st, m.atom_off, m.orb_atom,
+                           m.brow, m.bsplit, m.borb, m.voff, m.A32, m.B32, m.M, K, cols, z, x_full, res_out);
+    else
+        hipLaunchKernelGGL(true_residual_kernel<double>, dim3(n_cols * K), dim3(256), 0, st, m.atom_off, m.orb_atom,
+                           m.brow, m.bsplit, m.borb, m.voff, m.A, m.B, m.M, K, cols, z, x_full, res_out);
 }
 
 // Deterministic sum of n (a, b) pairs into out2[0], out2[1] (single workgroup).
