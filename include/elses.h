@@ -185,11 +185,12 @@ elses_status elses_ctx_pass_stats(elses_ctx ctx, int64_t *launches, double *avg_
  * Time `reps` back-to-back launches of one sparse pass on scratch blocks of
  * `slots` right-hand sides (a multiple of 64) with pass kernels `variant`
  * (as in elses_opts).  kind: 0 the A pass of a Lanczos step, 1 a
- * Richardson step of the overlap solve, 2 the last step with the Lanczos
- * correction, 3 the plain product; mixed precision (matrix created with
- * ELSES_MIXED): 4 the A pass, 5 an FP32 Richardson step, 6 the FP64
- * residual refinement, 7 the last FP32 step with the Lanczos correction,
- * 8 the plain FP32 product.  *avg_us receives the mean launch time
+ * Richardson step of the overlap solve, 2 the last step (with the dot
+ * products of the Lanczos step), 3 the plain product, 9 the first step
+ * (forming its operand from two vectors); mixed precision (matrix created
+ * with ELSES_MIXED): 4 the A pass, 5 an FP32 Richardson step, 6 the FP64
+ * residual refinement, 7 the last FP32 step, 8 the plain FP32 product,
+ * 10 the first FP32 step.  *avg_us receives the mean launch time
  * measured with HIP events on the context stream.  Used by the slot and
  * variant autotuner and by performance diagnostics.
  */
@@ -203,6 +204,46 @@ elses_status elses_time_pass(elses_ctx ctx, elses_mat mat, int32_t kind, int32_t
  * one-thread-per-entry kernel. */
 elses_status elses_spmm(elses_ctx ctx, elses_mat mat, int which, int32_t variant, int32_t nvec, const double *x,
                         double *y);
+
+/*
+ * Region problems (paper Sec. III-B: the real-space projection solves each
+ * column's equations on the principal sub-pencil (A_r, B_r) of the atoms
+ * within a radius of the column's atom; Eq. 7 needs only the column's own
+ * pattern).  A region set is built once and then solved for any shifts.
+ *
+ * elses_regions_create: region r is centred on atom centres[r] (HOST, n_regions
+ * distinct atoms) with radius radii[r] (HOST, Angstrom, > 0); it holds the atoms
+ * whose minimum-image distance to the centre is <= radius (the matrix needs
+ * pos, and box for periodic images).  Its columns are the orbitals of the
+ * centre atom, region by region in the order given, so consecutive regions
+ * should be spatial neighbours.  Regions are packed into tiles of
+ * tile_width column slots (64 or 128; 0 = 64) that advance through one
+ * persistent launch sequence; the set keeps its data on the device until
+ * destroyed, and depends on `mat`, which must outlive it.
+ */
+typedef struct elses_regions_s *elses_regions;
+elses_status elses_regions_create(elses_ctx ctx, elses_mat mat, int32_t n_regions, const int32_t *centres,
+                                  const double *radii, int32_t tile_width, elses_regions *out);
+void elses_regions_destroy(elses_regions reg);
+/* Sizes and layout of a region set (HOST outputs, each may be NULL):
+ * n_cols columns; n_tiles tiles; rows_total rows of all tiles' atom unions;
+ * useful_rows = sum over columns of their region's orbital count;
+ * cols [n_cols] global orbital of each column; pat_off [n_cols+1] offsets of
+ * each column's pattern P_j in the caller's matrix (as elses_pattern);
+ * region_orbitals [n_regions] orbitals of each region. */
+elses_status elses_regions_info(elses_regions reg, int32_t *n_cols, int32_t *n_tiles, int64_t *rows_total,
+                                int64_t *useful_rows, int32_t *cols, int64_t *pat_off, int32_t *region_orbitals);
+/* Solve (z_k B_r - A_r) x = e_j for every column of every region and every
+ * shift (HOST, Im z > 0), in pattern mode: x_out, rho_out, col_traces_out,
+ * iters_out and resid_out are laid out as in elses_density_matrix for the
+ * column list of elses_regions_info (pattern rows outside the region hold 0).
+ * c (HOST complex weights) may be NULL when no density output is requested.
+ * opts: as elses_opts (out_mode must be ELSES_OUT_PATTERN, variant 0 or a
+ * grouped variant; use_mixed needs a matrix created with ELSES_MIXED). */
+elses_status elses_regions_solve(elses_ctx ctx, elses_regions reg, int32_t n_shifts, const double *shifts,
+                                 const double *c, const elses_opts *opts, double *x_out, double *rho_out,
+                                 double *traces_out, double *col_traces_out, int32_t *iters_out,
+                                 double *resid_out);
 
 /* FP32 products with the FP32 copies of a matrix created with ELSES_MIXED:
  * y = fl32(X) x with FP32 accumulation, X = A (which=0) or B (which=1);

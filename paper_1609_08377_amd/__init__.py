@@ -96,6 +96,14 @@ def lib():
         L.elses_spmm.restype = ctypes.c_int
         L.elses_spmm32.argtypes = [P, P, ctypes.c_int, I32, I32, P, P]
         L.elses_spmm32.restype = ctypes.c_int
+        L.elses_regions_create.argtypes = [P, P, I32, P, P, I32, ctypes.POINTER(P)]
+        L.elses_regions_create.restype = ctypes.c_int
+        L.elses_regions_destroy.argtypes = [P]
+        L.elses_regions_destroy.restype = None
+        L.elses_regions_info.argtypes = [P, P, P, P, P, P, P, P]
+        L.elses_regions_info.restype = ctypes.c_int
+        L.elses_regions_solve.argtypes = [P, P, I32, P, P, ctypes.POINTER(Opts), P, P, P, P, P, P]
+        L.elses_regions_solve.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -323,3 +331,74 @@ def spmm32(ctx: Context, mat: Matrix, which: str, x, variant: str = "auto"):
                             _dev_ptr(y))
     ctx.check(st)
     return y
+
+
+class Regions:
+    """Region problems (principal sub-pencils around centre atoms) packed into tiles on the device."""
+
+    def __init__(self, ctx: Context, mat: Matrix, centres, radii, tile_width: int = 0):
+        self.ctx = ctx
+        self.mat = mat
+        centres = np.ascontiguousarray(centres, dtype=np.int32)
+        radii = np.ascontiguousarray(radii, dtype=np.float64)
+        if centres.shape != radii.shape:
+            raise ValueError("one radius per centre")
+        h = ctypes.c_void_p()
+        st = lib().elses_regions_create(ctx._h, mat._h, int(centres.shape[0]), _np_ptr(centres), _np_ptr(radii),
+                                        int(tile_width), ctypes.byref(h))
+        ctx.check(st)
+        self._h = h
+        nc, nt = ctypes.c_int32(), ctypes.c_int32()
+        rows, useful = ctypes.c_int64(), ctypes.c_int64()
+        lib().elses_regions_info(h, ctypes.byref(nc), ctypes.byref(nt), ctypes.byref(rows), ctypes.byref(useful),
+                                 None, None, None)
+        self.n_cols = int(nc.value)
+        self.n_tiles = int(nt.value)
+        self.rows_total = int(rows.value)
+        self.useful_rows = int(useful.value)
+        self.cols = np.zeros(self.n_cols, dtype=np.int32)
+        self.pat_off = np.zeros(self.n_cols + 1, dtype=np.int64)
+        self.region_orbitals = np.zeros(centres.shape[0], dtype=np.int32)
+        lib().elses_regions_info(h, None, None, None, None, _np_ptr(self.cols), _np_ptr(self.pat_off),
+                                 _np_ptr(self.region_orbitals))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().elses_regions_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def region_solve(ctx: Context, reg: Regions, shifts, c=None, *, tol=1e-8, max_outer=20000, inner_tol=1e-13,
+                 mixed=False, want_x=True, allow_not_converged=False, variant="auto"):
+    """Solve every region's columns for every shift; density outputs when weights c are given."""
+    torch = _torch()
+    z = _shifts_ri(shifts)
+    K = z.shape[0] // 2
+    cw = None if c is None else _shifts_ri(c)
+    if cw is not None and cw.shape[0] != 2 * K:
+        raise ValueError("one weight per shift")
+    nc = reg.n_cols
+    npat = int(reg.pat_off[-1])
+    dev = torch.device("cuda", ctx.device)
+    x = torch.empty(2 * npat * K, dtype=torch.float64, device=dev) if want_x else None
+    rho = torch.empty(npat, dtype=torch.float64, device=dev) if cw is not None else None
+    col_tr = torch.empty(2 * nc, dtype=torch.float64, device=dev) if cw is not None else None
+    iters = torch.empty(nc, dtype=torch.int32, device=dev)
+    resid = torch.empty(nc * K, dtype=torch.float64, device=dev)
+    traces = np.zeros(2)
+    opts = make_opts(tol, max_outer, inner_tol, False, 0, mixed, False, variant)
+    st = lib().elses_regions_solve(ctx._h, reg._h, K, _np_ptr(z), None if cw is None else _np_ptr(cw),
+                                   ctypes.byref(opts), _dev_ptr(x), _dev_ptr(rho),
+                                   None if cw is None else _np_ptr(traces), _dev_ptr(col_tr), _dev_ptr(iters),
+                                   _dev_ptr(resid))
+    ctx.check(st, allow_warn=allow_not_converged)
+    return dict(x=None if x is None else torch.view_as_complex(x.view(-1, 2)), rho=rho,
+                traces=traces if cw is not None else None,
+                col_traces=None if col_tr is None else col_tr.view(nc, 2), iters=iters, resid=resid.view(nc, K),
+                pat_off=reg.pat_off, cols=reg.cols, status=st)

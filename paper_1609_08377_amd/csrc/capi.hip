@@ -7,11 +7,13 @@
 //    spans the shift-invariant Krylov space K_n(B^{-1}A; B^{-1}e_j), shared by
 //    every shift; its vectors are real.
 //  * Each Lanczos step needs one overlap solve v = B^{-1} s.  It is done with a
-//    fixed-degree Chebyshev iteration on an interval enclosing the spectrum
-//    of B.  Being a fixed polynomial p(B), it is linear, so the Lanczos
-//    correction -alpha_n q_n can be applied after the solve (p(B) t_n = q_n
-//    exactly) and the process is the exact Lanczos process of the pencil
+//    fixed-degree Richardson iteration whose step lengths are the Chebyshev
+//    roots of an interval enclosing the spectrum of B.  Being a fixed
+//    polynomial p(B), the process is the exact Lanczos process of the pencil
 //    (A, p(B)^{-1}); the degree is chosen so that ||I - p(B) B|| <= inner_tol.
+//    The solve runs on s = s' - alpha_n t_n itself (alpha_n is reduced between
+//    the A pass and the first overlap step), which keeps q = p(B) t to
+//    rounding at every step.
 //  * A block of `ld` columns ("slots") advances together; every pass is one
 //    sparse product with the block plus the step's element-wise work.  When
 //    a column has converged for all shifts its slot takes the next column.
@@ -292,7 +294,7 @@ Rich richardson_plan(double lo, double hi, double tol) {
         t1 = t2;
         ++d;
     }
-    r.d = std::max(d, 2);
+    r.d = std::max(d, 3);  // a first step, at least one middle or last step
     const double pi = 3.14159265358979323846;
     std::vector<double> roots(r.d);
     for (int i = 0; i < r.d; ++i) roots[i] = cen + half * cos((2.0 * i + 1.0) * pi / (2.0 * r.d));
@@ -381,7 +383,15 @@ void elses_mat_destroy(elses_mat m) {
     delete m;
 }
 
-elses_status elses_mat_create(elses_ctx ctx, const elses_system* sys, int precision, elses_mat* out) {
+}  // extern "C"
+
+namespace {
+
+// Matrix creation.  bracket == nullptr: a caller's matrix (kept on the host
+// too, for carving regions; spectral bracket of B by Lanczos).  Otherwise an
+// internal batched matrix whose B spectrum lies inside the given interval.
+elses_status mat_create_impl(elses_ctx ctx, const elses_system* sys, int precision, const double* bracket,
+                             elses_mat* out) {
     if (!ctx) return ELSES_ERR_INVALID_ARG;
     if (!out || !sys) return set_err(ctx, ELSES_ERR_INVALID_ARG, "null argument");
     *out = nullptr;
@@ -488,6 +498,12 @@ elses_status elses_mat_create(elses_ctx ctx, const elses_system* sys, int precis
     }
     if (sys->pos) h.pos.assign(sys->pos, sys->pos + 3 * (size_t)N);
     h.box = sys->box;
+    if (!bracket) {
+        h.n_orb.assign(sys->n_orb, sys->n_orb + N);
+        h.in_voff = in_voff;
+        h.A_in.assign(sys->A_val, sys->A_val + nnz);
+        h.B_in.assign(sys->B_val, sys->B_val + nnz);
+    }
 
     auto* m = new elses_mat_s();
     m->ctx = ctx;
@@ -533,6 +549,8 @@ elses_status elses_mat_create(elses_ctx ctx, const elses_system* sys, int precis
         {
             HostGroups G;
             build_groups(sys, h, in_voff, G);
+            h.grp_row0.resize(G.R.size());  // moved into m->h below
+            for (size_t g = 0; g < G.R.size(); ++g) h.grp_row0[g] = G.rows[G.roff[g]];
             auto& D = d.grp;
             D.n = (int)G.R.size();
             D.nval = (int64_t)G.A.size();
@@ -593,63 +611,68 @@ elses_status elses_mat_create(elses_ctx ctx, const elses_system* sys, int precis
         }
         m->h = std::move(h);
 
-        // Spectral bracket of B: Lanczos sweep from a fixed pseudo-random start.
-        const int M = d.M;
-        const int steps = std::min(M, 80);
-        hipStream_t st = ctx->stream;
-        DevPool pool;
-        double* v = pool.get<double>(M);
-        double* u = pool.get<double>(M);
-        double* w = pool.get<double>(M);
-        const int nbl = std::min(256, (M + 255) / 256);
-        double* part = pool.get<double>(nbl);
-        std::vector<double> hv(M), hp(nbl);
-        uint64_t s = 0x2545F4914F6CDD1DULL;
-        double nrm = 0;
-        for (int i = 0; i < M; ++i) {
-            s ^= s << 13;
-            s ^= s >> 7;
-            s ^= s << 17;
-            hv[i] = (double)(s >> 11) / 9007199254740992.0 - 0.5;
-            nrm += hv[i] * hv[i];
-        }
-        nrm = sqrt(nrm);
-        for (int i = 0; i < M; ++i) hv[i] /= nrm;
-        HCHECK(hipMemcpyAsync(v, hv.data(), sizeof(double) * M, hipMemcpyHostToDevice, st));
-        HCHECK(hipMemsetAsync(u, 0, sizeof(double) * M, st));
-        std::vector<double> ta, tb;
-        double bprev = 0.0;
-        auto dotdev = [&](const double* x, const double* y) {
-            launch_dot_partial(x, y, M, part, nbl, st);
-            HCHECK(hipMemcpyAsync(hp.data(), part, sizeof(double) * nbl, hipMemcpyDeviceToHost, st));
-            HCHECK(hipStreamSynchronize(st));
-            double acc = 0;
-            for (double q : hp) acc += q;
-            return acc;
-        };
-        for (int k = 0; k < steps; ++k) {
-            launch_spmm_generic(d, d.B, 1, 1, v, w, st);
-            const double al = dotdev(v, w);
-            launch_lanczos_orth(w, v, u, al, bprev, M, st);
-            ta.push_back(al);
-            const double bb = sqrt(std::max(dotdev(w, w), 0.0));
-            if (k + 1 == steps || bb <= 1e-12 * fabs(al)) break;
-            tb.push_back(bb);
-            launch_lanczos_shift(u, v, w, 1.0 / bb, M, st);
-            bprev = bb;
-        }
-        HCHECK(hipGetLastError());
-        tb.resize(ta.size() > 0 ? ta.size() - 1 : 0);
-        const double tmin = tri_eig(ta, tb, 0);
-        const double tmax = tri_eig(ta, tb, (int)ta.size() - 1);
-        const double width = tmax - tmin;
-        m->b_lo = tmin - 0.02 * width - 1e-3 * fabs(tmin);
-        m->b_hi = tmax + 0.02 * width + 1e-3 * fabs(tmax);
-        if (!(m->b_lo > 0.0) || !std::isfinite(m->b_hi)) {
-            char buf[160];
-            snprintf(buf, sizeof buf, "overlap B is not positive definite (Lanczos bracket [%g, %g])", tmin, tmax);
-            elses_mat_destroy(m);
-            return set_err(ctx, ELSES_ERR_NOT_SPD, buf);
+        if (bracket) {
+            m->b_lo = bracket[0];
+            m->b_hi = bracket[1];
+        } else {
+            // Spectral bracket of B: Lanczos sweep from a fixed pseudo-random start.
+            const int M = d.M;
+            const int steps = std::min(M, 80);
+            hipStream_t st = ctx->stream;
+            DevPool pool;
+            double* v = pool.get<double>(M);
+            double* u = pool.get<double>(M);
+            double* w = pool.get<double>(M);
+            const int nbl = std::min(256, (M + 255) / 256);
+            double* part = pool.get<double>(nbl);
+            std::vector<double> hv(M), hp(nbl);
+            uint64_t s = 0x2545F4914F6CDD1DULL;
+            double nrm = 0;
+            for (int i = 0; i < M; ++i) {
+                s ^= s << 13;
+                s ^= s >> 7;
+                s ^= s << 17;
+                hv[i] = (double)(s >> 11) / 9007199254740992.0 - 0.5;
+                nrm += hv[i] * hv[i];
+            }
+            nrm = sqrt(nrm);
+            for (int i = 0; i < M; ++i) hv[i] /= nrm;
+            HCHECK(hipMemcpyAsync(v, hv.data(), sizeof(double) * M, hipMemcpyHostToDevice, st));
+            HCHECK(hipMemsetAsync(u, 0, sizeof(double) * M, st));
+            std::vector<double> ta, tb;
+            double bprev = 0.0;
+            auto dotdev = [&](const double* x, const double* y) {
+                launch_dot_partial(x, y, M, part, nbl, st);
+                HCHECK(hipMemcpyAsync(hp.data(), part, sizeof(double) * nbl, hipMemcpyDeviceToHost, st));
+                HCHECK(hipStreamSynchronize(st));
+                double acc = 0;
+                for (double q : hp) acc += q;
+                return acc;
+            };
+            for (int k = 0; k < steps; ++k) {
+                launch_spmm_generic(d, d.B, 1, 1, v, w, st);
+                const double al = dotdev(v, w);
+                launch_lanczos_orth(w, v, u, al, bprev, M, st);
+                ta.push_back(al);
+                const double bb = sqrt(std::max(dotdev(w, w), 0.0));
+                if (k + 1 == steps || bb <= 1e-12 * fabs(al)) break;
+                tb.push_back(bb);
+                launch_lanczos_shift(u, v, w, 1.0 / bb, M, st);
+                bprev = bb;
+            }
+            HCHECK(hipGetLastError());
+            tb.resize(ta.size() > 0 ? ta.size() - 1 : 0);
+            const double tmin = tri_eig(ta, tb, 0);
+            const double tmax = tri_eig(ta, tb, (int)ta.size() - 1);
+            const double width = tmax - tmin;
+            m->b_lo = tmin - 0.02 * width - 1e-3 * fabs(tmin);
+            m->b_hi = tmax + 0.02 * width + 1e-3 * fabs(tmax);
+            if (!(m->b_lo > 0.0) || !std::isfinite(m->b_hi)) {
+                char buf[160];
+                snprintf(buf, sizeof buf, "overlap B is not positive definite (Lanczos bracket [%g, %g])", tmin, tmax);
+                elses_mat_destroy(m);
+                return set_err(ctx, ELSES_ERR_NOT_SPD, buf);
+            }
         }
     } catch (const HipFail& f) {
         elses_mat_destroy(m);
@@ -658,6 +681,14 @@ elses_status elses_mat_create(elses_ctx ctx, const elses_system* sys, int precis
     }
     *out = m;
     return ELSES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+elses_status elses_mat_create(elses_ctx ctx, const elses_system* sys, int precision, elses_mat* out) {
+    return mat_create_impl(ctx, sys, precision, nullptr, out);
 }
 
 elses_status elses_mat_info(elses_mat m, int64_t* M, int64_t* pmax, double* b_lo, double* b_hi) {
@@ -784,15 +815,265 @@ int choose_slots(int n_cols, int M, const elses_opts& o) {
     return std::max(ld, 64);
 }
 
+}  // namespace
+
+// Region problems packed into tiles of one block-diagonal matrix.  A region
+// is the principal sub-pencil of the atoms within a radius of a centre atom
+// (the paper's real-space projection, Sec. III-B); its columns are the
+// centre atom's orbitals.  Consecutive regions fill tiles of L column slots;
+// tile t's block holds the union of its regions' atoms, and a per-(row,
+// column) bit marks the rows inside each column's own region.  Keeping every
+// vector zero outside its region makes each column's solve exactly that of
+// its region's sub-pencil, while all columns of a tile share one pass over
+// the union.
+struct elses_regions_s {
+    elses_ctx ctx = nullptr;
+    elses_mat gm = nullptr;  // the caller's matrix (not owned)
+    elses_mat bm = nullptr;  // block-diagonal tile matrix (owned)
+    int L = 64, n_tiles = 0, n_cols = 0, n_regions = 0;
+    std::vector<int> cols;         // global orbital of each column, region by region
+    std::vector<int> col_row;      // row of each column's unit vector in bm
+    std::vector<int> slot_map;     // [n_tiles * L] column of each slot or -1
+    std::vector<int64_t> pat_off;  // [n_cols + 1] offsets of the global pattern of each column
+    std::vector<int> rows;         // bm row of each pattern entry, -1 outside the region
+    std::vector<int64_t> vidx;     // internal value index of X_ji in gm per pattern entry
+    std::vector<int> group_tile;   // tile of each row group of bm (non-decreasing)
+    std::vector<int> region_orbs;  // orbitals of each region
+    std::vector<int> region_tile;
+    int64_t useful = 0;            // sum over columns of their region's orbitals
+    uint64_t* d_mask = nullptr;
+    int* d_col_row = nullptr;
+    int* d_rows = nullptr;
+    int64_t* d_vidx = nullptr;
+    int64_t* d_pat_off = nullptr;
+    int* d_slot_map = nullptr;
+    ~elses_regions_s() {
+        void* p[] = {d_mask, d_col_row, d_rows, d_vidx, d_pat_off, d_slot_map};
+        for (void* q : p)
+            if (q) (void)hipFree(q);
+        if (bm) elses_mat_destroy(bm);
+    }
+};
+
+namespace {
+
+elses_status regions_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, const int32_t* centres,
+                                 const double* radii, int tile_width, elses_regions* out) {
+    const HostMatrix& h = gm->h;
+    const int N = h.n_atoms;
+    if (h.n_orb.empty()) return set_err(ctx, ELSES_ERR_INVALID_ARG, "regions need a caller-created matrix");
+    if (h.pos.empty()) return set_err(ctx, ELSES_ERR_INVALID_ARG, "regions need atom positions (pos)");
+    if (n_regions < 1 || !centres || !radii) return set_err(ctx, ELSES_ERR_INVALID_ARG, "no regions");
+    const int L = tile_width == 0 ? 64 : tile_width;
+    if (L != 64 && L != 128) return set_err(ctx, ELSES_ERR_INVALID_ARG, "tile_width must be 0, 64 or 128");
+    {
+        std::vector<char> seen(N, 0);
+        for (int r = 0; r < n_regions; ++r) {
+            if (centres[r] < 0 || centres[r] >= N) return set_err(ctx, ELSES_ERR_INVALID_ARG, "centre out of range");
+            if (seen[centres[r]]) return set_err(ctx, ELSES_ERR_INVALID_ARG, "duplicate centre");
+            seen[centres[r]] = 1;
+            if (!(radii[r] > 0.0) || !std::isfinite(radii[r]))
+                return set_err(ctx, ELSES_ERR_INVALID_ARG, "radii must be finite and > 0");
+        }
+    }
+    auto* P = new elses_regions_s();
+    P->ctx = ctx;
+    P->gm = gm;
+    P->L = L;
+    P->n_regions = n_regions;
+    // region membership: minimum-image distance to the centre <= radius
+    const double box = h.box;
+    std::vector<std::vector<int>> reg(n_regions);
+    for (int r = 0; r < n_regions; ++r) {
+        const int c = centres[r];
+        const double cx = h.pos[3 * c], cy = h.pos[3 * c + 1], cz = h.pos[3 * c + 2];
+        const double R2 = radii[r] * radii[r];
+        int orbs = 0;
+        for (int I = 0; I < N; ++I) {
+            double dx = h.pos[3 * I] - cx, dy = h.pos[3 * I + 1] - cy, dz = h.pos[3 * I + 2] - cz;
+            if (box > 0.0) {
+                dx -= box * std::nearbyint(dx / box);
+                dy -= box * std::nearbyint(dy / box);
+                dz -= box * std::nearbyint(dz / box);
+            }
+            if (dx * dx + dy * dy + dz * dz <= R2) {
+                reg[r].push_back(I);
+                orbs += h.n_orb[I];
+            }
+        }
+        P->region_orbs.push_back(orbs);
+    }
+    // tiles: consecutive regions while their columns fit
+    std::vector<int> tile_r0{0};
+    {
+        int used = 0;
+        for (int r = 0; r < n_regions; ++r) {
+            const int nc = h.n_orb[centres[r]];
+            if (used + nc > L) {
+                tile_r0.push_back(r);
+                used = 0;
+            }
+            used += nc;
+        }
+        tile_r0.push_back(n_regions);
+    }
+    const int T = (int)tile_r0.size() - 1;
+    P->n_tiles = T;
+    P->slot_map.assign((size_t)T * L, -1);
+    // block-diagonal system of the tile unions
+    std::vector<int8_t> bn_orb;
+    std::vector<int64_t> brp{0};
+    std::vector<int32_t> bcol;
+    std::vector<double> bA, bB;
+    std::vector<int> stamp(N, -1), loc(N, -1);
+    std::vector<int> tile_row0, tile_atom0;
+    std::vector<std::vector<int>> tile_atoms(T);
+    int atom_base = 0, row_base = 0;
+    for (int t = 0; t < T; ++t) {
+        std::vector<int>& U = tile_atoms[t];
+        for (int r = tile_r0[t]; r < tile_r0[t + 1]; ++r)
+            for (int I : reg[r])
+                if (stamp[I] != t) {
+                    stamp[I] = t;
+                    U.push_back(I);
+                }
+        std::sort(U.begin(), U.end());
+        for (size_t k = 0; k < U.size(); ++k) loc[U[k]] = atom_base + (int)k;
+        tile_atom0.push_back(atom_base);
+        tile_row0.push_back(row_base);
+        for (int I : U) {
+            bn_orb.push_back(h.n_orb[I]);
+            const int nI = h.n_orb[I];
+            for (int b = h.brow[I]; b < h.brow[I + 1]; ++b) {
+                const int J = h.bcol[b];
+                if (stamp[J] != t) continue;
+                bcol.push_back(loc[J]);
+                const int64_t len = (int64_t)nI * h.n_orb[J];
+                bA.insert(bA.end(), h.A_in.begin() + h.in_voff[b], h.A_in.begin() + h.in_voff[b] + len);
+                bB.insert(bB.end(), h.B_in.begin() + h.in_voff[b], h.B_in.begin() + h.in_voff[b] + len);
+            }
+            brp.push_back((int64_t)bcol.size());
+            row_base += nI;
+        }
+        atom_base += (int)U.size();
+    }
+    tile_atom0.push_back(atom_base);
+    tile_row0.push_back(row_base);
+    elses_system bsys{};
+    bsys.n_atoms = atom_base;
+    bsys.n_orb = bn_orb.data();
+    bsys.blk_row_ptr = brp.data();
+    bsys.blk_col = bcol.data();
+    bsys.A_val = bA.data();
+    bsys.B_val = bB.data();
+    bsys.pos = nullptr;
+    bsys.box = 0.0;
+    const double bracket[2] = {gm->b_lo, gm->b_hi};  // principal submatrices: Cauchy interlacing
+    elses_status st = mat_create_impl(ctx, &bsys, gm->precision, bracket, &P->bm);
+    if (st != ELSES_OK) {
+        delete P;
+        return st;
+    }
+    const int Mb = P->bm->d.M;
+    std::vector<int> brow_off(atom_base + 1, 0);
+    for (int a = 0; a < atom_base; ++a) brow_off[a + 1] = brow_off[a] + bn_orb[a];
+    // columns, slots, masks, patterns
+    const int mw = L / 64;
+    std::vector<uint64_t> mask((size_t)Mb * mw, 0);
+    std::vector<int64_t> asc_voff(h.brow[N]);
+    try {
+        HCHECK(hipMemcpy(asc_voff.data(), gm->d.asc_voff, sizeof(int64_t) * asc_voff.size(), hipMemcpyDeviceToHost));
+    } catch (const HipFail& f) {
+        delete P;
+        return set_err(ctx, ELSES_ERR_HIP, std::string(f.what) + ": " + hipGetErrorString(f.e));
+    }
+    P->pat_off.push_back(0);
+    for (int t = 0; t < T; ++t) {
+        for (int k = 0; k < (int)tile_atoms[t].size(); ++k) loc[tile_atoms[t][k]] = tile_atom0[t] + k;
+        int slot = 0;
+        for (int r = tile_r0[t]; r < tile_r0[t + 1]; ++r) {
+            P->region_tile.push_back(t);
+            const int C = centres[r];
+            std::vector<char> inreg;  // membership of the tile's union atoms
+            inreg.assign(tile_atoms[t].size(), 0);
+            for (int I : reg[r]) inreg[loc[I] - tile_atom0[t]] = 1;
+            const int c_first = (int)P->cols.size();
+            for (int q = 0; q < h.n_orb[C]; ++q) {
+                const int cidx = (int)P->cols.size();
+                P->cols.push_back(h.atom_off[C] + q);
+                P->col_row.push_back(brow_off[loc[C]] + q);
+                P->slot_map[(size_t)t * L + slot] = cidx;
+                for (int I : reg[r])
+                    for (int row = brow_off[loc[I]]; row < brow_off[loc[I] + 1]; ++row)
+                        mask[(size_t)row * mw + (slot >> 6)] |= 1ull << (slot & 63);
+                ++slot;
+                P->useful += P->region_orbs[r];
+                // pattern of column (C, q) in the caller's matrix
+                for (int b = h.brow[C]; b < h.brow[C + 1]; ++b) {
+                    const int J = h.bcol[b];
+                    const int nJ = h.n_orb[J];
+                    const bool inside = stamp[J] >= 0 && loc[J] >= tile_atom0[t] && loc[J] < tile_atom0[t + 1] &&
+                                        inreg[loc[J] - tile_atom0[t]];
+                    for (int al = 0; al < nJ; ++al) {
+                        P->rows.push_back(inside ? brow_off[loc[J]] + al : -1);
+                        P->vidx.push_back(asc_voff[b] + (int64_t)q * nJ + al);
+                    }
+                }
+                P->pat_off.push_back((int64_t)P->rows.size());
+            }
+            (void)c_first;
+        }
+    }
+    P->n_cols = (int)P->cols.size();
+    // tile of each row group
+    {
+        std::vector<int> row_tile(Mb);
+        for (int t = 0; t < T; ++t)
+            for (int row = tile_row0[t]; row < tile_row0[t + 1]; ++row) row_tile[row] = t;
+        P->group_tile.resize(P->bm->h.grp_row0.size());
+        for (size_t g = 0; g < P->group_tile.size(); ++g) P->group_tile[g] = row_tile[P->bm->h.grp_row0[g]];
+        for (size_t g = 1; g < P->group_tile.size(); ++g)
+            if (P->group_tile[g] < P->group_tile[g - 1]) {
+                delete P;
+                return set_err(ctx, ELSES_ERR_HIP, "internal: row groups are not ordered by tile");
+            }
+    }
+    try {
+        P->d_mask = dalloc<uint64_t>(mask.size());
+        P->d_col_row = dalloc<int>(P->col_row.size());
+        P->d_rows = dalloc<int>(P->rows.size());
+        P->d_vidx = dalloc<int64_t>(P->vidx.size());
+        P->d_pat_off = dalloc<int64_t>(P->pat_off.size());
+        P->d_slot_map = dalloc<int>(P->slot_map.size());
+        HCHECK(hipMemcpy(P->d_mask, mask.data(), sizeof(uint64_t) * mask.size(), hipMemcpyHostToDevice));
+        HCHECK(hipMemcpy(P->d_col_row, P->col_row.data(), sizeof(int) * P->col_row.size(), hipMemcpyHostToDevice));
+        HCHECK(hipMemcpy(P->d_rows, P->rows.data(), sizeof(int) * P->rows.size(), hipMemcpyHostToDevice));
+        HCHECK(hipMemcpy(P->d_vidx, P->vidx.data(), sizeof(int64_t) * P->vidx.size(), hipMemcpyHostToDevice));
+        HCHECK(hipMemcpy(P->d_pat_off, P->pat_off.data(), sizeof(int64_t) * P->pat_off.size(),
+                         hipMemcpyHostToDevice));
+        HCHECK(hipMemcpy(P->d_slot_map, P->slot_map.data(), sizeof(int) * P->slot_map.size(),
+                         hipMemcpyHostToDevice));
+    } catch (const HipFail& f) {
+        delete P;
+        const elses_status s = (f.e == hipErrorOutOfMemory) ? ELSES_ERR_OOM : ELSES_ERR_HIP;
+        return set_err(ctx, s, std::string(f.what) + ": " + hipGetErrorString(f.e));
+    }
+    *out = P;
+    return ELSES_OK;
+}
+
 elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t* cols, int K,
                         const double* shifts, const double* cw, const elses_opts* opts_in, double* x_out,
                         int32_t* iters_out, double* resid_out, double* rho_out, double* traces_out,
-                        double* col_traces_out) {
+                        double* col_traces_out, const elses_regions_s* rp = nullptr) {
     if (!ctx || !mat) return ELSES_ERR_INVALID_ARG;
     elses_opts o;
     elses_opts_default(&o);
     if (opts_in) o = *opts_in;
-    const DevMatrix& d = mat->d;
+    // gd: the caller's matrix (columns, patterns, trace values); d: the
+    // matrix of the passes (gd, or the block-diagonal region tiles)
+    const DevMatrix& gd = mat->d;
+    const DevMatrix& d = rp ? rp->bm->d : mat->d;
     const HostMatrix& h = mat->h;
     const int M = d.M;
     const bool density = (cw != nullptr);
@@ -820,7 +1101,8 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         return set_err(ctx, ELSES_ERR_INVALID_ARG, "audit needs ELSES_OUT_FULL with x_out and resid_out");
     if (density && full) return set_err(ctx, ELSES_ERR_INVALID_ARG, "density matrix output uses the pattern mode");
     if (n_cols > 0 && !cols) return set_err(ctx, ELSES_ERR_INVALID_ARG, "cols is null");
-    {
+    if (rp && full) return set_err(ctx, ELSES_ERR_INVALID_ARG, "region solves use the pattern mode");
+    if (!rp) {
         std::vector<char> seen(M, 0);
         for (int c = 0; c < n_cols; ++c) {
             if (cols[c] < 0 || cols[c] >= M) return set_err(ctx, ELSES_ERR_INVALID_ARG, "column out of range");
@@ -832,11 +1114,46 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
     if (n_cols == 0) return ELSES_OK;
 
     hipStream_t st = ctx->stream;
-    const int ld = choose_slots(n_cols, M, o);
+    // ld: slots (columns advanced together); vw: width of a vector row
+    const int ld = rp ? rp->n_tiles * rp->L : choose_slots(n_cols, M, o);
+    const int vw = rp ? rp->L : ld;
     if (ld % 64 != 0) return set_err(ctx, ELSES_ERR_INVALID_ARG, "slot count must be a multiple of 64");
     PassArgs pa{};
-    const char* verr = configure_pass(d, o.variant, ld, pa);
+    const char* verr = configure_pass(d, o.variant, vw, pa);
     if (verr) return set_err(ctx, ELSES_ERR_INVALID_ARG, verr);
+    // region tiles: slabs of groups of one tile, chunks of slabs for the reductions
+    std::vector<int> slab_group, slab_tile, chunk_s0, chunk_s1, tile_chunk_off;
+    if (rp) {
+        if (pa.staged != 9) return set_err(ctx, ELSES_ERR_INVALID_ARG, "region solves use the grouped passes");
+        const int gpw = kWavesPerBlock / pa.group_split;
+            const int ng = (int)rp->group_tile.size();
+        if (ng == 0) return set_err(ctx, ELSES_ERR_INVALID_ARG, "region tiles have no row groups");
+        tile_chunk_off.push_back(0);
+        int g = 0;
+        for (int t = 0; t < rp->n_tiles; ++t) {
+            const int g0 = g;
+            while (g < ng && rp->group_tile[g] == t) ++g;
+            const int s0 = (int)slab_tile.size();
+            for (int q = g0; q < g; q += gpw) {
+                for (int i = 0; i < gpw; ++i) slab_group.push_back(q + i < g ? q + i : -1);
+                slab_tile.push_back(t);
+            }
+            const int s1 = (int)slab_tile.size();
+            for (int q = s0; q < s1; q += 64) {
+                chunk_s0.push_back(q);
+                chunk_s1.push_back(std::min(q + 64, s1));
+            }
+            tile_chunk_off.push_back((int)chunk_s0.size());
+        }
+        while (slab_tile.size() % 8 != 0) {
+            for (int i = 0; i < gpw; ++i) slab_group.push_back(-1);
+            slab_tile.push_back(0);
+        }
+        pa.n_slabs = (int)slab_tile.size();
+        pa.n_tiles = pa.n_tiles32 = 1;
+        pa.mask_words = rp->L / 64;
+        pa.mask = rp->d_mask;
+    }
     const int n_groups = pa.n_slabs;
     const bool mixed = o.use_mixed != 0;
     if (mixed && (pa.staged == 1 || pa.staged == 2))
@@ -852,7 +1169,9 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
 
     // host-side pattern offsets
     std::vector<int64_t> row_off(n_cols + 1, 0);
-    {
+    if (rp) {
+        row_off = rp->pat_off;
+    } else {
         std::vector<int> orb_atom(M);
         for (int I = 0; I < h.n_atoms; ++I)
             for (int q = h.atom_off[I]; q < h.atom_off[I + 1]; ++q) orb_atom[q] = I;
@@ -866,10 +1185,9 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
     try {
         HCHECK(hipSetDevice(ctx->device));
         DevPool pool;
-        const size_t vsz = (size_t)M * ld;
+        const size_t vsz = (size_t)M * vw;
         double* buf[5] = {};
         for (int i = 0; i < 5; ++i) {
-            if (mixed && i == 1) continue;  // the mixed solve keeps its iterates in FP32
             buf[i] = pool.get<double>(vsz);
             HCHECK(hipMemsetAsync(buf[i], 0, vsz * sizeof(double), st));
         }
@@ -879,11 +1197,28 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
                 buf32[i] = pool.get<float>(vsz);
                 HCHECK(hipMemsetAsync(buf32[i], 0, vsz * sizeof(float), st));
             }
-        double* part0 = pool.get<double>((size_t)n_groups * ld);
-        double* part1 = pool.get<double>((size_t)n_groups * ld);
-        HCHECK(hipMemsetAsync(part0, 0, sizeof(double) * n_groups * ld, st));
-        HCHECK(hipMemsetAsync(part1, 0, sizeof(double) * n_groups * ld, st));
-        double* red_tmp = pool.get<double>((size_t)((n_groups + 63) / 64) * ld);
+        double* part0 = pool.get<double>((size_t)n_groups * vw);
+        double* part1 = pool.get<double>((size_t)n_groups * vw);
+        HCHECK(hipMemsetAsync(part0, 0, sizeof(double) * n_groups * vw, st));
+        HCHECK(hipMemsetAsync(part1, 0, sizeof(double) * n_groups * vw, st));
+        double* red_tmp = pool.get<double>(rp ? chunk_s0.size() * (size_t)vw : (size_t)((n_groups + 63) / 64) * ld);
+        int *d_slab_group = nullptr, *d_slab_tile = nullptr, *d_chunk = nullptr;
+        if (rp) {
+            d_slab_group = pool.get<int>(slab_group.size());
+            d_slab_tile = pool.get<int>(slab_tile.size());
+            d_chunk = pool.get<int>(2 * chunk_s0.size() + tile_chunk_off.size());
+            HCHECK(hipMemcpyAsync(d_slab_group, slab_group.data(), sizeof(int) * slab_group.size(),
+                                  hipMemcpyHostToDevice, st));
+            HCHECK(hipMemcpyAsync(d_slab_tile, slab_tile.data(), sizeof(int) * slab_tile.size(), hipMemcpyHostToDevice,
+                                  st));
+            HCHECK(hipMemcpyAsync(d_chunk, chunk_s0.data(), sizeof(int) * chunk_s0.size(), hipMemcpyHostToDevice, st));
+            HCHECK(hipMemcpyAsync(d_chunk + chunk_s0.size(), chunk_s1.data(), sizeof(int) * chunk_s1.size(),
+                                  hipMemcpyHostToDevice, st));
+            HCHECK(hipMemcpyAsync(d_chunk + 2 * chunk_s0.size(), tile_chunk_off.data(),
+                                  sizeof(int) * tile_chunk_off.size(), hipMemcpyHostToDevice, st));
+            pa.slab_group = d_slab_group;
+            pa.slab_tile = d_slab_tile;
+        }
         double* vs = pool.get<double>(ld);
         double* ss = pool.get<double>(ld);
         double* alpha = pool.get<double>(ld);
@@ -899,10 +1234,10 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         double* res = pool.get<double>((size_t)ld * K);
         double* xs = pool.get<double>((size_t)ld * K * rmax * 2);
         double* ps = pool.get<double>((size_t)ld * K * rmax * 2);
-        int* d_cols = pool.get<int>(n_cols);
-        int64_t* d_row_off = pool.get<int64_t>(n_cols + 1);
-        int* d_rows = full ? nullptr : pool.get<int>((size_t)row_off[n_cols]);
-        int64_t* d_vidx = density ? pool.get<int64_t>((size_t)row_off[n_cols]) : nullptr;
+        int* d_cols = rp ? rp->d_col_row : pool.get<int>(n_cols);
+        int64_t* d_row_off = rp ? rp->d_pat_off : pool.get<int64_t>(n_cols + 1);
+        int* d_rows = rp ? rp->d_rows : (full ? nullptr : pool.get<int>((size_t)row_off[n_cols]));
+        int64_t* d_vidx = rp ? rp->d_vidx : (density ? pool.get<int64_t>((size_t)row_off[n_cols]) : nullptr);
         double* d_z = pool.get<double>(2 * K);
         double* d_cw = density ? pool.get<double>(2 * K) : nullptr;
         int* counters = pool.get<int>(4);
@@ -910,14 +1245,19 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
                                                   : nullptr;
         double* tr2 = pool.get<double>(2);
         HCHECK(hipMemsetAsync(conv, 0, sizeof(int) * ld * K, st));
-        HCHECK(hipMemcpyAsync(d_cols, cols, sizeof(int) * n_cols, hipMemcpyHostToDevice, st));
-        HCHECK(hipMemcpyAsync(d_row_off, row_off.data(), sizeof(int64_t) * (n_cols + 1), hipMemcpyHostToDevice, st));
+        if (!rp) {
+            HCHECK(hipMemcpyAsync(d_cols, cols, sizeof(int) * n_cols, hipMemcpyHostToDevice, st));
+            HCHECK(hipMemcpyAsync(d_row_off, row_off.data(), sizeof(int64_t) * (n_cols + 1), hipMemcpyHostToDevice,
+                                  st));
+        }
         HCHECK(hipMemcpyAsync(d_z, shifts, sizeof(double) * 2 * K, hipMemcpyHostToDevice, st));
         if (density) HCHECK(hipMemcpyAsync(d_cw, cw, sizeof(double) * 2 * K, hipMemcpyHostToDevice, st));
-        if (!full) launch_pattern_setup(d, n_cols, d_cols, d_row_off, d_rows, d_vidx, st);
+        if (!full && !rp) launch_pattern_setup(d, n_cols, d_cols, d_row_off, d_rows, d_vidx, st);
 
         ShiftArgs sa{};
         sa.ld = ld;
+        sa.vld = vw;
+        sa.slot_map = rp ? rp->d_slot_map : nullptr;
         sa.K = K;
         sa.M = M;
         sa.z = d_z;
@@ -943,8 +1283,8 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         sa.row_off = d_row_off;
         sa.rows = d_rows;
         sa.vidx = d_vidx;
-        sa.Bv = d.B;
-        sa.Av = d.A;
+        sa.Bv = gd.B;
+        sa.Av = gd.A;
         sa.full = full ? 1 : 0;
         sa.tol = o.tol;
         sa.max_outer = o.max_outer;
@@ -967,20 +1307,21 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         pa.part1 = part1;
         pa.g0 = rich.g0;
 
+        // column sums of the dot partials (masked: idle and starting slots get 0)
+        auto reduce = [&](const double* part, double* out, bool masked) {
+            const int* sn = masked ? slot_n : nullptr;
+            const int* sr = masked ? slot_row : nullptr;
+            if (rp)
+                launch_col_reduce_tiles(part, vw, rp->n_tiles, (int)chunk_s0.size(), d_chunk,
+                                        d_chunk + chunk_s0.size(), d_chunk + 2 * chunk_s0.size(), red_tmp, sn, sr,
+                                        out, st);
+            else
+                launch_col_reduce(part, n_groups, ld, red_tmp, sn, sr, out, st);
+        };
         HCHECK(hipHostMalloc((void**)&h_rem, sizeof(int) * 4, hipHostMallocDefault));
         HCHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        double* Vq = buf[0];
-        double* Xa = buf[1];
-        double* Xb = buf[2];
-        double* Tp = buf[3];
-        double* Tn = buf[4];
-        const int poll = 8;
-        const int64_t generations = (n_cols + ld - 1) / ld + 1;
-        const int64_t cap = (int64_t)o.max_outer * generations + 64;
-        bool pending = false;
         int64_t it = 0;
-        // sampled event timing of one Chebyshev pass per `prof_stride` outer iterations
-        // A sample spans the back-to-back Richardson steps k = 2 .. d-2 of one
+        // Sampled event timing of the overlap-solve passes.  A sample spans the back-to-back Richardson steps k = 2 .. d-2 of one
         // outer iteration (d - 3 launches of the same kernel), so the mean
         // launch time excludes the event overhead.
         struct EvPair {
@@ -1006,8 +1347,8 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         if (!prof.empty()) {
             const double w = mixed ? 4.0 : 8.0;  // bytes per value and per vector entry of the timed pass
             ctx->prof_bytes = (double)d.nnz * w + (double)d.nnzb * 4.0 + (double)d.n_atoms * 20.0 +
-                              3.0 * (double)M * ld * w;
-            ctx->prof_flops = 2.0 * (double)d.nnz * ld + 3.0 * (double)M * ld;
+                              3.0 * (double)M * vw * w;
+            ctx->prof_flops = 2.0 * (double)d.nnz * vw + 3.0 * (double)M * vw;
             ctx->prof_slots = ld;
         }
         EvPair* open_sample = nullptr;
@@ -1028,110 +1369,107 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
                 open_sample = nullptr;
             }
         };
-        pa.vals32 = valsA32;
+        // Buffers: q_n, t_{n-1}, t_n and two free blocks.  Each outer step:
+        // s' = A q_n - beta t_{n-1} overwrites t_{n-1}; the first overlap step
+        // writes s = s' - alpha t_n to a free block; the Richardson iterates
+        // ping-pong between the other free block and the s' block; then
+        // q <- v, t_{n-1} <- t_n, t_n <- s.
+        double* Vq = buf[0];
+        double* Tp = buf[1];
+        double* Tn = buf[2];
+        double* F1 = buf[3];
+        double* F2 = buf[4];
         float* S32 = buf32[0];
         float* Xa32 = buf32[1];
         float* Xb32 = buf32[2];
         float* R32 = buf32[3];
         float* Da32 = buf32[4];
         float* Db32 = buf32[5];
-        double* Vn = buf[2];
-        while (mixed) {
-            // w = A q_n (FP32 values, FP64 accumulation), s', alpha partials,
-            // FP32 copies of s' and x_1
+        const int poll = 8;
+        const int64_t generations = (n_cols + ld - 1) / ld + 1;
+        const int64_t cap = (int64_t)o.max_outer * generations + 64;
+        bool pending = false;
+        for (;;) {
+            // w = A q_n, s' = w - beta t_{n-1} (in place of t_{n-1}), alpha_n
+            pa.vals = valsA;
             pa.vals32 = valsA32;
             pa.Xg = Vq;
             pa.S = Tp;
             pa.Vq = Vq;
-            pa.R32o = S32;
-            pa.Xio32 = Xa32;
-            launch_pass(PASS_LANCZOS_A_MX, pa, st);
-            launch_col_reduce(part0, n_groups, ld, red_tmp, slot_n, slot_row, alpha, st);
-            // round 1: FP32 Richardson solve of B x = s'
-            pa.vals32 = valsB32;
-            float* xcur = Xa32;
-            float* xoth = Xb32;
-            pa.R32 = S32;
-            for (int k = 1; k < rich.d; ++k) {
-                pa.Xg32 = xcur;
-                pa.Xio32 = xoth;
-                pa.tau = rich.tau[k - 1];
-                timed_pass(PASS_STEP32, k);
-                std::swap(xcur, xoth);
-            }
-            // FP64 residual r = s' - B x, first correction iterate
-            pa.Xg32 = xcur;
-            pa.R32o = R32;
-            pa.Xio32 = Da32;
-            launch_pass(PASS_REFINE, pa, st);
-            // round 2: FP32 solve of B d = r; the last step forms v = x + d
-            // and applies the deferred Lanczos correction
-            float* dcur = Da32;
-            float* doth = Db32;
-            pa.R32 = R32;
-            pa.Xr1 = xcur;
-            pa.Xio = Vn;
-            pa.Tn = Tn;
-            for (int k = 1; k < rich.d; ++k) {
-                pa.Xg32 = dcur;
-                pa.Xio32 = doth;
-                pa.tau = rich.tau[k - 1];
-                launch_pass(k == rich.d - 1 ? PASS_STEP32_LAST : PASS_STEP32, pa, st);
-                std::swap(dcur, doth);
-            }
-            launch_col_reduce(part0, n_groups, ld, red_tmp, nullptr, nullptr, vs, st);
-            launch_col_reduce(part1, n_groups, ld, red_tmp, nullptr, nullptr, ss, st);
-            sa.Vq = Vq;
-            launch_shift_update(sa, st);
-            HCHECK(hipGetLastError());
-            std::swap(Vq, Vn);
-            std::swap(Tp, Tn);
-            ++it;
-            if (it % poll == 0) {
-                if (pending) {
-                    HCHECK(hipEventSynchronize(ev));
-                    harvest();
-                    if (h_rem[0] == 0) break;
-                }
-                HCHECK(hipMemcpyAsync(h_rem, sa.remaining, sizeof(int), hipMemcpyDeviceToHost, st));
-                HCHECK(hipEventRecord(ev, st));
-                pending = true;
-            }
-            if (it > cap) throw HipFail{hipErrorUnknown, "solver loop did not terminate"};
-        }
-        while (!mixed) {
-            // w = A q_n, s' = w - beta t_{n-1}, alpha partials, x_1
-            pa.vals = valsA;
-            pa.Xg = Vq;
-            pa.Xio = Xa;
-            pa.S = Tp;
-            pa.Vq = Vq;
-            launch_pass(PASS_LANCZOS_A, pa, st);
-            launch_col_reduce(part0, n_groups, ld, red_tmp, slot_n, slot_row, alpha, st);
-            // overlap solve by Richardson steps (Chebyshev roots, Leja order)
-            double* xcur = Xa;
-            double* xoth = Xb;
+            launch_pass(mixed ? PASS_LANCZOS_A_MX : PASS_LANCZOS_A, pa, st);
+            reduce(part0, alpha, true);
+            // overlap solve v = p(B) s on s = s' - alpha t_n (Richardson steps
+            // with the Chebyshev roots in Leja order)
             pa.vals = valsB;
+            pa.vals32 = valsB32;
             pa.Tn = Tn;
-            for (int k = 1; k < rich.d; ++k) {
-                pa.Xg = xcur;
-                pa.Xio = xoth;
-                pa.tau = rich.tau[k - 1];
-                timed_pass(k == rich.d - 1 ? PASS_STEP_LAST : PASS_STEP, k);
-                std::swap(xcur, xoth);
+            pa.Sout = F1;
+            pa.tau = rich.tau[0];
+            double* vout = nullptr;
+            if (!mixed) {
+                pa.Xio = F2;
+                launch_pass(PASS_STEP_FIRST, pa, st);
+                double* xcur = F2;
+                double* xoth = Tp;
+                pa.S = F1;
+                for (int k = 2; k < rich.d; ++k) {
+                    pa.Xg = xcur;
+                    pa.Xio = xoth;
+                    pa.tau = rich.tau[k - 1];
+                    timed_pass(k == rich.d - 1 ? PASS_STEP_LAST : PASS_STEP, k);
+                    std::swap(xcur, xoth);
+                }
+                vout = xcur;
+                F2 = xoth;
+            } else {
+                // round 1: FP32 solve of B x = s (s kept in FP64 and FP32)
+                pa.R32o = S32;
+                pa.Xio32 = Xa32;
+                launch_pass(PASS_STEP32_FIRST, pa, st);
+                float* xcur = Xa32;
+                float* xoth = Xb32;
+                pa.R32 = S32;
+                for (int k = 2; k < rich.d; ++k) {
+                    pa.Xg32 = xcur;
+                    pa.Xio32 = xoth;
+                    pa.tau = rich.tau[k - 1];
+                    timed_pass(PASS_STEP32, k);
+                    std::swap(xcur, xoth);
+                }
+                // FP64 residual r = s - B x, first correction iterate
+                pa.S = F1;
+                pa.Xg32 = xcur;
+                pa.R32o = R32;
+                pa.Xio32 = Da32;
+                launch_pass(PASS_REFINE, pa, st);
+                // round 2: FP32 solve of B d = r; the last step forms v = x + d
+                float* dcur = Da32;
+                float* doth = Db32;
+                pa.R32 = R32;
+                pa.Xr1 = xcur;
+                pa.Xio = F2;
+                for (int k = 1; k < rich.d; ++k) {
+                    pa.Xg32 = dcur;
+                    pa.Xio32 = doth;
+                    pa.tau = rich.tau[k - 1];
+                    launch_pass(k == rich.d - 1 ? PASS_STEP32_LAST : PASS_STEP32, pa, st);
+                    std::swap(dcur, doth);
+                }
+                vout = F2;
+                F2 = Tp;
             }
-            launch_col_reduce(part0, n_groups, ld, red_tmp, nullptr, nullptr, vs, st);
-            launch_col_reduce(part1, n_groups, ld, red_tmp, nullptr, nullptr, ss, st);
+            reduce(part0, vs, false);
+            reduce(part1, ss, false);
             // multi-shift recurrences, convergence, slot refill
             sa.Vq = Vq;
             launch_shift_update(sa, st);
             HCHECK(hipGetLastError());
-            // rotate buffers
+            // rotate: q <- v, t_{n-1} <- t_n, t_n <- s; the old q block is free
             double* oldV = Vq;
-            Vq = xcur;
-            Xa = oldV;
-            Xb = xoth;
-            std::swap(Tp, Tn);
+            Vq = vout;
+            Tp = Tn;
+            Tn = F1;
+            F1 = oldV;
             ++it;
             if (it % poll == 0) {
                 if (pending) {
@@ -1220,7 +1558,7 @@ elses_status elses_time_pass(elses_ctx ctx, elses_mat mat, int32_t kind, int32_t
                              int32_t reps, double* avg_us) {
     if (!ctx || !mat || !avg_us) return ELSES_ERR_INVALID_ARG;
     if (kind < 0 || kind >= kPassKinds || reps < 1) return set_err(ctx, ELSES_ERR_INVALID_ARG, "bad kind or reps");
-    const bool k32 = kind >= PASS_LANCZOS_A_MX;
+    const bool k32 = (kind >= PASS_LANCZOS_A_MX && kind <= PASS_PLAIN32) || kind == PASS_STEP32_FIRST;
     if (k32 && mat->precision != ELSES_MIXED)
         return set_err(ctx, ELSES_ERR_INVALID_ARG, "mixed-precision passes need a matrix created with ELSES_MIXED");
     const DevMatrix& d = mat->d;
@@ -1258,6 +1596,7 @@ elses_status elses_time_pass(elses_ctx ctx, elses_mat mat, int32_t kind, int32_t
         pa.S = S;
         pa.Vq = V;
         pa.Tn = T;
+        pa.Sout = V;
         pa.Xg32 = F[0];
         pa.Xio32 = F[1];
         pa.R32 = F[2];
@@ -1292,6 +1631,44 @@ elses_status elses_time_pass(elses_ctx ctx, elses_mat mat, int32_t kind, int32_t
         return set_err(ctx, ELSES_ERR_HIP, std::string(f.what) + ": " + hipGetErrorString(f.e));
     }
     return ELSES_OK;
+}
+
+elses_status elses_regions_create(elses_ctx ctx, elses_mat mat, int32_t n_regions, const int32_t* centres,
+                                  const double* radii, int32_t tile_width, elses_regions* out) {
+    if (!ctx || !mat || !out) return ELSES_ERR_INVALID_ARG;
+    *out = nullptr;
+    try {
+        HCHECK(hipSetDevice(ctx->device));
+    } catch (const HipFail& f) {
+        return set_err(ctx, ELSES_ERR_HIP, std::string(f.what) + ": " + hipGetErrorString(f.e));
+    }
+    return regions_create_impl(ctx, mat, n_regions, centres, radii, tile_width, out);
+}
+
+void elses_regions_destroy(elses_regions reg) { delete reg; }
+
+elses_status elses_regions_info(elses_regions reg, int32_t* n_cols, int32_t* n_tiles, int64_t* rows_total,
+                                int64_t* useful_rows, int32_t* cols, int64_t* pat_off, int32_t* region_orbitals) {
+    if (!reg) return ELSES_ERR_INVALID_ARG;
+    if (n_cols) *n_cols = reg->n_cols;
+    if (n_tiles) *n_tiles = reg->n_tiles;
+    if (rows_total) *rows_total = reg->bm->d.M;
+    if (useful_rows) *useful_rows = reg->useful;
+    if (cols) std::copy(reg->cols.begin(), reg->cols.end(), cols);
+    if (pat_off) std::copy(reg->pat_off.begin(), reg->pat_off.end(), pat_off);
+    if (region_orbitals) std::copy(reg->region_orbs.begin(), reg->region_orbs.end(), region_orbitals);
+    return ELSES_OK;
+}
+
+elses_status elses_regions_solve(elses_ctx ctx, elses_regions reg, int32_t n_shifts, const double* shifts,
+                                 const double* c, const elses_opts* opts, double* x_out, double* rho_out,
+                                 double* traces_out, double* col_traces_out, int32_t* iters_out,
+                                 double* resid_out) {
+    if (!ctx || !reg) return ELSES_ERR_INVALID_ARG;
+    if (!c && (rho_out || traces_out || col_traces_out))
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "density outputs need the weights c");
+    return solve_core(ctx, reg->gm, reg->n_cols, reg->cols.data(), n_shifts, shifts, c, opts, x_out, iters_out,
+                      resid_out, rho_out, traces_out, col_traces_out, reg);
 }
 
 elses_status elses_spmm32(elses_ctx ctx, elses_mat mat, int which, int32_t variant, int32_t nvec, const float* x,

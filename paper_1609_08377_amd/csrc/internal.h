@@ -80,6 +80,11 @@ struct HostMatrix {
     double box = 0;
     int pmax = 0;                     // max over atoms of the coupled-orbital count
     std::vector<int> atom_plen;       // coupled-orbital count per atom
+    // caller's layout (caller matrices only; used to carve regions)
+    std::vector<int8_t> n_orb;
+    std::vector<int64_t> in_voff;     // value offset of each block (ascending order), nnzb + 1
+    std::vector<double> A_in, B_in;
+    std::vector<int> grp_row0;        // first row of each row group
 };
 
 }  // namespace elses
@@ -113,19 +118,21 @@ namespace elses {
 // Vector passes over the atom-block matrix (lanes = right-hand sides).
 // ---------------------------------------------------------------------------
 enum PassKind {
-    PASS_LANCZOS_A = 0,
-    PASS_STEP = 1,
-    PASS_STEP_LAST = 2,
-    PASS_PLAIN = 3,
+    PASS_LANCZOS_A = 0,     // w = A q_n, s' = w - beta_{n-1} t_{n-1}, partial q_n.s'
+    PASS_STEP = 1,          // Richardson step x_{k+1} = x_k + tau (s - B x_k)
+    PASS_STEP_LAST = 2,     // last step, partial v.s and s.s
+    PASS_PLAIN = 3,         // y = X x
     // mixed precision: FP32 matrix values; overlap solve in FP32 vectors with
     // one FP64-accumulated residual refinement
-    PASS_LANCZOS_A_MX = 4,  // as PASS_LANCZOS_A with FP32 values; also writes FP32 s' and x_1
-    PASS_STEP32 = 5,        // FP32 Richardson step x_{k+1} = x_k + tau (r - B x_k)
-    PASS_REFINE = 6,        // r = s' - B x (FP64 accumulation); FP32 r and first correction iterate
-    PASS_STEP32_LAST = 7,   // last FP32 correction step, v = x + d, then the Lanczos correction
-    PASS_PLAIN32 = 8        // y = X x in FP32 (diagnostics)
+    PASS_LANCZOS_A_MX = 4,  // as PASS_LANCZOS_A with FP32 values
+    PASS_STEP32 = 5,        // FP32 Richardson step
+    PASS_REFINE = 6,        // r = s - B x (FP64 accumulation); FP32 r and first correction iterate
+    PASS_STEP32_LAST = 7,   // last FP32 correction step, v = x + d, partial v.s and s.s
+    PASS_PLAIN32 = 8,       // y = X x in FP32 (diagnostics)
+    PASS_STEP_FIRST = 9,    // s = s' - alpha_n t_n, x_1 = g0 s formed while gathering; first step
+    PASS_STEP32_FIRST = 10  // the same with an FP32 iterate; also writes s in FP32
 };
-constexpr int kPassKinds = 9;
+constexpr int kPassKinds = 11;
 
 struct PassArgs {
     // matrix
@@ -148,25 +155,36 @@ struct PassArgs {
     int n_clusters;
     const int *cl_atom, *cl_uoff, *cl_urow, *bloc;
     int n_grp, group_split;  // row groups; waves sharing one group (1, 2 or 4)
+    // Region tiles (block-diagonal batched matrix, grouped passes only):
+    // slab_group[slab * groups_per_slab + i] is the i-th group of a slab or -1,
+    // slab_tile[slab] the column tile whose per-slot state the slab uses.  The
+    // vectors are [M][ld] with ld = the tile width; every row belongs to one
+    // tile.  mask[row * mask_words + w] holds one bit per column: set when the
+    // row lies inside that column's region.  Outputs outside it are zero.
+    const int *slab_group, *slab_tile;
+    const uint64_t *mask;
+    int mask_words;
     int place;               // workgroup placement (0 XCD regions tile by tile, 1 XCD regions tile-fastest, 2 plain)
     const int *g_R, *g_roff, *g_rows, *g_uoff, *g_u4, *g_uorb;
     const int64_t *g_voff;
     // vectors
     const double *Xg;   // gathered operand
-    double *Xio;        // STEP: out x_{k+1}; LANCZOS_A: out x_1; PLAIN: out y
-    double *S;          // LANCZOS_A: in t_{n-1} / out s'; STEP: in s; STEP_LAST: in s', out s
-    const double *Vq;   // STEP_LAST / LANCZOS_A: q_n (unnormalised, own rows)
-    const double *Tn;   // STEP_LAST: t_n (unnormalised, own rows)
+    double *Xio;        // STEP*: out x_{k+1} (STEP_LAST, STEP32_LAST: v); PLAIN: out y
+    double *S;          // LANCZOS_A: in t_{n-1} / out s'; STEP*_FIRST: in s' (gathered);
+                        // STEP, STEP_LAST, REFINE, STEP32_LAST: in s
+    double *Sout;       // STEP*_FIRST: out s = s' - alpha_n t_n
+    const double *Vq;   // LANCZOS_A: q_n (unnormalised)
+    const double *Tn;   // STEP*_FIRST: t_n (unnormalised, gathered)
     // FP32 vectors of the mixed-precision overlap solve
     const float *Xg32;  // gathered FP32 operand (STEP32*, REFINE, PLAIN32)
     float *Xio32;       // FP32 output iterate
     const float *R32;   // FP32 right-hand side (STEP32*)
-    float *R32o;        // LANCZOS_A_MX: FP32 s'; REFINE: FP32 residual
+    float *R32o;        // STEP32_FIRST: FP32 s; REFINE: FP32 residual
     const float *Xr1;   // STEP32_LAST: first-round FP32 solution x
     // per-slot scalars
     const double *inv_beta;   // 1/beta_{n-1}
     const double *coefT;      // beta_{n-1}/beta_{n-2}
-    const double *alpha;      // alpha_n (reduced)
+    const double *alpha;      // alpha_n (reduced before the first step)
     const int *slot_n;        // iteration counter (0 = start vector)
     const int *slot_row;      // e_j row of the slot's column (-1 idle)
     // Richardson step x_{k+1} = x_k + tau (s - B x_k)
@@ -183,6 +201,7 @@ void launch_pass(PassKind kind, const PassArgs &a, hipStream_t st);
 // ---------------------------------------------------------------------------
 struct ShiftArgs {
     int ld;          // slot count
+    int vld;         // row stride of the [M][vld] vectors; slot s uses column s % vld
     int K;           // shifts
     int M;
     const double *z; // [K] complex
@@ -212,6 +231,7 @@ struct ShiftArgs {
     int full;                      // 1: rows are 0..M-1
     double tol;
     int max_outer;
+    const int *slot_map;           // initial column of each slot (-1 idle), or null: slot s takes column s
     int *queue;                    // next column to start
     int *remaining;                // columns not yet finished
     int *n_notconv;                // columns finished without convergence
@@ -227,6 +247,13 @@ struct ShiftArgs {
 // ceil(n_part/64) x ld doubles).  With slot_n given, idle or starting slots get 0.
 void launch_col_reduce(const double *part, int n_part, int ld, double *tmp, const int *slot_n, const int *slot_row,
                        double *out, hipStream_t st);
+// Region tiles: out[t * L + c] = sum over the slabs of tile t of part[slab * L + c],
+// in two deterministic stages.  Chunk k covers slabs [chunk_s0[k], chunk_s1[k]);
+// tile t owns chunks [tile_chunk_off[t], tile_chunk_off[t+1]); tmp holds
+// n_chunks x L doubles.
+void launch_col_reduce_tiles(const double *part, int L, int n_tiles, int n_chunks, const int *chunk_s0,
+                             const int *chunk_s1, const int *tile_chunk_off, double *tmp, const int *slot_n,
+                             const int *slot_row, double *out, hipStream_t st);
 void launch_shift_update(const ShiftArgs &a, hipStream_t st);
 void launch_pattern_setup(const DevMatrix &m, int n_cols, const int *cols, const int64_t *row_off, int *rows,
                           int64_t *vidx, hipStream_t st);

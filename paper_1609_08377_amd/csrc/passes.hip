@@ -5,27 +5,35 @@
 // the element-wise work of one solver step into the epilogue, so the vectors
 // cross HBM as few times as possible:
 //
-//   PASS_LANCZOS_A  w = A q_n; s' = w - beta_{n-1} t_{n-1}; partial q_n.s';
-//                   x_1 = g0 s' (first overlap-solve iterate).  Slots at
-//                   n = 0 take s' = e_j instead (start vector B^{-1} e_j).
-//   PASS_STEP       one Richardson step of the overlap solve B v = s:
-//                   x_{k+1} = x_k + tau_k (s - B x_k)
-//   PASS_STEP_LAST  the last step, then the deferred Lanczos correction
-//                   v = x - alpha_n q_n, s = s' - alpha_n t_n, and partial
-//                   dots v.s and s.s (beta_n^2 and ||s||^2).
+//   PASS_LANCZOS_A  w = A q_n; s' = w - beta_{n-1} t_{n-1}; partial q_n.s'
+//                   (alpha_n).  Slots at n = 0 take s' = e_j instead (start
+//                   vector B^{-1} e_j).
+//   PASS_STEP_FIRST first Richardson step of the overlap solve B v = s with
+//                   s = s' - alpha_n t_n: the operand x_1 = g0 s is formed
+//                   from s' and t_n while gathering; s is stored for the
+//                   later steps.
+//   PASS_STEP       x_{k+1} = x_k + tau_k (s - B x_k)
+//   PASS_STEP_LAST  the last step, v = x_d, with partial dots v.s and s.s
+//                   (beta_n^2 and ||s||^2).
 //   PASS_PLAIN      y = X x.
 //
 // Mixed precision (FP32 matrix values, FP32 overlap-solve vectors, FP64
 // Lanczos vectors and scalars):
 //   PASS_LANCZOS_A_MX  as PASS_LANCZOS_A with FP32 values and FP64
-//                      accumulation; also writes s' and x_1 in FP32.
+//                      accumulation.
+//   PASS_STEP32_FIRST  as PASS_STEP_FIRST with an FP32 iterate; writes s in
+//                      FP64 and FP32.
 //   PASS_STEP32        FP32 Richardson step on FP32 vectors.
-//   PASS_REFINE        r = s' - B x with FP64 accumulation of the FP32
+//   PASS_REFINE        r = s - B x with FP64 accumulation of the FP32
 //                      first-round solution x; writes r and the first
 //                      correction iterate g0 r in FP32.
 //   PASS_STEP32_LAST   last FP32 correction step d, then v = x + d in FP64
-//                      and the deferred Lanczos correction as above.
+//                      and the partial dots v.s, s.s.
 //   PASS_PLAIN32       y = X x in FP32.
+//
+// The overlap solve always runs on s itself, so v = p(B) s for the fixed
+// Richardson polynomial p and the Lanczos vectors q = p(B) t stay consistent
+// to rounding at every step.
 //
 // Matrix values are identical for all lanes of a wave, so they are read
 // through the scalar unit; each lane streams its own right-hand side(s).
@@ -83,6 +91,12 @@ struct KindTypes<PASS_PLAIN32> {
     using TX = float;
     using TA = float;
 };
+template <>
+struct KindTypes<PASS_STEP32_FIRST> {
+    using TV = float;
+    using TX = double;
+    using TA = float;
+};
 
 template <int KIND>
 constexpr bool kVec32 = std::is_same_v<typename KindTypes<KIND>::TX, float>;
@@ -96,6 +110,8 @@ constexpr bool kHasDots = KIND == PASS_LANCZOS_A || KIND == PASS_STEP_LAST || KI
                           KIND == PASS_STEP32_LAST;
 template <int KIND>
 constexpr bool kHasD1 = KIND == PASS_STEP_LAST || KIND == PASS_STEP32_LAST;
+template <int KIND>
+constexpr bool kFirst = KIND == PASS_STEP_FIRST || KIND == PASS_STEP32_FIRST;
 
 __device__ __forceinline__ double fmac(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float fmac(float a, float b, float c) { return fmaf(a, b, c); }
@@ -256,6 +272,25 @@ struct GlobalSrc {
     }
 };
 
+// The first overlap-solve operand x_1 = g0 (s' - f t_n), formed from two
+// gathered FP64 rows (f = alpha_n / beta_{n-1} per column: t_n is stored
+// unnormalised).
+template <int CPL, typename TA>
+struct FirstSrc {
+    const double* __restrict__ Sp;
+    const double* __restrict__ T;
+    int ld, c0;
+    double g0;
+    double f[CPL];
+    __device__ __forceinline__ void get(int row, TA (&r)[CPL]) const {
+        double sp[CPL], t[CPL];
+        load_cols<CPL>(Sp, (size_t)row * ld + c0, sp);
+        load_cols<CPL>(T, (size_t)row * ld + c0, t);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) r[c] = static_cast<TA>(g0 * fma(-f[c], t[c], sp[c]));
+    }
+};
+
 // LDS tile [rows][64] doubles, one column per lane
 struct LdsSrc {
     const double* tile;
@@ -276,21 +311,58 @@ struct ColState {
     int n, r;
 };
 
+// Gather source of a pass kind.
+template <int KIND, int CPL>
+__device__ __forceinline__ auto make_src(const PassArgs& a, int c0, const ColState (&cs)[CPL]) {
+    using TA = typename KindTypes<KIND>::TA;
+    using TX = typename KindTypes<KIND>::TX;
+    if constexpr (kFirst<KIND>) {
+        FirstSrc<CPL, TA> src{a.S, a.Tn, a.ld, c0, a.g0, {}};
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) src.f[c] = cs[c].al * cs[c].A;
+        return src;
+    } else {
+        return GlobalSrc<CPL, TX, TA>{gather_src<KIND>(a), a.ld, c0};
+    }
+}
+
+// Region membership of (row, columns c0 .. c0+CPL-1); all set without a mask.
+template <int CPL>
+__device__ __forceinline__ void row_mask(const PassArgs& a, int row, int c0, bool (&in)[CPL]) {
+    if (a.mask) {
+        const uint64_t w = a.mask[(size_t)row * a.mask_words + (c0 >> 6)];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) in[c] = (w >> ((c0 & 63) + c)) & 1ull;
+    } else {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) in[c] = true;
+    }
+}
+
+template <int CPL, typename T>
+__device__ __forceinline__ void apply_mask(const bool (&in)[CPL], T (&v)[CPL]) {
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) v[c] = in[c] ? v[c] : T(0);
+}
+
 template <int KIND, int NI, int CPL, typename TA>
 __device__ __forceinline__ void epilogue(const PassArgs& a, int row, int c0, const TA (&acc)[NI][CPL], int arow,
                                          const ColState (&cs)[CPL], double (&d0)[CPL], double (&d1)[CPL]) {
     const size_t idx = (size_t)row * a.ld + c0;
+    bool in[CPL];
+    row_mask<CPL>(a, row, c0, in);
     if constexpr (KIND == PASS_PLAIN || KIND == PASS_PLAIN32) {
         TA y[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) y[c] = acc[arow][c];
+        apply_mask<CPL>(in, y);
         if constexpr (KIND == PASS_PLAIN)
             store_cols<CPL>(a.Xio, idx, y);
         else
             store_cols<CPL>(a.Xio32, idx, y);
     } else if constexpr (KIND == PASS_LANCZOS_A || KIND == PASS_LANCZOS_A_MX) {
         // cs.A = 1/beta_{n-1}, cs.B = beta_{n-1}/beta_{n-2}
-        double tp[CPL], vq[CPL], sp[CPL], x1[CPL];
+        double tp[CPL], vq[CPL], sp[CPL];
         load_cols<CPL>(a.S, idx, tp);
         load_cols<CPL>(a.Vq, idx, vq);
 #pragma unroll
@@ -298,23 +370,35 @@ __device__ __forceinline__ void epilogue(const PassArgs& a, int row, int c0, con
             if (cs[c].n == 0) {
                 sp[c] = (row == cs[c].r) ? 1.0 : 0.0;
             } else {
-                sp[c] = acc[arow][c] * cs[c].A - cs[c].B * tp[c];
+                sp[c] = in[c] ? acc[arow][c] * cs[c].A - cs[c].B * tp[c] : 0.0;
                 d0[c] = fma(vq[c] * cs[c].A, sp[c], d0[c]);
             }
-            x1[c] = a.g0 * sp[c];
         }
         store_cols<CPL>(a.S, idx, sp);
-        if constexpr (KIND == PASS_LANCZOS_A) {
-            store_cols<CPL>(a.Xio, idx, x1);
+    } else if constexpr (KIND == PASS_STEP_FIRST || KIND == PASS_STEP32_FIRST) {
+        // s = s' - alpha_n t_n on the own rows, then the first step from x_1 = g0 s
+        double sp[CPL], tn[CPL], sv[CPL];
+        load_cols<CPL>(a.S, idx, sp);
+        load_cols<CPL>(a.Tn, idx, tn);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) sv[c] = in[c] ? fma(-(cs[c].al * cs[c].A), tn[c], sp[c]) : 0.0;
+        store_cols<CPL>(a.Sout, idx, sv);
+        if constexpr (KIND == PASS_STEP_FIRST) {
+            double xn[CPL];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) xn[c] = in[c] ? a.g0 * sv[c] + a.tau * (sv[c] - acc[arow][c]) : 0.0;
+            store_cols<CPL>(a.Xio, idx, xn);
         } else {
-            float s32[CPL], x32[CPL];
+            float s32[CPL], xn[CPL];
+            const float tau = static_cast<float>(a.tau);
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                s32[c] = static_cast<float>(sp[c]);
-                x32[c] = static_cast<float>(x1[c]);
+                s32[c] = static_cast<float>(sv[c]);
+                const float x1 = static_cast<float>(a.g0 * sv[c]);
+                xn[c] = in[c] ? fmaf(tau, s32[c] - acc[arow][c], x1) : 0.0f;
             }
             store_cols<CPL>(a.R32o, idx, s32);
-            store_cols<CPL>(a.Xio32, idx, x32);
+            store_cols<CPL>(a.Xio32, idx, xn);
         }
     } else if constexpr (KIND == PASS_STEP || KIND == PASS_STEP_LAST) {
         double xk[CPL], s[CPL], xn[CPL];
@@ -322,24 +406,16 @@ __device__ __forceinline__ void epilogue(const PassArgs& a, int row, int c0, con
         load_cols<CPL>(a.S, idx, s);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) xn[c] = xk[c] + a.tau * (s[c] - acc[arow][c]);
+        apply_mask<CPL>(in, xn);
         if constexpr (KIND == PASS_STEP) {
             store_cols<CPL>(a.Xio, idx, xn);
         } else {
-            double vq[CPL], tn[CPL];
-            load_cols<CPL>(a.Vq, idx, vq);
-            load_cols<CPL>(a.Tn, idx, tn);
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                if (cs[c].n != 0) {
-                    const double f = cs[c].al * cs[c].A;
-                    xn[c] -= f * vq[c];
-                    s[c] -= f * tn[c];
-                }
                 d0[c] = fma(xn[c], s[c], d0[c]);
                 d1[c] = fma(s[c], s[c], d1[c]);
             }
             store_cols<CPL>(a.Xio, idx, xn);
-            store_cols<CPL>(a.S, idx, s);
         }
     } else if constexpr (KIND == PASS_REFINE) {
         double s[CPL];
@@ -347,7 +423,7 @@ __device__ __forceinline__ void epilogue(const PassArgs& a, int row, int c0, con
         load_cols<CPL>(a.S, idx, s);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            const double r = s[c] - acc[arow][c];
+            const double r = in[c] ? s[c] - acc[arow][c] : 0.0;
             r32[c] = static_cast<float>(r);
             x32[c] = static_cast<float>(a.g0 * r);
         }
@@ -361,28 +437,21 @@ __device__ __forceinline__ void epilogue(const PassArgs& a, int row, int c0, con
         const float tau = static_cast<float>(a.tau);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) xn[c] = fmaf(tau, r[c] - acc[arow][c], xk[c]);
+        apply_mask<CPL>(in, xn);
         if constexpr (KIND == PASS_STEP32) {
             store_cols<CPL>(a.Xio32, idx, xn);
         } else {
             float x1[CPL];
-            double vq[CPL], tn[CPL], s[CPL], v[CPL];
+            double s[CPL], v[CPL];
             load_cols<CPL>(a.Xr1, idx, x1);
-            load_cols<CPL>(a.Vq, idx, vq);
-            load_cols<CPL>(a.Tn, idx, tn);
             load_cols<CPL>(a.S, idx, s);
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                v[c] = static_cast<double>(x1[c]) + static_cast<double>(xn[c]);
-                if (cs[c].n != 0) {
-                    const double f = cs[c].al * cs[c].A;
-                    v[c] -= f * vq[c];
-                    s[c] -= f * tn[c];
-                }
+                v[c] = in[c] ? static_cast<double>(x1[c]) + static_cast<double>(xn[c]) : 0.0;
                 d0[c] = fma(v[c], s[c], d0[c]);
                 d1[c] = fma(s[c], s[c], d1[c]);
             }
             store_cols<CPL>(a.Xio, idx, v);
-            store_cols<CPL>(a.S, idx, s);
         }
     }
 }
@@ -392,12 +461,14 @@ __device__ __forceinline__ void load_colstate(const PassArgs& a, int c0, ColStat
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         cs[c] = {0.0, 0.0, 0.0, 0, -1};
-        if constexpr (kHasDots<KIND>) {
+        if constexpr (KIND == PASS_LANCZOS_A || KIND == PASS_LANCZOS_A_MX || kFirst<KIND>) {
             cs[c].A = a.inv_beta[c0 + c];
             cs[c].n = a.slot_n[c0 + c];
             cs[c].r = a.slot_row[c0 + c];
-            if constexpr (KIND == PASS_LANCZOS_A || KIND == PASS_LANCZOS_A_MX) cs[c].B = a.coefT[c0 + c];
-            if constexpr (kHasD1<KIND>) cs[c].al = a.alpha[c0 + c];
+            if constexpr (kFirst<KIND>)
+                cs[c].al = a.alpha[c0 + c];
+            else
+                cs[c].B = a.coefT[c0 + c];
         }
     }
 }
@@ -496,7 +567,7 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(PassArgs a, const int* __r
     double d0[CPL], d1[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) d0[c] = d1[c] = 0.0;
-    const GlobalSrc<CPL, TX, TA> src{gather_src<KIND>(a), a.ld, c0};
+    const auto src = make_src<KIND, CPL>(a, c0, cs);
     const int first = slab * a.atoms_per_slab;
     const int last = min(first + a.atoms_per_slab, a.n_atoms);  // empty for trailing slabs
     for (int I = first + wave; I < last; I += kWavesPerBlock) {
@@ -543,15 +614,20 @@ __global__ __launch_bounds__(NW* kWave) void pass_lds_kernel(PassArgs a, const i
         const int* __restrict__ ur = a.cl_urow + u0;
         // stage the union rows of this column tile (one 512-byte row per wave
         // step), issuing four row loads before their LDS stores
+        const auto gsrc = make_src<KIND, 1>(a, c0, cs);
         int u = wave;
         for (; u + 3 * NW < nu; u += 4 * NW) {
-            double t[4];
+            double t[4][1];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) t[j] = a.Xg[(size_t)ur[u + j * NW] * a.ld + c0];
+            for (int j = 0; j < 4; ++j) gsrc.get(ur[u + j * NW], t[j]);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) tile_x[(u + j * NW) * kWave + lane] = t[j];
+            for (int j = 0; j < 4; ++j) tile_x[(u + j * NW) * kWave + lane] = t[j][0];
         }
-        for (; u < nu; u += NW) tile_x[u * kWave + lane] = a.Xg[(size_t)ur[u] * a.ld + c0];
+        for (; u < nu; u += NW) {
+            double t[1];
+            gsrc.get(ur[u], t);
+            tile_x[u * kWave + lane] = t[0];
+        }
     }
     __syncthreads();
     const LdsSrc src{tile_x, lane};
@@ -612,15 +688,22 @@ __global__ __launch_bounds__(kBlock) void pass_group_kernel(PassArgs a, const in
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sub = wave % KS, gi = wave / KS;
-    const int c0 = tile * (kWave * CPL) + lane * CPL;
+    // c0: column of the vectors; sc: index of the per-slot state.  With
+    // region tiles the vectors hold one tile per row and the slab names the
+    // tile of its slot state.
+    int c0 = tile * (kWave * CPL) + lane * CPL, sc = c0;
+    if (a.slab_tile) {
+        c0 = lane * CPL;
+        sc = a.slab_tile[slab] * (kWave * CPL) + c0;
+    }
     ColState cs[CPL];
-    load_colstate<KIND, CPL>(a, c0, cs);
+    load_colstate<KIND, CPL>(a, sc, cs);
     double d0[CPL], d1[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) d0[c] = d1[c] = 0.0;
-    const GlobalSrc<CPL, TX, TA> src{gather_src<KIND>(a), a.ld, c0};
-    const int g = slab * GPW + gi;
-    const bool live = g < a.n_grp;
+    const auto src = make_src<KIND, CPL>(a, c0, cs);
+    const int g = a.slab_group ? a.slab_group[slab * GPW + gi] : slab * GPW + gi;
+    const bool live = a.slab_group ? g >= 0 : g < a.n_grp;
     int R = 0;
     TA* pw = part + (size_t)wave * kMaxGroupRows * kWave * CPL;
     if (live) {
@@ -722,6 +805,8 @@ void launch_pass(PassKind kind, const PassArgs& a, hipStream_t st) {
         case PASS_REFINE: launch_kind<PASS_REFINE>(a, st); break;
         case PASS_STEP32_LAST: launch_kind<PASS_STEP32_LAST>(a, st); break;
         case PASS_PLAIN32: launch_kind<PASS_PLAIN32>(a, st); break;
+        case PASS_STEP_FIRST: launch_kind<PASS_STEP_FIRST>(a, st); break;
+        case PASS_STEP32_FIRST: launch_kind<PASS_STEP32_FIRST>(a, st); break;
     }
 }
 
@@ -744,6 +829,37 @@ __global__ void col_reduce2_kernel(const double* __restrict__ tmp, int nb, int l
     for (int k = 0; k < nb; ++k) s += tmp[(size_t)k * ld + c];
     if (slot_n) s = (slot_n[c] == 0 || slot_row[c] < 0) ? 0.0 : s;
     out[c] = s;
+}
+
+__global__ void col_reduce_tiles1_kernel(const double* __restrict__ part, int L, const int* __restrict__ s0,
+                                         const int* __restrict__ s1, double* __restrict__ tmp) {
+    const int k = blockIdx.x;
+    for (int c = threadIdx.x; c < L; c += blockDim.x) {
+        double s = 0.0;
+        for (int q = s0[k]; q < s1[k]; ++q) s += part[(size_t)q * L + c];
+        tmp[(size_t)k * L + c] = s;
+    }
+}
+
+__global__ void col_reduce_tiles2_kernel(const double* __restrict__ tmp, int L, int n_slots,
+                                         const int* __restrict__ tile_chunk_off, const int* __restrict__ slot_n,
+                                         const int* __restrict__ slot_row, double* __restrict__ out) {
+    const int sidx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sidx >= n_slots) return;
+    const int t = sidx / L, c = sidx - t * L;
+    double s = 0.0;
+    for (int k = tile_chunk_off[t]; k < tile_chunk_off[t + 1]; ++k) s += tmp[(size_t)k * L + c];
+    if (slot_n) s = (slot_n[sidx] == 0 || slot_row[sidx] < 0) ? 0.0 : s;
+    out[sidx] = s;
+}
+
+void launch_col_reduce_tiles(const double* part, int L, int n_tiles, int n_chunks, const int* chunk_s0,
+                             const int* chunk_s1, const int* tile_chunk_off, double* tmp, const int* slot_n,
+                             const int* slot_row, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(col_reduce_tiles1_kernel, dim3(n_chunks), dim3(L), 0, st, part, L, chunk_s0, chunk_s1, tmp);
+    const int n_slots = n_tiles * L;
+    hipLaunchKernelGGL(col_reduce_tiles2_kernel, dim3((n_slots + 255) / 256), dim3(256), 0, st, tmp, L, n_slots,
+                       tile_chunk_off, slot_n, slot_row, out);
 }
 
 void launch_col_reduce(const double* part, int n_part, int ld, double* tmp, const int* slot_n, const int* slot_row,

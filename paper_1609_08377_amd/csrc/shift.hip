@@ -128,13 +128,14 @@ __global__ __launch_bounds__(kShiftThreads) void shift_update_kernel(ShiftArgs a
     const int len = a.full ? a.M : (int)(a.row_off[cidx + 1] - a.row_off[cidx]);
     const int* rows = a.full ? nullptr : a.rows + a.row_off[cidx];
     const double qs = a.inv_beta[slot];
+    const int vcol = slot % a.vld;
     double* xs = a.xs + (size_t)slot * K * a.rmax * 2;
     double* ps = a.ps + (size_t)slot * K * a.rmax * 2;
     for (int base = 0; base < len; base += kChunk) {
         const int cl = min(kChunk, len - base);
         for (int p = t; p < cl; p += kShiftThreads) {
-            const int row = rows ? rows[base + p] : base + p;
-            sq[p] = a.Vq[(size_t)row * a.ld + slot] * qs;
+            const int row = rows ? rows[base + p] : base + p;  // -1: outside the column's region
+            sq[p] = row >= 0 ? a.Vq[(size_t)row * a.vld + vcol] * qs : 0.0;
         }
         __syncthreads();
         const int tot = K * cl;
@@ -167,8 +168,12 @@ __global__ __launch_bounds__(kShiftThreads) void shift_update_kernel(ShiftArgs a
         __syncthreads();
     }
 
+    // Breakdown: beta_n^2 = v.s at the rounding level means the Krylov space
+    // is invariant (exhausted for a small problem); the current iterates are
+    // then exact for every shift and the column ends here.
+    const bool breakdown = !(vs > 0.0) || !(beta > 1e-13 * (fabs(alpha) + bprev));
     const bool exhausted = (n >= a.max_outer);
-    if (!done && !exhausted) {
+    if (!done && !exhausted && !breakdown) {
         if (t == 0) {
             a.beta_prev[slot] = beta;
             a.inv_beta[slot] = 1.0 / beta;
@@ -237,23 +242,21 @@ void launch_shift_update(const ShiftArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(shift_update_kernel, dim3(a.ld), dim3(kShiftThreads), 0, st, a);
 }
 
-// Slots 0..n_active-1 start columns 0..n_active-1; the rest are idle.
+// Slots 0..n_active-1 start columns 0..n_active-1 (or the columns of
+// slot_map); the rest are idle.
 __global__ void slot_init_kernel(ShiftArgs a, int n_active) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= a.ld) return;
-    if (s < n_active) {
-        a.slot_row[s] = a.cols[s];
-        a.slot_cidx[s] = s;
-    } else {
-        a.slot_row[s] = -1;
-        a.slot_cidx[s] = -1;
-    }
+    const int c = a.slot_map ? a.slot_map[s] : (s < n_active ? s : -1);
+    a.slot_row[s] = c >= 0 ? a.cols[c] : -1;
+    a.slot_cidx[s] = c;
     a.slot_n[s] = 0;
     a.inv_beta[s] = 0.0;
     a.coefT[s] = 0.0;
     a.beta_prev[s] = 0.0;
     if (s == 0) {
-        *a.queue = n_active;
+        // with an explicit slot map every column has its own slot: no refill
+        *a.queue = a.slot_map ? a.n_cols : n_active;
         *a.remaining = a.n_cols;
         *a.n_notconv = 0;
     }
