@@ -55,7 +55,12 @@ WORKLOADS = {
     "c2": (4096, 64, "4096-atom amorphous hydrocarbon box (C:H=1:2, 1.0 g/cm^3), M=8191 (4x4/4x1/1x1 atom "
                      "blocks, ~71 nnz/row), all 8191 columns x 64 shifts z=eps_k+0.01i on [-1,1] Ha, FP64, "
                      "tol 1e-8, global"),
+    "c3": (50000, 64, "2048 local regions (centre atoms sampled without replacement, radius U[6,14] A, "
+                      "187-3079 orbitals) carved from a 50000-atom amorphous hydrocarbon box (M=100001), all "
+                      "orbitals of each centre x 64 shifts, packed into tiles and advanced by one launch "
+                      "sequence, tol 1e-8"),
 }
+N_REGIONS = 2048
 
 
 def cpu_baseline(sysm, shifts, gpu_iters_mean: float, budget_s: float = 20.0):
@@ -127,7 +132,9 @@ def main():
     ap.add_argument("--batch", type=int, default=1024, help="columns per step")
     ap.add_argument("--cols", type=int, default=0, help="limit the column count (0 = all)")
     ap.add_argument("--slots", type=int, default=0)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="default: fp64 for c1/c2, mixed (FP32-stored A, B) for c3")
+    ap.add_argument("--tile", type=int, default=64, help="column slots per region tile (c3)")
     ap.add_argument("--copy-calib", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--variant", default="auto", choices=["auto", "direct", "staged8", "staged4", "grouped", "grouped2", "grouped1"])
     ap.add_argument("--no-cpu", action="store_true")
@@ -158,21 +165,44 @@ def main():
     if args.cols:
         all_cols = all_cols[:args.cols]
     batches = [all_cols[i:i + args.batch] for i in range(0, len(all_cols), args.batch)]
-    mixed = args.precision == "mixed"
+    region_mode = args.config == "c3"
+    precision = args.precision or ("mixed" if region_mode else "fp64")
+    mixed = precision == "mixed"
 
     ctx = el.Context(0)
-    mat = el.Matrix.from_system(ctx, sysm, precision=args.precision)
+    mat = el.Matrix.from_system(ctx, sysm, precision=precision)
     lib = el.lib()
     import ctypes
     lib.elses_ctx_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     lib.elses_ctx_pass_stats.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 6
 
-    def step(cols, max_outer=args.max_outer):
-        return el.density_matrix(ctx, mat, cols, z, cw, slots=args.slots, want_x=True, max_outer=max_outer,
-                                 allow_not_converged=max_outer < 20000, variant=args.variant, mixed=mixed)
+    extra = {}
+    if region_mode:
+        centres, radii = synth.sample_regions(sysm, N_REGIONS, seed)
+        t_plan = time.perf_counter()
+        reg = el.Regions(ctx, mat, centres, radii, args.tile)
+        extra = {"regions": int(centres.size), "region_tiles": reg.n_tiles, "tile_width": args.tile,
+                 "tile_rows_total": reg.rows_total,
+                 "useful_lane_fraction": round(reg.useful_rows / (reg.rows_total * args.tile), 4),
+                 "region_orbitals_min_mean_max": [int(reg.region_orbitals.min()),
+                                                  round(float(reg.region_orbitals.mean()), 1),
+                                                  int(reg.region_orbitals.max())],
+                 "region_set_build_s": round(time.perf_counter() - t_plan, 2)}
+        small = el.Regions(ctx, mat, centres[:8], radii[:8], args.tile)
+        batches = [reg.cols]
 
-    # load the kernels and touch the allocator outside the timed region
-    step(batches[0][:64], max_outer=16)
+        def step(cols, max_outer=args.max_outer, r=reg):
+            return el.region_solve(ctx, r, z, cw, want_x=True, max_outer=max_outer,
+                                   allow_not_converged=max_outer < 20000, variant=args.variant, mixed=mixed)
+
+        step(None, max_outer=16, r=small)
+    else:
+        def step(cols, max_outer=args.max_outer):
+            return el.density_matrix(ctx, mat, cols, z, cw, slots=args.slots, want_x=True, max_outer=max_outer,
+                                     allow_not_converged=max_outer < 20000, variant=args.variant, mixed=mixed)
+
+        # load the kernels and touch the allocator outside the timed region
+        step(batches[0][:64], max_outer=16)
     for w in range(args.warmup):
         print(f"warmup {w + 1}/{args.warmup}", file=sys.stderr, flush=True)
         step(batches[w % len(batches)])
@@ -204,7 +234,7 @@ def main():
     value = n_solves / dt
     iters = torch.cat(iters_all).cpu().numpy()
     achieved = nbytes.value / (avg_us.value * 1e-6) / 1e9 if avg_us.value > 0 else 0.0
-    tag = ("step32" if mixed else "step64") + f"_{args.config}_{slots.value}"
+    tag = ("step32" if mixed else "step64") + f"_{args.config}_{args.tile if region_mode else slots.value}"
     traffic = committed_traffic(tag) if args.variant == "auto" else None
     kernel = ("pass_group_kernel<PASS_STEP32> (FP32 B SpMM + Richardson step)" if mixed else
               "pass_group_kernel<PASS_STEP> (FP64 B SpMM + Richardson step)")
@@ -218,16 +248,21 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32/f64 mixed" if mixed else "f64", "data": "synthetic",
-        "config": {"workload": args.config + ": " + desc + (" [mixed precision: FP32-stored A, B]" if mixed else ""),
+        "config": {"workload": args.config + ": " + desc + (" [mixed precision: FP32-stored A, B]" if mixed else
+                                                             " [FP64]"),
                    "n_atoms": n_atoms, "M": int(sysm.M), "columns_per_step": args.batch,
                    "batches_in_job": len(batches), "columns_timed": int(n_solves // K), "shifts": K, "tol": 1e-8,
                    "slots": slots.value, "outer_iters_mean": float(iters.mean()),
                    "outer_iters_max": int(iters.max()), "max_resid_estimate": resid_max,
                    "trace_rhoB_timed_columns": trace_b, "passes_per_step": int(total.value // max(args.steps, 1)),
-                   "gflops_timed_pass": round(flops.value / (avg_us.value * 1e-6) / 1e9, 1) if avg_us.value else 0},
+                   "gflops_timed_pass": round(flops.value / (avg_us.value * 1e-6) / 1e9, 1) if avg_us.value else 0,
+                   **extra},
         "roofline": roof,
     }
-    if not args.no_cpu:
+    if region_mode:
+        res["config"].pop("columns_per_step", None)
+        res["config"]["batches_in_job"] = 1
+    if not args.no_cpu and not region_mode:
         print("timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(sysm, z, float(iters.mean()), args.cpu_budget)
     print(json.dumps(res), flush=True)
