@@ -245,6 +245,66 @@ elses_status elses_regions_solve(elses_ctx ctx, elses_regions reg, int32_t n_shi
                                  double *traces_out, double *col_traces_out, int32_t *iters_out,
                                  double *resid_out);
 
+/*
+ * Learned block sparse approximate inverse (SPAI) of the overlap B.
+ *
+ * The overlap solves B v = s of the method (paper Sec. III-B: B^{-1} enters
+ * every step of the generalized problem) can be preconditioned by an
+ * approximate inverse M on B's own block pattern.  A multilayer perceptron
+ * predicts the blocks M_IJ of the upper pairs I <= J (M_JI = M_IJ^T) from
+ * per-pair features; it is trained on the exact blocks of B^{-1}, which the
+ * overlap solve itself computes for small systems.
+ *
+ * Pairs: the upper pairs (I <= J) of the block pattern, atom row by atom
+ * row, ascending J.  Features (FP32 [n_pairs][40]): displacement r_J - r_I
+ * over 4 A (3), its length over 4 A, 4-orbital flags of I and J, 10 B_IJ
+ * zero-padded to 4 x 4 (16), 10 (E^2)_IJ with E = B - I zero-padded (16),
+ * 1 if I == J, 0.  Network: 40 -> 128 -> 128 -> 128 -> 16, exact GELU after
+ * the hidden layers, output the 4 x 4 block (valid part n_I x n_J).
+ * Parameters: ELSES_MLP_PARAMS FP32 values W1[128][40] b1[128] W2[128][128]
+ * b2[128] W3[128][128] b3[128] W4[16][128] b4[16] (DEVICE, caller-owned).
+ * Targets (FP32 [n_pairs][16]) with their valid-entry mask (1 / 0).
+ * Loss: sum over valid entries of (output - target)^2 / number of valid
+ * entries.
+ */
+#define ELSES_MLP_PARAMS 40336
+/* Number of upper pairs; pairs (HOST int32 [n][2], may be NULL) receives (I, J). */
+elses_status elses_spai_pairs(elses_mat mat, int64_t *n_pairs, int32_t *pairs);
+/* feat (DEVICE float [n_pairs][40]); needs atom positions. */
+elses_status elses_spai_features(elses_ctx ctx, elses_mat mat, float *feat);
+/* Exact blocks (B^{-1})_IJ from overlap solves of all unit vectors (to
+ * 1e-13), target and mask (DEVICE float [n_pairs][16]); for M <= 65536. */
+elses_status elses_spai_targets(elses_ctx ctx, elses_mat mat, float *target, float *mask);
+/* Loss (HOST) and its gradient (DEVICE float [ELSES_MLP_PARAMS]) over n rows
+ * of features / targets / masks (DEVICE), FP32 forward and backward passes. */
+elses_status elses_mlp_loss_grad(elses_ctx ctx, const float *params, int64_t n, const float *feat,
+                                 const float *target, const float *mask, double *loss, float *grad);
+/* `steps` Adam steps (lr, beta 0.9 / 0.999, eps 1e-8) on mini-batches of
+ * `batch` rows drawn by seeded shuffles; params (DEVICE) updated in place;
+ * loss_history (HOST double [steps], may be NULL) receives each batch loss. */
+elses_status elses_spai_train(elses_ctx ctx, float *params, int64_t n, const float *feat, const float *target,
+                              const float *mask, int32_t steps, int32_t batch, double lr, uint64_t seed,
+                              double *loss_history);
+/* Network outputs (DEVICE float [n][16]) for n feature rows; bf16 != 0: BF16
+ * weights and activations (round to nearest even) with FP32 accumulation and
+ * FP32 biases; otherwise FP32 throughout. */
+elses_status elses_spai_predict(elses_ctx ctx, const float *params, int64_t n, const float *feat, int32_t bf16,
+                                float *out);
+/* M on B's pattern: features, inference and assembly (diagonal blocks
+ * symmetrised).  M_vals (DEVICE double, as many values as B) is in the
+ * library's internal block order: an opaque buffer for elses_overlap_solve. */
+elses_status elses_spai_apply(elses_ctx ctx, elses_mat mat, const float *params, int32_t bf16, double *M_vals);
+/* Overlap solve x = p(B) s for nvec right-hand sides (DEVICE double
+ * [M][nvec], nvec a multiple of 64) to relative residual tol by Richardson
+ * steps with Chebyshev roots.  With M_vals (from elses_spai_apply) the steps
+ * are x_{k+1} = x_k + tau_k M (s - B x_k) on the spectral interval of M B
+ * (estimated by Lanczos); if M is not SPD the plain iteration is used.
+ * passes_out receives the number of sparse passes, bracket_out (HOST [2])
+ * the interval used, used_precond 1 if M was used. */
+elses_status elses_overlap_solve(elses_ctx ctx, elses_mat mat, const double *M_vals, double tol, int32_t nvec,
+                                 const double *s, double *x, int32_t *passes_out, double *bracket_out,
+                                 int32_t *used_precond);
+
 /* FP32 products with the FP32 copies of a matrix created with ELSES_MIXED:
  * y = fl32(X) x with FP32 accumulation, X = A (which=0) or B (which=1);
  * x, y DEVICE float [M][nvec], nvec a positive multiple of 64; `variant` as

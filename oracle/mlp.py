@@ -191,3 +191,22 @@ def assemble(sysm, P: np.ndarray, out: np.ndarray) -> np.ndarray:
             M[oI:oI + nI, oJ:oJ + nJ] = blk
             M[oJ:oJ + nJ, oI:oI + nI] = blk.T
     return M
+
+
+def bf16(x):
+    """Round to bfloat16 (round to nearest, ties to even), returned as FP64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(theta, X):
+    """Inference with bfloat16 weights, inputs and hidden activations, FP64
+    accumulation (the reference of a BF16 / FP32-accumulate kernel) and
+    unrounded biases."""
+    W1, b1, W2, b2, W3, b3, W4, b4 = unpack(np.asarray(theta, dtype=np.float64))
+    h = bf16(X)
+    for W, b in ((W1, b1), (W2, b2), (W3, b3)):
+        h = bf16(gelu(h @ bf16(W).T + b))
+    return h @ bf16(W4).T + b4

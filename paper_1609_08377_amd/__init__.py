@@ -96,6 +96,17 @@ def lib():
         L.elses_spmm.restype = ctypes.c_int
         L.elses_spmm32.argtypes = [P, P, ctypes.c_int, I32, I32, P, P]
         L.elses_spmm32.restype = ctypes.c_int
+        L.elses_spai_pairs.argtypes = [P, P, P]
+        L.elses_spai_features.argtypes = [P, P, P]
+        L.elses_spai_targets.argtypes = [P, P, P, P]
+        L.elses_mlp_loss_grad.argtypes = [P, P, ctypes.c_int64, P, P, P, P, P]
+        L.elses_spai_train.argtypes = [P, P, ctypes.c_int64, P, P, P, I32, I32, ctypes.c_double, ctypes.c_uint64, P]
+        L.elses_spai_predict.argtypes = [P, P, ctypes.c_int64, P, I32, P]
+        L.elses_spai_apply.argtypes = [P, P, P, I32, P]
+        L.elses_overlap_solve.argtypes = [P, P, P, ctypes.c_double, I32, P, P, P, P, P]
+        for fn in ("elses_spai_pairs", "elses_spai_features", "elses_spai_targets", "elses_mlp_loss_grad",
+                   "elses_spai_train", "elses_spai_predict", "elses_spai_apply", "elses_overlap_solve"):
+            getattr(L, fn).restype = ctypes.c_int
         L.elses_regions_create.argtypes = [P, P, I32, P, P, I32, ctypes.POINTER(P)]
         L.elses_regions_create.restype = ctypes.c_int
         L.elses_regions_destroy.argtypes = [P]
@@ -190,6 +201,7 @@ class Matrix:
         hi = ctypes.c_double()
         lib().elses_mat_info(h, ctypes.byref(M), ctypes.byref(pmax), ctypes.byref(lo), ctypes.byref(hi))
         self.M = int(M.value)
+        self.nnz = int(av.shape[0])  # values of A (and B): every block n_I x n_J
         self.pmax = int(pmax.value)
         self.b_interval = (lo.value, hi.value)
         self._keep = None
@@ -402,3 +414,81 @@ def region_solve(ctx: Context, reg: Regions, shifts, c=None, *, tol=1e-8, max_ou
                 traces=traces if cw is not None else None,
                 col_traces=None if col_tr is None else col_tr.view(nc, 2), iters=iters, resid=resid.view(nc, K),
                 pat_off=reg.pat_off, cols=reg.cols, status=st)
+
+
+# ---------------------------------------------------------------------------
+# Learned SPAI of the overlap
+# ---------------------------------------------------------------------------
+MLP_PARAMS = 40336
+
+
+def spai_pairs(mat: Matrix) -> np.ndarray:
+    n = ctypes.c_int64()
+    lib().elses_spai_pairs(mat._h, ctypes.byref(n), None)
+    out = np.zeros((n.value, 2), dtype=np.int32)
+    lib().elses_spai_pairs(mat._h, ctypes.byref(n), _np_ptr(out))
+    return out
+
+
+def spai_features(ctx: Context, mat: Matrix):
+    torch = _torch()
+    n = spai_pairs(mat).shape[0]
+    f = torch.empty((n, 40), dtype=torch.float32, device=torch.device("cuda", ctx.device))
+    ctx.check(lib().elses_spai_features(ctx._h, mat._h, _dev_ptr(f)))
+    return f
+
+
+def spai_targets(ctx: Context, mat: Matrix):
+    torch = _torch()
+    n = spai_pairs(mat).shape[0]
+    dev = torch.device("cuda", ctx.device)
+    t = torch.zeros((n, 16), dtype=torch.float32, device=dev)
+    m = torch.zeros((n, 16), dtype=torch.float32, device=dev)
+    ctx.check(lib().elses_spai_targets(ctx._h, mat._h, _dev_ptr(t), _dev_ptr(m)))
+    return t, m
+
+
+def mlp_loss_grad(ctx: Context, params, feat, target, mask):
+    torch = _torch()
+    g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=params.device)
+    loss = ctypes.c_double()
+    ctx.check(lib().elses_mlp_loss_grad(ctx._h, _dev_ptr(params), feat.shape[0], _dev_ptr(feat), _dev_ptr(target),
+                                        _dev_ptr(mask), ctypes.byref(loss), _dev_ptr(g)))
+    return loss.value, g
+
+
+def spai_train(ctx: Context, params, feat, target, mask, steps: int, batch: int = 4096, lr: float = 1e-3,
+               seed: int = 0):
+    hist = np.zeros(steps)
+    ctx.check(lib().elses_spai_train(ctx._h, _dev_ptr(params), feat.shape[0], _dev_ptr(feat), _dev_ptr(target),
+                                     _dev_ptr(mask), steps, batch, lr, seed, _np_ptr(hist)))
+    return hist
+
+
+def spai_predict(ctx: Context, params, feat, bf16: bool = False):
+    torch = _torch()
+    out = torch.empty((feat.shape[0], 16), dtype=torch.float32, device=feat.device)
+    ctx.check(lib().elses_spai_predict(ctx._h, _dev_ptr(params), feat.shape[0], _dev_ptr(feat), 1 if bf16 else 0,
+                                       _dev_ptr(out)))
+    return out
+
+
+def spai_apply(ctx: Context, mat: Matrix, params, bf16: bool = True):
+    """Device buffer of M on B's pattern (opaque internal order) for overlap_solve."""
+    torch = _torch()
+    n = mat.nnz
+    mv = torch.zeros(n, dtype=torch.float64, device=params.device)
+    ctx.check(lib().elses_spai_apply(ctx._h, mat._h, _dev_ptr(params), 1 if bf16 else 0, _dev_ptr(mv)))
+    return mv
+
+
+def overlap_solve(ctx: Context, mat: Matrix, s, M_vals=None, tol: float = 1e-13):
+    """x = B^{-1} s for s a float64 (M, nvec) device tensor; returns (x, passes, bracket, used_precond)."""
+    torch = _torch()
+    s = s.contiguous()
+    x = torch.empty_like(s)
+    passes, used = ctypes.c_int32(), ctypes.c_int32()
+    br = np.zeros(2)
+    ctx.check(lib().elses_overlap_solve(ctx._h, mat._h, _dev_ptr(M_vals), tol, s.shape[1], _dev_ptr(s), _dev_ptr(x),
+                                        ctypes.byref(passes), _np_ptr(br), ctypes.byref(used)))
+    return x, passes.value, tuple(br), bool(used.value)

@@ -1718,3 +1718,504 @@ elses_status elses_spmm(elses_ctx ctx, elses_mat mat, int which, int32_t variant
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned block SPAI of the overlap and the preconditioned overlap solve
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kMlpIn = 40, kMlpHid = 128, kMlpOut = 16;
+constexpr int64_t kOffW1 = 0, kOffb1 = kOffW1 + kMlpHid * kMlpIn, kOffW2 = kOffb1 + kMlpHid,
+                  kOffb2 = kOffW2 + kMlpHid * kMlpHid, kOffW3 = kOffb2 + kMlpHid,
+                  kOffb3 = kOffW3 + kMlpHid * kMlpHid, kOffW4 = kOffb3 + kMlpHid,
+                  kOffb4 = kOffW4 + kMlpOut * kMlpHid, kMlpParams = kOffb4 + kMlpOut;
+
+// Upper pairs (I <= J) of the block pattern with the ascending indices of the
+// blocks (I, J) and (J, I).
+struct PairList {
+    std::vector<int> I, J, b, bt;
+};
+
+PairList make_pairs(const HostMatrix& h) {
+    PairList P;
+    for (int I = 0; I < h.n_atoms; ++I)
+        for (int b = h.brow[I]; b < h.brow[I + 1]; ++b) {
+            const int J = h.bcol[b];
+            if (J < I) continue;
+            const int* beg = h.bcol.data() + h.brow[J];
+            const int* end = h.bcol.data() + h.brow[J + 1];
+            const int bt = (int)(std::lower_bound(beg, end, I) - h.bcol.data());
+            P.I.push_back(I);
+            P.J.push_back(J);
+            P.b.push_back(b);
+            P.bt.push_back(bt);
+        }
+    return P;
+}
+
+struct DevPairs {
+    int64_t n = 0;
+    int *I = nullptr, *J = nullptr, *b = nullptr, *bt = nullptr;
+};
+
+DevPairs upload_pairs(DevPool& pool, const PairList& P, hipStream_t st) {
+    DevPairs D;
+    D.n = (int64_t)P.I.size();
+    D.I = pool.get<int>(D.n);
+    D.J = pool.get<int>(D.n);
+    D.b = pool.get<int>(D.n);
+    D.bt = pool.get<int>(D.n);
+    HCHECK(hipMemcpyAsync(D.I, P.I.data(), sizeof(int) * D.n, hipMemcpyHostToDevice, st));
+    HCHECK(hipMemcpyAsync(D.J, P.J.data(), sizeof(int) * D.n, hipMemcpyHostToDevice, st));
+    HCHECK(hipMemcpyAsync(D.b, P.b.data(), sizeof(int) * D.n, hipMemcpyHostToDevice, st));
+    HCHECK(hipMemcpyAsync(D.bt, P.bt.data(), sizeof(int) * D.n, hipMemcpyHostToDevice, st));
+    return D;
+}
+
+void spai_features_dev(elses_mat mat, DevPool& pool, const DevPairs& D, float* feat, hipStream_t st) {
+    const HostMatrix& h = mat->h;
+    int* bcol = pool.get<int>(h.bcol.size());
+    double* pos = pool.get<double>(h.pos.size());
+    HCHECK(hipMemcpyAsync(bcol, h.bcol.data(), sizeof(int) * h.bcol.size(), hipMemcpyHostToDevice, st));
+    HCHECK(hipMemcpyAsync(pos, h.pos.data(), sizeof(double) * h.pos.size(), hipMemcpyHostToDevice, st));
+    launch_spai_features(D.n, D.I, D.J, D.b, mat->d, bcol, pos, h.box, feat, st);
+}
+
+// Workspace of one forward / backward pass over n rows.
+struct MlpWork {
+    float *Z1, *H1, *Z2, *H2, *Z3, *H3, *out, *gout, *G1, *G2, *G3;
+    double *part, *loss;
+    float* scale;
+};
+
+MlpWork mlp_work(DevPool& pool, int64_t n) {
+    MlpWork w{};
+    const size_t nh = (size_t)n * kMlpHid, no = (size_t)n * kMlpOut;
+    w.Z1 = pool.get<float>(nh);
+    w.H1 = pool.get<float>(nh);
+    w.Z2 = pool.get<float>(nh);
+    w.H2 = pool.get<float>(nh);
+    w.Z3 = pool.get<float>(nh);
+    w.H3 = pool.get<float>(nh);
+    w.G1 = pool.get<float>(nh);
+    w.G2 = pool.get<float>(nh);
+    w.G3 = pool.get<float>(nh);
+    w.out = pool.get<float>(no);
+    w.gout = pool.get<float>(no);
+    w.part = pool.get<double>(2 * 64);
+    w.loss = pool.get<double>(1);
+    w.scale = pool.get<float>(1);
+    return w;
+}
+
+void mlp_forward(const float* th, int64_t n, const float* X, MlpWork& w, hipStream_t st) {
+    const int N = (int)n;
+    launch_gemm(N, kMlpHid, kMlpIn, X, kMlpIn, 1, th + kOffW1, 1, kMlpIn, w.Z1, kMlpHid, false, st);
+    launch_bias_act(n, kMlpHid, w.Z1, th + kOffb1, w.H1, true, st);
+    launch_gemm(N, kMlpHid, kMlpHid, w.H1, kMlpHid, 1, th + kOffW2, 1, kMlpHid, w.Z2, kMlpHid, false, st);
+    launch_bias_act(n, kMlpHid, w.Z2, th + kOffb2, w.H2, true, st);
+    launch_gemm(N, kMlpHid, kMlpHid, w.H2, kMlpHid, 1, th + kOffW3, 1, kMlpHid, w.Z3, kMlpHid, false, st);
+    launch_bias_act(n, kMlpHid, w.Z3, th + kOffb3, w.H3, true, st);
+    launch_gemm(N, kMlpOut, kMlpHid, w.H3, kMlpHid, 1, th + kOffW4, 1, kMlpHid, w.out, kMlpOut, false, st);
+    launch_bias_act(n, kMlpOut, w.out, th + kOffb4, w.out, false, st);
+}
+
+// loss (device scalar) and gradient g of the masked mean squared error
+void mlp_loss_grad(const float* th, int64_t n, const float* X, const float* T, const float* W, MlpWork& w, float* g,
+                   hipStream_t st) {
+    const int N = (int)n;
+    mlp_forward(th, n, X, w, st);
+    launch_loss(n * kMlpOut, w.out, T, W, w.gout, w.part, w.loss, w.scale, st);
+    // layer 4
+    launch_gemm(kMlpOut, kMlpHid, N, w.gout, 1, kMlpOut, w.H3, kMlpHid, 1, g + kOffW4, kMlpHid, false, st);
+    launch_colsum(n, kMlpOut, w.gout, g + kOffb4, st);
+    launch_gemm(N, kMlpHid, kMlpOut, w.gout, kMlpOut, 1, th + kOffW4, kMlpHid, 1, w.G3, kMlpHid, false, st);
+    launch_gelu_back(n * kMlpHid, w.Z3, w.G3, st);
+    // layer 3
+    launch_gemm(kMlpHid, kMlpHid, N, w.G3, 1, kMlpHid, w.H2, kMlpHid, 1, g + kOffW3, kMlpHid, false, st);
+    launch_colsum(n, kMlpHid, w.G3, g + kOffb3, st);
+    launch_gemm(N, kMlpHid, kMlpHid, w.G3, kMlpHid, 1, th + kOffW3, kMlpHid, 1, w.G2, kMlpHid, false, st);
+    launch_gelu_back(n * kMlpHid, w.Z2, w.G2, st);
+    // layer 2
+    launch_gemm(kMlpHid, kMlpHid, N, w.G2, 1, kMlpHid, w.H1, kMlpHid, 1, g + kOffW2, kMlpHid, false, st);
+    launch_colsum(n, kMlpHid, w.G2, g + kOffb2, st);
+    launch_gemm(N, kMlpHid, kMlpHid, w.G2, kMlpHid, 1, th + kOffW2, kMlpHid, 1, w.G1, kMlpHid, false, st);
+    launch_gelu_back(n * kMlpHid, w.Z1, w.G1, st);
+    // layer 1
+    launch_gemm(kMlpHid, kMlpIn, N, w.G1, 1, kMlpHid, X, kMlpIn, 1, g + kOffW1, kMlpIn, false, st);
+    launch_colsum(n, kMlpHid, w.G1, g + kOffb1, st);
+}
+
+elses_status hip_err(elses_ctx ctx, const HipFail& f) {
+    const elses_status s = (f.e == hipErrorOutOfMemory) ? ELSES_ERR_OOM : ELSES_ERR_HIP;
+    return set_err(ctx, s, std::string(f.what) + ": " + hipGetErrorString(f.e));
+}
+
+// x = p(B) s by the Richardson steps of `rich` from x_0 = 0 (direct passes).
+// Returns the buffer holding x (xa or xb).
+double* richardson_solve(const DevMatrix& d, const Rich& rich, int nvec, const double* s, double* xa, double* xb,
+                         double* zero, hipStream_t st) {
+    PassArgs pa{};
+    configure_pass(d, 1, nvec, pa);
+    pa.vals = d.B;
+    pa.S = const_cast<double*>(s);
+    pa.Xg = zero;
+    pa.Xio = xa;
+    pa.tau = rich.g0;
+    launch_pass(PASS_STEP, pa, st);
+    double* cur = xa;
+    double* oth = xb;
+    for (int k = 1; k < rich.d; ++k) {
+        pa.Xg = cur;
+        pa.Xio = oth;
+        pa.tau = rich.tau[k - 1];
+        launch_pass(PASS_STEP, pa, st);
+        std::swap(cur, oth);
+    }
+    return cur;
+}
+
+}  // namespace
+
+extern "C" {
+
+elses_status elses_spai_pairs(elses_mat mat, int64_t* n_pairs, int32_t* pairs) {
+    if (!mat || !n_pairs) return ELSES_ERR_INVALID_ARG;
+    const PairList P = make_pairs(mat->h);
+    *n_pairs = (int64_t)P.I.size();
+    if (pairs)
+        for (size_t p = 0; p < P.I.size(); ++p) {
+            pairs[2 * p] = P.I[p];
+            pairs[2 * p + 1] = P.J[p];
+        }
+    return ELSES_OK;
+}
+
+elses_status elses_spai_features(elses_ctx ctx, elses_mat mat, float* feat) {
+    if (!ctx || !mat || !feat) return ELSES_ERR_INVALID_ARG;
+    if (mat->h.pos.empty()) return set_err(ctx, ELSES_ERR_INVALID_ARG, "features need atom positions");
+    hipStream_t st = ctx->stream;
+    try {
+        HCHECK(hipSetDevice(ctx->device));
+        DevPool pool;
+        const DevPairs D = upload_pairs(pool, make_pairs(mat->h), st);
+        spai_features_dev(mat, pool, D, feat, st);
+        HCHECK(hipGetLastError());
+        HCHECK(hipStreamSynchronize(st));
+    } catch (const HipFail& f) {
+        return hip_err(ctx, f);
+    }
+    return ELSES_OK;
+}
+
+elses_status elses_spai_targets(elses_ctx ctx, elses_mat mat, float* target, float* mask) {
+    if (!ctx || !mat || !target || !mask) return ELSES_ERR_INVALID_ARG;
+    const HostMatrix& h = mat->h;
+    const DevMatrix& d = mat->d;
+    if (h.M > 65536) return set_err(ctx, ELSES_ERR_INVALID_ARG, "exact-inverse targets are for small systems");
+    hipStream_t st = ctx->stream;
+    try {
+        HCHECK(hipSetDevice(ctx->device));
+        DevPool pool;
+        const DevPairs D = upload_pairs(pool, make_pairs(h), st);
+        const Rich rich = richardson_plan(mat->b_lo, mat->b_hi, 1e-13);
+        constexpr int kChunk = 1024;
+        const size_t vsz = (size_t)h.M * kChunk;
+        double* S = pool.get<double>(vsz);
+        double* Xa = pool.get<double>(vsz);
+        double* Xb = pool.get<double>(vsz);
+        double* Z = pool.get<double>(vsz);
+        HCHECK(hipMemsetAsync(Z, 0, sizeof(double) * vsz, st));
+        // column chunks that end on atom boundaries
+        int c0 = 0;
+        while (c0 < h.M) {
+            int c1 = c0;
+            for (int I = 0; I < h.n_atoms; ++I)
+                if (h.atom_off[I + 1] <= c0 + kChunk && h.atom_off[I + 1] > c1) c1 = h.atom_off[I + 1];
+            const int ld = ((c1 - c0 + 63) / 64) * 64;
+            launch_eye(h.M, ld, c0, S, st);
+            double* X = richardson_solve(d, rich, ld, S, Xa, Xb, Z, st);
+            launch_spai_targets(D.n, D.I, D.J, d.atom_off, X, ld, c0, target, mask, st);
+            c0 = c1;
+        }
+        HCHECK(hipGetLastError());
+        HCHECK(hipStreamSynchronize(st));
+    } catch (const HipFail& f) {
+        return hip_err(ctx, f);
+    }
+    return ELSES_OK;
+}
+
+elses_status elses_mlp_loss_grad(elses_ctx ctx, const float* params, int64_t n, const float* feat,
+                                 const float* target, const float* mask, double* loss, float* grad) {
+    if (!ctx || !params || !feat || !target || !mask || !grad || n < 1 || n > (1 << 22))
+        return ELSES_ERR_INVALID_ARG;
+    hipStream_t st = ctx->stream;
+    try {
+        HCHECK(hipSetDevice(ctx->device));
+        DevPool pool;
+        MlpWork w = mlp_work(pool, n);
+        mlp_loss_grad(params, n, feat, target, mask, w, grad, st);
+        double l = 0.0;
+        HCHECK(hipMemcpyAsync(&l, w.loss, sizeof(double), hipMemcpyDeviceToHost, st));
+        HCHECK(hipGetLastError());
+        HCHECK(hipStreamSynchronize(st));
+        if (loss) *loss = l;
+    } catch (const HipFail& f) {
+        return hip_err(ctx, f);
+    }
+    return ELSES_OK;
+}
+
+elses_status elses_spai_train(elses_ctx ctx, float* params, int64_t n, const float* feat, const float* target,
+                              const float* mask, int32_t steps, int32_t batch, double lr, uint64_t seed,
+                              double* loss_history) {
+    if (!ctx || !params || !feat || !target || !mask || n < 1 || steps < 1 || batch < 1 || !(lr > 0.0))
+        return ELSES_ERR_INVALID_ARG;
+    hipStream_t st = ctx->stream;
+    const int bs = (int)std::min<int64_t>(batch, n);
+    try {
+        HCHECK(hipSetDevice(ctx->device));
+        DevPool pool;
+        MlpWork w = mlp_work(pool, bs);
+        float* g = pool.get<float>(kMlpParams);
+        float* m = pool.get<float>(kMlpParams);
+        float* v = pool.get<float>(kMlpParams);
+        HCHECK(hipMemsetAsync(m, 0, sizeof(float) * kMlpParams, st));
+        HCHECK(hipMemsetAsync(v, 0, sizeof(float) * kMlpParams, st));
+        float* Xb = pool.get<float>((size_t)bs * kMlpIn);
+        float* Tb = pool.get<float>((size_t)bs * kMlpOut);
+        float* Wb = pool.get<float>((size_t)bs * kMlpOut);
+        int* idx = pool.get<int>(bs);
+        double* hist = pool.get<double>(steps);
+        // seeded shuffles of the rows, one per epoch (splitmix64 + Fisher-Yates)
+        std::vector<int> perm(n);
+        for (int64_t i = 0; i < n; ++i) perm[i] = (int)i;
+        uint64_t x = seed;
+        auto next = [&]() {
+            uint64_t z = (x += 0x9E3779B97F4A7C15ULL);
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+            return z ^ (z >> 31);
+        };
+        int64_t pos = n;
+        std::vector<int> hidx(bs);
+        for (int t = 0; t < steps; ++t) {
+            for (int i = 0; i < bs; ++i) {
+                if (pos >= n) {
+                    for (int64_t k = n - 1; k > 0; --k) std::swap(perm[k], perm[next() % (uint64_t)(k + 1)]);
+                    pos = 0;
+                }
+                hidx[i] = perm[pos++];
+            }
+            HCHECK(hipMemcpyAsync(idx, hidx.data(), sizeof(int) * bs, hipMemcpyHostToDevice, st));
+            launch_gather_rows(bs, kMlpIn, idx, feat, Xb, st);
+            launch_gather_rows(bs, kMlpOut, idx, target, Tb, st);
+            launch_gather_rows(bs, kMlpOut, idx, mask, Wb, st);
+            mlp_loss_grad(params, bs, Xb, Tb, Wb, w, g, st);
+            HCHECK(hipMemcpyAsync(hist + t, w.loss, sizeof(double), hipMemcpyDeviceToDevice, st));
+            launch_adam(kMlpParams, params, g, m, v, (float)lr, t + 1, st);
+            // the host batch buffer is reused: wait for its upload
+            HCHECK(hipStreamSynchronize(st));
+        }
+        if (loss_history)
+            HCHECK(hipMemcpyAsync(loss_history, hist, sizeof(double) * steps, hipMemcpyDeviceToHost, st));
+        HCHECK(hipGetLastError());
+        HCHECK(hipStreamSynchronize(st));
+    } catch (const HipFail& f) {
+        return hip_err(ctx, f);
+    }
+    return ELSES_OK;
+}
+
+elses_status elses_spai_predict(elses_ctx ctx, const float* params, int64_t n, const float* feat, int32_t bf16,
+                                float* out) {
+    if (!ctx || !params || !feat || !out || n < 0) return ELSES_ERR_INVALID_ARG;
+    if (n == 0) return ELSES_OK;
+    hipStream_t st = ctx->stream;
+    try {
+        HCHECK(hipSetDevice(ctx->device));
+        DevPool pool;
+        if (bf16) {
+            uint16_t* wb = pool.get<uint16_t>(kMlpParams);
+            launch_to_bf16(kMlpParams, params, wb, st);
+            launch_infer_bf16(n, wb, params, feat, out, st);
+        } else {
+            MlpWork w = mlp_work(pool, n);
+            mlp_forward(params, n, feat, w, st);
+            HCHECK(hipMemcpyAsync(out, w.out, sizeof(float) * n * kMlpOut, hipMemcpyDeviceToDevice, st));
+        }
+        HCHECK(hipGetLastError());
+        HCHECK(hipStreamSynchronize(st));
+    } catch (const HipFail& f) {
+        return hip_err(ctx, f);
+    }
+    return ELSES_OK;
+}
+
+elses_status elses_spai_apply(elses_ctx ctx, elses_mat mat, const float* params, int32_t bf16, double* M_vals) {
+    if (!ctx || !mat || !params || !M_vals) return ELSES_ERR_INVALID_ARG;
+    if (mat->h.pos.empty()) return set_err(ctx, ELSES_ERR_INVALID_ARG, "features need atom positions");
+    hipStream_t st = ctx->stream;
+    try {
+        HCHECK(hipSetDevice(ctx->device));
+        DevPool pool;
+        const DevPairs D = upload_pairs(pool, make_pairs(mat->h), st);
+        float* feat = pool.get<float>((size_t)D.n * kMlpIn);
+        float* out = pool.get<float>((size_t)D.n * kMlpOut);
+        spai_features_dev(mat, pool, D, feat, st);
+        if (bf16) {
+            uint16_t* wb = pool.get<uint16_t>(kMlpParams);
+            launch_to_bf16(kMlpParams, params, wb, st);
+            launch_infer_bf16(D.n, wb, params, feat, out, st);
+        } else {
+            constexpr int64_t kRows = 65536;  // forward in slices to bound the workspace
+            MlpWork w = mlp_work(pool, std::min<int64_t>(kRows, D.n));
+            for (int64_t p0 = 0; p0 < D.n; p0 += kRows) {
+                const int64_t nn = std::min<int64_t>(kRows, D.n - p0);
+                mlp_forward(params, nn, feat + p0 * kMlpIn, w, st);
+                HCHECK(hipMemcpyAsync(out + p0 * kMlpOut, w.out, sizeof(float) * nn * kMlpOut,
+                                      hipMemcpyDeviceToDevice, st));
+            }
+        }
+        launch_spai_assemble(D.n, D.I, D.J, D.b, D.bt, mat->d, out, M_vals, st);
+        HCHECK(hipGetLastError());
+        HCHECK(hipStreamSynchronize(st));
+    } catch (const HipFail& f) {
+        return hip_err(ctx, f);
+    }
+    return ELSES_OK;
+}
+
+elses_status elses_overlap_solve(elses_ctx ctx, elses_mat mat, const double* M_vals, double tol, int32_t nvec,
+                                 const double* s, double* x, int32_t* passes_out, double* bracket_out,
+                                 int32_t* used_precond) {
+    if (!ctx || !mat || !s || !x) return ELSES_ERR_INVALID_ARG;
+    if (nvec < 64 || nvec % 64 != 0) return set_err(ctx, ELSES_ERR_INVALID_ARG, "nvec must be a multiple of 64");
+    if (!(tol > 0.0 && tol < 1.0)) return set_err(ctx, ELSES_ERR_INVALID_ARG, "tol must be in (0, 1)");
+    const DevMatrix& d = mat->d;
+    const int M = d.M;
+    hipStream_t st = ctx->stream;
+    try {
+        HCHECK(hipSetDevice(ctx->device));
+        DevPool pool;
+        double lo = mat->b_lo, hi = mat->b_hi;
+        bool pre = M_vals != nullptr;
+        if (pre) {
+            // spectral interval of M B: Lanczos in the B inner product (M B is
+            // self-adjoint there); M B has positive spectrum iff M is SPD
+            double* v = pool.get<double>(M);
+            double* u = pool.get<double>(M);
+            double* vp = pool.get<double>(M);
+            double* w = pool.get<double>(M);
+            double* uw = pool.get<double>(M);
+            double* junk = pool.get<double>(M);
+            const int nbl = std::min(256, (M + 255) / 256);
+            double* part = pool.get<double>(nbl);
+            std::vector<double> hv(M), hp(nbl);
+            uint64_t r = 0x9E3779B97F4A7C15ULL;
+            for (int i = 0; i < M; ++i) {
+                r ^= r << 13;
+                r ^= r >> 7;
+                r ^= r << 17;
+                hv[i] = (double)(r >> 11) / 9007199254740992.0 - 0.5;
+            }
+            auto dotdev = [&](const double* a, const double* b) {
+                launch_dot_partial(a, b, M, part, nbl, st);
+                HCHECK(hipMemcpyAsync(hp.data(), part, sizeof(double) * nbl, hipMemcpyDeviceToHost, st));
+                HCHECK(hipStreamSynchronize(st));
+                double t = 0;
+                for (double q : hp) t += q;
+                return t;
+            };
+            HCHECK(hipMemcpyAsync(v, hv.data(), sizeof(double) * M, hipMemcpyHostToDevice, st));
+            HCHECK(hipMemsetAsync(vp, 0, sizeof(double) * M, st));
+            launch_spmm_generic(d, d.B, 1, 1, v, u, st);
+            const double n0 = std::sqrt(dotdev(v, u));
+            launch_lanczos_shift(junk, v, v, 1.0 / n0, M, st);
+            launch_lanczos_shift(junk, u, u, 1.0 / n0, M, st);
+            std::vector<double> ta, tb;
+            double bprev = 0.0;
+            const int steps = std::min(M, 60);
+            for (int k = 0; k < steps; ++k) {
+                launch_spmm_generic(d, M_vals, 1, 1, u, w, st);  // w = M B v
+                const double al = dotdev(u, w);
+                launch_lanczos_orth(w, v, vp, al, bprev, M, st);
+                launch_spmm_generic(d, d.B, 1, 1, w, uw, st);
+                const double bb2 = dotdev(w, uw);
+                ta.push_back(al);
+                if (k + 1 == steps || !(bb2 > 1e-24 * al * al)) break;
+                const double bb = std::sqrt(bb2);
+                tb.push_back(bb);
+                launch_lanczos_shift(vp, v, w, 1.0 / bb, M, st);
+                launch_lanczos_shift(junk, u, uw, 1.0 / bb, M, st);
+                bprev = bb;
+            }
+            tb.resize(ta.size() - 1);
+            const double tmin = tri_eig(ta, tb, 0), tmax = tri_eig(ta, tb, (int)ta.size() - 1);
+            const double width = tmax - tmin;
+            lo = tmin - 0.02 * width - 1e-3 * std::fabs(tmin);
+            hi = tmax + 0.02 * width + 1e-3 * std::fabs(tmax);
+            if (!(lo > 0.0) || !std::isfinite(hi)) {
+                pre = false;  // M is not SPD: fall back to the plain overlap solve
+                lo = mat->b_lo;
+                hi = mat->b_hi;
+            }
+        }
+        if (bracket_out) {
+            bracket_out[0] = lo;
+            bracket_out[1] = hi;
+        }
+        const Rich rich = richardson_plan(lo, hi, tol);
+        const size_t vsz = (size_t)M * nvec;
+        double* Z = pool.get<double>(vsz);
+        double* Xa = pool.get<double>(vsz);
+        double* Xb = pool.get<double>(vsz);
+        HCHECK(hipMemsetAsync(Z, 0, sizeof(double) * vsz, st));
+        double* res = nullptr;
+        int passes = 0;
+        if (!pre) {
+            res = richardson_solve(d, rich, nvec, s, Xa, Xb, Z, st);
+            passes = rich.d;
+        } else {
+            double* R = pool.get<double>(vsz);
+            PassArgs pa{};
+            configure_pass(d, 1, nvec, pa);
+            // x_1 = g0 M s
+            pa.vals = M_vals;
+            pa.Xg = const_cast<double*>(s);
+            pa.S = Z;
+            pa.Xio = Xa;
+            pa.tau = rich.g0;
+            launch_pass(PASS_PSTEP, pa, st);
+            double* cur = Xa;
+            double* oth = Xb;
+            for (int k = 1; k < rich.d; ++k) {
+                pa.vals = d.B;  // r = s - B x_k
+                pa.Xg = cur;
+                pa.S = const_cast<double*>(s);
+                pa.Xio = R;
+                launch_pass(PASS_RESID, pa, st);
+                pa.vals = M_vals;  // x_{k+1} = x_k + tau_k M r
+                pa.Xg = R;
+                pa.S = cur;
+                pa.Xio = oth;
+                pa.tau = rich.tau[k - 1];
+                launch_pass(PASS_PSTEP, pa, st);
+                std::swap(cur, oth);
+            }
+            res = cur;
+            passes = 2 * rich.d - 1;
+        }
+        HCHECK(hipMemcpyAsync(x, res, sizeof(double) * vsz, hipMemcpyDeviceToDevice, st));
+        HCHECK(hipGetLastError());
+        HCHECK(hipStreamSynchronize(st));
+        if (passes_out) *passes_out = passes;
+        if (used_precond) *used_precond = pre ? 1 : 0;
+    } catch (const HipFail& f) {
+        return hip_err(ctx, f);
+    }
+    return ELSES_OK;
+}
+
+}  // extern "C"

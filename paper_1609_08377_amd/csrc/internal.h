@@ -130,9 +130,12 @@ enum PassKind {
     PASS_STEP32_LAST = 7,   // last FP32 correction step, v = x + d, partial v.s and s.s
     PASS_PLAIN32 = 8,       // y = X x in FP32 (diagnostics)
     PASS_STEP_FIRST = 9,    // s = s' - alpha_n t_n, x_1 = g0 s formed while gathering; first step
-    PASS_STEP32_FIRST = 10  // the same with an FP32 iterate; also writes s in FP32
+    PASS_STEP32_FIRST = 10, // the same with an FP32 iterate; also writes s in FP32
+    // preconditioned overlap solve x_{k+1} = x_k + tau M (s - B x_k)
+    PASS_RESID = 11,        // r = s - B x  (S: s, gathered: x, out: r)
+    PASS_PSTEP = 12         // x_{k+1} = x_k + tau M r  (S: x_k, gathered: r, values: M)
 };
-constexpr int kPassKinds = 11;
+constexpr int kPassKinds = 13;
 
 struct PassArgs {
     // matrix
@@ -270,5 +273,27 @@ void launch_sum_pairs(const double *v, int n, double *out2, hipStream_t st);
 
 // Partial dot products (deterministic two-stage): out[b] = sum over block b
 void launch_dot_partial(const double *a, const double *b, int n, double *part, int nblocks, hipStream_t st);
+
+// Learned SPAI (spai.hip): features, exact-inverse targets, FP32 training,
+// BF16 inference, assembly of M on B's pattern.
+void launch_spai_features(int64_t n, const int *pI, const int *pJ, const int *pb, const DevMatrix &d,
+                          const int *bcol, const double *pos, double box, float *feat, hipStream_t st);
+void launch_eye(int M, int ld, int c0, double *S, hipStream_t st);
+void launch_spai_targets(int64_t n, const int *pI, const int *pJ, const int *atom_off, const double *X, int ld,
+                         int c0, float *target, float *mask, hipStream_t st);
+void launch_gemm(int Mr, int N, int K, const float *A, int64_t sa0, int64_t sa1, const float *B, int64_t sb0,
+                 int64_t sb1, float *C, int64_t sc0, bool acc, hipStream_t st);
+void launch_bias_act(int64_t rows, int N, float *Z, const float *b, float *H, bool act, hipStream_t st);
+void launch_gelu_back(int64_t n, const float *Z, float *G, hipStream_t st);
+void launch_colsum(int64_t rows, int N, const float *G, float *db, hipStream_t st);
+void launch_loss(int64_t n, const float *out, const float *T, const float *W, float *gout, double *part,
+                 double *loss, float *scale, hipStream_t st);
+void launch_adam(int64_t n, float *th, const float *g, float *m, float *v, float lr, int t, hipStream_t st);
+void launch_gather_rows(int n, int F, const int *idx, const float *src, float *dst, hipStream_t st);
+void launch_to_bf16(int64_t n, const float *x, uint16_t *y, hipStream_t st);
+void launch_infer_bf16(int64_t n, const uint16_t *Wbf, const float *params, const float *feat, float *out,
+                       hipStream_t st);
+void launch_spai_assemble(int64_t n, const int *pI, const int *pJ, const int *pb, const int *pbt,
+                          const DevMatrix &d, const float *out, double *Mv, hipStream_t st);
 
 }  // namespace elses

@@ -417,6 +417,13 @@ __device__ __forceinline__ void epilogue(const PassArgs& a, int row, int c0, con
             }
             store_cols<CPL>(a.Xio, idx, xn);
         }
+    } else if constexpr (KIND == PASS_RESID || KIND == PASS_PSTEP) {
+        double sv[CPL], y[CPL];
+        load_cols<CPL>(a.S, idx, sv);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) y[c] = KIND == PASS_RESID ? sv[c] - acc[arow][c] : sv[c] + a.tau * acc[arow][c];
+        apply_mask<CPL>(in, y);
+        store_cols<CPL>(a.Xio, idx, y);
     } else if constexpr (KIND == PASS_REFINE) {
         double s[CPL];
         float r32[CPL], x32[CPL];
@@ -807,6 +814,8 @@ void launch_pass(PassKind kind, const PassArgs& a, hipStream_t st) {
         case PASS_PLAIN32: launch_kind<PASS_PLAIN32>(a, st); break;
         case PASS_STEP_FIRST: launch_kind<PASS_STEP_FIRST>(a, st); break;
         case PASS_STEP32_FIRST: launch_kind<PASS_STEP32_FIRST>(a, st); break;
+        case PASS_RESID: launch_kind<PASS_RESID>(a, st); break;
+        case PASS_PSTEP: launch_kind<PASS_PSTEP>(a, st); break;
     }
 }
 

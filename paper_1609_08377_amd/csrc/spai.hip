@@ -1,0 +1,441 @@
+// Learned block sparse approximate inverse of the overlap (gfx950 kernels).
+//
+// A small multilayer perceptron maps features of an atom pair (I, J) of B's
+// block pattern to the block M_IJ of an approximate inverse M ~ B^{-1}; the
+// preconditioned overlap solve then iterates x_{k+1} = x_k + tau_k M (s - B x_k).
+//
+// Features of a pair (I <= J), F = 40: displacement r_J - r_I / 4 A (3), its
+// length / 4 A, 4-orbital flags of I and J, 10 B_IJ (4 x 4 zero-padded),
+// 10 (E^2)_IJ with E = B - I (4 x 4), 1 if I == J, 0.
+// Network: 40 -> 128 -> 128 -> 128 -> 16 with the exact GELU x Phi(x) after
+// the hidden layers; parameters flat FP32: W1[128][40] b1 W2[128][128] b2
+// W3[128][128] b3 W4[16][128] b4.
+#include <math.h>
+
+#include "internal.h"
+
+namespace elses {
+
+// ---------------------------------------------------------------------------
+// Features, targets
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int find_block(const int* __restrict__ bcol, int b0, int b1, int J) {
+    while (b0 < b1) {
+        const int m = (b0 + b1) >> 1;
+        if (bcol[m] < J)
+            b0 = m + 1;
+        else
+            b1 = m;
+    }
+    return b0;
+}
+
+__global__ void spai_features_kernel(int64_t n, const int* __restrict__ pI, const int* __restrict__ pJ,
+                                     const int* __restrict__ pb, const int* __restrict__ atom_off,
+                                     const int* __restrict__ brow, const int* __restrict__ bcol,
+                                     const int64_t* __restrict__ asc_voff, const double* __restrict__ Bv,
+                                     const double* __restrict__ pos, double box, float* __restrict__ feat) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int I = pI[p], J = pJ[p];
+    const int nI = atom_off[I + 1] - atom_off[I], nJ = atom_off[J + 1] - atom_off[J];
+    float* f = feat + p * 40;
+    double d[3];
+    double r2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        double t = pos[3 * J + c] - pos[3 * I + c];
+        if (box > 0.0) t -= box * nearbyint(t / box);
+        d[c] = t;
+        r2 += t * t;
+    }
+    for (int c = 0; c < 3; ++c) f[c] = (float)(d[c] / 4.0);
+    f[3] = (float)(sqrt(r2) / 4.0);
+    f[4] = nI == 4 ? 1.f : 0.f;
+    f[5] = nJ == 4 ? 1.f : 0.f;
+    const double* bij = Bv + asc_voff[pb[p]];
+    for (int e = 0; e < 16; ++e) {
+        const int a = e >> 2, c = e & 3;
+        f[6 + e] = (a < nI && c < nJ) ? (float)(10.0 * bij[a * nJ + c]) : 0.f;
+    }
+    // (E^2)_IJ = sum_K E_IK E_KJ over the atoms K coupled to I (and to J)
+    double e2[4][4] = {};
+    for (int bk = brow[I]; bk < brow[I + 1]; ++bk) {
+        const int K = bcol[bk];
+        const int b2 = find_block(bcol, brow[K], brow[K + 1], J);
+        if (b2 >= brow[K + 1] || bcol[b2] != J) continue;
+        const int nK = atom_off[K + 1] - atom_off[K];
+        const double* eik = Bv + asc_voff[bk];
+        const double* ekj = Bv + asc_voff[b2];
+        for (int a = 0; a < nI; ++a)
+            for (int m = 0; m < nK; ++m) {
+                const double x = eik[a * nK + m] - ((K == I && a == m) ? 1.0 : 0.0);
+                if (x == 0.0) continue;
+                for (int c = 0; c < nJ; ++c) e2[a][c] += x * (ekj[m * nJ + c] - ((K == J && m == c) ? 1.0 : 0.0));
+            }
+    }
+    for (int e = 0; e < 16; ++e) {
+        const int a = e >> 2, c = e & 3;
+        f[22 + e] = (a < nI && c < nJ) ? (float)(10.0 * e2[a][c]) : 0.f;
+    }
+    f[38] = I == J ? 1.f : 0.f;
+    f[39] = 0.f;
+}
+
+void launch_spai_features(int64_t n, const int* pI, const int* pJ, const int* pb, const DevMatrix& d,
+                          const int* bcol, const double* pos, double box, float* feat, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(spai_features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, pI, pJ, pb,
+                       d.atom_off, d.brow, bcol, d.asc_voff, d.B, pos, box, feat);
+}
+
+__global__ void eye_kernel(int M, int ld, int c0, double* __restrict__ S) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)M * ld) return;
+    const int r = (int)(i / ld), c = (int)(i - (int64_t)r * ld);
+    S[i] = (r == c0 + c) ? 1.0 : 0.0;
+}
+
+void launch_eye(int M, int ld, int c0, double* S, hipStream_t st) {
+    const int64_t n = (int64_t)M * ld;
+    hipLaunchKernelGGL(eye_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, M, ld, c0, S);
+}
+
+// target[p] = (B^{-1})_IJ for the pairs whose columns J's orbitals lie in
+// [c0, c0 + ld) of X = B^{-1} [:, c0 : c0 + ld]  ([M][ld])
+__global__ void spai_targets_kernel(int64_t n, const int* __restrict__ pI, const int* __restrict__ pJ,
+                                    const int* __restrict__ atom_off, const double* __restrict__ X, int ld, int c0,
+                                    float* __restrict__ target, float* __restrict__ mask) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int I = pI[p], J = pJ[p];
+    const int oI = atom_off[I], oJ = atom_off[J];
+    const int nI = atom_off[I + 1] - oI, nJ = atom_off[J + 1] - oJ;
+    if (oJ < c0 || oJ + nJ > c0 + ld) return;
+    for (int e = 0; e < 16; ++e) {
+        const int a = e >> 2, c = e & 3;
+        const bool ok = a < nI && c < nJ;
+        target[p * 16 + e] = ok ? (float)X[(size_t)(oI + a) * ld + (oJ + c - c0)] : 0.f;
+        mask[p * 16 + e] = ok ? 1.f : 0.f;
+    }
+}
+
+void launch_spai_targets(int64_t n, const int* pI, const int* pJ, const int* atom_off, const double* X, int ld,
+                         int c0, float* target, float* mask, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(spai_targets_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, pI, pJ,
+                       atom_off, X, ld, c0, target, mask);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 training kernels
+// ---------------------------------------------------------------------------
+
+// C(i, j) (=, or += when acc) sum_k A(i, k) B(k, j) with A(i, k) = A[i sa0 + k sa1],
+// B(k, j) = B[k sb0 + j sb1], C(i, j) = C[i sc0 + j].  64 x 64 tiles, K in steps
+// of 16 through LDS, 4 x 4 outputs per thread.
+__global__ __launch_bounds__(256) void gemm_kernel(int Mr, int N, int K, const float* __restrict__ A, int64_t sa0,
+                                                   int64_t sa1, const float* __restrict__ B, int64_t sb0,
+                                                   int64_t sb1, float* __restrict__ C, int64_t sc0, int acc) {
+    __shared__ float As[16][68];
+    __shared__ float Bs[16][68];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    float r[4][4] = {};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+            const int ii = e >> 4, kk = e & 15;
+            const int gi = i0 + ii, gk = k0 + kk;
+            As[kk][ii] = (gi < Mr && gk < K) ? A[gi * sa0 + gk * sa1] : 0.f;
+        }
+        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+            const int kk = e >> 6, jj = e & 63;
+            const int gk = k0 + kk, gj = j0 + jj;
+            Bs[kk][jj] = (gk < K && gj < N) ? B[gk * sb0 + gj * sb1] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            float a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = As[kk][ty * 4 + q];
+                b[q] = Bs[kk][tx * 4 + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int w = 0; w < 4; ++w) r[q][w] = fmaf(a[q], b[w], r[q][w]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int gi = i0 + ty * 4 + q;
+        if (gi >= Mr) continue;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int gj = j0 + tx * 4 + w;
+            if (gj >= N) continue;
+            float* c = C + gi * sc0 + gj;
+            *c = acc ? *c + r[q][w] : r[q][w];
+        }
+    }
+}
+
+void launch_gemm(int Mr, int N, int K, const float* A, int64_t sa0, int64_t sa1, const float* B, int64_t sb0,
+                 int64_t sb1, float* C, int64_t sc0, bool acc, hipStream_t st) {
+    if (Mr <= 0 || N <= 0) return;
+    hipLaunchKernelGGL(gemm_kernel, dim3((N + 63) / 64, (Mr + 63) / 64), dim3(256), 0, st, Mr, N, K, A, sa0, sa1, B,
+                       sb0, sb1, C, sc0, acc ? 1 : 0);
+}
+
+__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_df(float x) {
+    return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// Z[i][j] += b[j]; H = act ? gelu(Z) : Z
+__global__ void bias_act_kernel(int64_t rows, int N, float* __restrict__ Z, const float* __restrict__ b,
+                                float* __restrict__ H, int act) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * N) return;
+    const float z = Z[e] + b[e % N];
+    Z[e] = z;
+    H[e] = act ? gelu_f(z) : z;
+}
+
+void launch_bias_act(int64_t rows, int N, float* Z, const float* b, float* H, bool act, hipStream_t st) {
+    const int64_t n = rows * N;
+    if (n == 0) return;
+    hipLaunchKernelGGL(bias_act_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rows, N, Z, b, H,
+                       act ? 1 : 0);
+}
+
+__global__ void gelu_back_kernel(int64_t n, const float* __restrict__ Z, float* __restrict__ G) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) G[e] *= gelu_df(Z[e]);
+}
+
+void launch_gelu_back(int64_t n, const float* Z, float* G, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(gelu_back_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, Z, G);
+}
+
+// db[j] = sum_i G[i][j] (one thread per column, rows in order)
+__global__ void colsum_kernel(int64_t rows, int N, const float* __restrict__ G, float* __restrict__ db) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    float s = 0.f;
+    for (int64_t i = 0; i < rows; ++i) s += G[i * N + j];
+    db[j] = s;
+}
+
+void launch_colsum(int64_t rows, int N, const float* G, float* db, hipStream_t st) {
+    hipLaunchKernelGGL(colsum_kernel, dim3((N + 127) / 128), dim3(128), 0, st, rows, N, G, db);
+}
+
+// r = (out - T) W; partial sums of r^2 and W per block; gout = r (scaled later)
+__global__ __launch_bounds__(256) void loss_partial_kernel(int64_t n, const float* __restrict__ out,
+                                                           const float* __restrict__ T,
+                                                           const float* __restrict__ W, float* __restrict__ gout,
+                                                           double* __restrict__ part) {
+    __shared__ double s1[256], s2[256];
+    double a = 0.0, w = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const float r = (out[e] - T[e]) * W[e];
+        gout[e] = r;
+        a += (double)r * r;
+        w += W[e];
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = w;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            s1[threadIdx.x] += s1[threadIdx.x + o];
+            s2[threadIdx.x] += s2[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s1[0];
+        part[2 * blockIdx.x + 1] = s2[0];
+    }
+}
+
+// loss = sum r^2 / sum W; scale[0] = 2 / sum W (factor of the output gradient)
+__global__ void loss_final_kernel(int nb, const double* __restrict__ part, double* __restrict__ loss,
+                                  float* __restrict__ scale) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a = 0.0, w = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        a += part[2 * b];
+        w += part[2 * b + 1];
+    }
+    *loss = w > 0.0 ? a / w : 0.0;
+    *scale = w > 0.0 ? (float)(2.0 / w) : 0.f;
+}
+
+__global__ void scale_kernel(int64_t n, const float* __restrict__ scale, float* __restrict__ g) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) g[e] *= *scale;
+}
+
+constexpr int kLossBlocks = 64;
+
+void launch_loss(int64_t n, const float* out, const float* T, const float* W, float* gout, double* part,
+                 double* loss, float* scale, hipStream_t st) {
+    hipLaunchKernelGGL(loss_partial_kernel, dim3(kLossBlocks), dim3(256), 0, st, n, out, T, W, gout, part);
+    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, st, kLossBlocks, part, loss, scale);
+    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, scale, gout);
+}
+
+__global__ void adam_kernel(int64_t n, float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float gg = g[e];
+    const float mm = b1 * m[e] + (1.f - b1) * gg;
+    const float vv = b2 * v[e] + (1.f - b2) * gg * gg;
+    m[e] = mm;
+    v[e] = vv;
+    th[e] -= lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+}
+
+void launch_adam(int64_t n, float* th, const float* g, float* m, float* v, float lr, int t, hipStream_t st) {
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f / (1.f - powf(b1, (float)t)), c2 = 1.f / (1.f - powf(b2, (float)t));
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, th, g, m, v, lr, b1, b2,
+                       1e-8f, c1, c2);
+}
+
+__global__ void gather_rows_kernel(int n, int F, const int* __restrict__ idx, const float* __restrict__ src,
+                                   float* __restrict__ dst) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * F) return;
+    const int i = (int)(e / F), f = (int)(e - (int64_t)i * F);
+    dst[e] = src[(int64_t)idx[i] * F + f];
+}
+
+void launch_gather_rows(int n, int F, const int* idx, const float* src, float* dst, hipStream_t st) {
+    const int64_t t = (int64_t)n * F;
+    if (t == 0) return;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, n, F, idx, src, dst);
+}
+
+// ---------------------------------------------------------------------------
+// BF16 inference: weights and activations rounded to bfloat16 (round to
+// nearest even), products accumulated in FP32, FP32 biases.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float bf16_round(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xFFFF0000u);
+}
+
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__global__ void to_bf16_kernel(int64_t n, const float* __restrict__ x, uint16_t* __restrict__ y) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) y[e] = (uint16_t)(__float_as_uint(bf16_round(x[e])) >> 16);
+}
+
+void launch_to_bf16(int64_t n, const float* x, uint16_t* y, hipStream_t st) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, y);
+}
+
+// One workgroup of 256 threads infers 64 pairs: activations in LDS, thread
+// (o, half) accumulates output neuron o for 32 pairs.
+__global__ __launch_bounds__(256) void infer_bf16_kernel(int64_t n, const uint16_t* __restrict__ W1,
+                                                         const float* __restrict__ b1,
+                                                         const uint16_t* __restrict__ W2,
+                                                         const float* __restrict__ b2,
+                                                         const uint16_t* __restrict__ W3,
+                                                         const float* __restrict__ b3,
+                                                         const uint16_t* __restrict__ W4,
+                                                         const float* __restrict__ b4,
+                                                         const float* __restrict__ feat, float* __restrict__ out) {
+    __shared__ float h[2][64][128];
+    const int64_t p0 = (int64_t)blockIdx.x * 64;
+    const int o = threadIdx.x & 127, half = threadIdx.x >> 7;
+    for (int e = threadIdx.x; e < 64 * 40; e += 256) {
+        const int pp = e / 40, f = e - pp * 40;
+        h[0][pp][f] = (p0 + pp < n) ? bf16_round(feat[(p0 + pp) * 40 + f]) : 0.f;
+    }
+    __syncthreads();
+    const uint16_t* Ws[4] = {W1, W2, W3, W4};
+    const float* bs[4] = {b1, b2, b3, b4};
+    const int nin[4] = {40, 128, 128, 128};
+    const int nout[4] = {128, 128, 128, 16};
+    int cur = 0;
+    for (int l = 0; l < 4; ++l) {
+        if (o < nout[l]) {
+            float acc[32];
+#pragma unroll
+            for (int q = 0; q < 32; ++q) acc[q] = 0.f;
+            const uint16_t* w = Ws[l] + (size_t)o * nin[l];
+            for (int i = 0; i < nin[l]; ++i) {
+                const float wi = bf16_to_f(w[i]);
+#pragma unroll
+                for (int q = 0; q < 32; ++q) acc[q] = fmaf(wi, h[cur][half * 32 + q][i], acc[q]);
+            }
+            const float bb = bs[l][o];
+#pragma unroll
+            for (int q = 0; q < 32; ++q) {
+                const float z = acc[q] + bb;
+                if (l < 3) {
+                    h[cur ^ 1][half * 32 + q][o] = bf16_round(gelu_f(z));
+                } else {
+                    const int64_t p = p0 + half * 32 + q;
+                    if (p < n) out[p * 16 + o] = z;
+                }
+            }
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+}
+
+void launch_infer_bf16(int64_t n, const uint16_t* Wbf, const float* params, const float* feat, float* out,
+                       hipStream_t st) {
+    if (n == 0) return;
+    // offsets of the flat parameter layout
+    const size_t oW1 = 0, ob1 = oW1 + 128 * 40, oW2 = ob1 + 128, ob2 = oW2 + 128 * 128, oW3 = ob2 + 128,
+                 ob3 = oW3 + 128 * 128, oW4 = ob3 + 128, ob4 = oW4 + 16 * 128;
+    hipLaunchKernelGGL(infer_bf16_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, n, Wbf + oW1,
+                       params + ob1, Wbf + oW2, params + ob2, Wbf + oW3, params + ob3, Wbf + oW4, params + ob4, feat,
+                       out);
+}
+
+// Assemble M on B's pattern (internal layout, FP64) from the upper-pair blocks:
+// M_IJ = out_p (valid part), M_JI = M_IJ^T, diagonal blocks symmetrised.
+__global__ void spai_assemble_kernel(int64_t n, const int* __restrict__ pI, const int* __restrict__ pJ,
+                                     const int* __restrict__ pb, const int* __restrict__ pbt,
+                                     const int* __restrict__ atom_off, const int64_t* __restrict__ asc_voff,
+                                     const float* __restrict__ out, double* __restrict__ Mv) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int I = pI[p], J = pJ[p];
+    const int nI = atom_off[I + 1] - atom_off[I], nJ = atom_off[J + 1] - atom_off[J];
+    const float* o = out + p * 16;
+    double* mij = Mv + asc_voff[pb[p]];
+    double* mji = Mv + asc_voff[pbt[p]];
+    for (int a = 0; a < nI; ++a)
+        for (int c = 0; c < nJ; ++c) {
+            double v = o[a * 4 + c];
+            if (I == J) v = 0.5 * (v + (double)o[c * 4 + a]);
+            mij[a * nJ + c] = v;
+            if (I != J) mji[c * nI + a] = v;
+        }
+}
+
+void launch_spai_assemble(int64_t n, const int* pI, const int* pJ, const int* pb, const int* pbt,
+                          const DevMatrix& d, const float* out, double* Mv, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(spai_assemble_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, pI, pJ, pb, pbt,
+                       d.atom_off, d.asc_voff, out, Mv);
+}
+
+}  // namespace elses

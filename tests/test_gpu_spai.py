@@ -1,0 +1,145 @@
+"""Learned block SPAI of the overlap through the C ABI, against the CPU FP64 reference (oracle/mlp.py).
+
+Parity: features, exact-inverse targets, the MLP loss and gradient (FP32
+kernels vs FP64 backpropagation) and inference (FP32, and BF16 with FP32
+accumulation).  Effect (parity unpinned: training is not unique): training
+lowers the loss, the learned M is SPD and narrows the spectral interval of
+the overlap iteration, and the preconditioned overlap solve gives the same
+answer as the plain one.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def el():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1609_08377_amd as el
+    el.lib()
+    return el
+
+
+@pytest.fixture(scope="module")
+def ctx(el):
+    return el.Context(0)
+
+
+@pytest.fixture(scope="module")
+def small(el, ctx):
+    s = synth.make_system(64, 2024, r_cut=3.5)
+    return s, el.Matrix.from_system(ctx, s)
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def test_pairs_and_features(el, ctx, small):
+    s, mat = small
+    P = mlp.pairs(s)
+    assert np.array_equal(el.spai_pairs(mat), P)
+    f = el.spai_features(ctx, mat).cpu().numpy().astype(np.float64)
+    ref = mlp.features(s, P)
+    assert np.abs(f - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+def test_targets_are_exact_inverse_blocks(el, ctx, small):
+    s, mat = small
+    P = mlp.pairs(s)
+    T, W = el.spai_targets(ctx, mat)
+    Binv = np.linalg.inv(oracle.to_csr(s, "B").dense())
+    Tr, Wr = mlp.targets(s, P, Binv)
+    assert np.array_equal(W.cpu().numpy(), Wr)
+    assert np.abs(T.cpu().numpy() - Tr).max() <= 2e-7 * np.abs(Tr).max()
+
+
+def test_loss_and_gradient_match_oracle(el, ctx, small):
+    s, mat = small
+    P = mlp.pairs(s)
+    X = mlp.features(s, P)
+    Binv = np.linalg.inv(oracle.to_csr(s, "B").dense())
+    T, W = mlp.targets(s, P, Binv)
+    theta = mlp.init_params(3) + 0.02 * np.random.default_rng(4).standard_normal(mlp.N_PARAM)
+    # both sides see the same FP32-rounded inputs
+    th32, X32, T32 = (a.astype(np.float32) for a in (theta, X, T))
+    loss_ref, g_ref = mlp.loss_grad(th32.astype(np.float64), X32.astype(np.float64), T32.astype(np.float64), W)
+    loss, g = el.mlp_loss_grad(ctx, dev(th32), dev(X32), dev(T32), dev(W))
+    g = g.cpu().numpy().astype(np.float64)
+    assert abs(loss - loss_ref) <= 1e-5 * loss_ref
+    offs = np.cumsum([0] + [int(np.prod(sh)) for sh in mlp.SHAPES])
+    for i in range(len(mlp.SHAPES)):  # every weight and bias block
+        gr, gg = g_ref[offs[i]:offs[i + 1]], g[offs[i]:offs[i + 1]]
+        assert np.abs(gg - gr).max() <= 1e-4 * np.abs(g_ref).max(), i
+
+
+def test_inference_fp32_and_bf16(el, ctx, small):
+    s, mat = small
+    P = mlp.pairs(s)
+    X = mlp.features(s, P).astype(np.float32)
+    theta = (mlp.init_params(8) + 0.05 * np.random.default_rng(9).standard_normal(mlp.N_PARAM)).astype(np.float32)
+    ref, _ = mlp.forward(theta.astype(np.float64), X.astype(np.float64))
+    out = el.spai_predict(ctx, dev(theta), dev(X)).cpu().numpy()
+    assert np.abs(out - ref).max() <= 1e-5 * np.abs(ref).max()
+    ref16 = mlp.forward_bf16(theta, X.astype(np.float64))
+    out16 = el.spai_predict(ctx, dev(theta), dev(X), bf16=True).cpu().numpy()
+    # FP32 accumulation order can move a BF16 rounding by one unit (2^-8 relative)
+    assert np.abs(out16 - ref16).max() <= 2e-2 * np.abs(ref16).max()
+    assert np.abs(out16 - ref).max() <= 5e-2 * np.abs(ref).max()
+
+
+def test_training_and_preconditioned_overlap_solve(el, ctx):
+    """Train on exact inverses of 500-atom boxes, apply to an unseen box."""
+    feats, targs, masks = [], [], []
+    for seed in (11, 12, 13):
+        s = synth.make_system(500, seed)
+        m = el.Matrix.from_system(ctx, s)
+        feats.append(el.spai_features(ctx, m))
+        T, W = el.spai_targets(ctx, m)
+        targs.append(T)
+        masks.append(W)
+    X, T, W = torch.cat(feats), torch.cat(targs), torch.cat(masks)
+    theta = dev(mlp.init_params(synth.config_seed(4) + 5))
+    loss0, _ = el.mlp_loss_grad(ctx, theta, X, T, W)
+    hist = el.spai_train(ctx, theta, X, T, W, steps=1500, batch=4096, lr=2e-3, seed=1)
+    loss1, _ = el.mlp_loss_grad(ctx, theta, X, T, W)
+    assert loss1 < 0.1 * loss0, (loss0, loss1)
+    assert np.all(np.isfinite(hist))
+    # unseen box
+    s = synth.make_system(500, 99)
+    mat = el.Matrix.from_system(ctx, s)
+    Mv = el.spai_apply(ctx, mat, theta, bf16=True)
+    rng = np.random.default_rng(0)
+    rhs = dev(rng.standard_normal((mat.M, 64)), torch.float64)
+    x0, p0, br0, u0 = el.overlap_solve(ctx, mat, rhs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x0, p0, br0, u0 = el.overlap_solve(ctx, mat, rhs)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    x1, p1, br1, u1 = el.overlap_solve(ctx, mat, rhs, Mv)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x1, p1, br1, u1 = el.overlap_solve(ctx, mat, rhs, Mv)
+    torch.cuda.synchronize()
+    t_pre = time.perf_counter() - t0
+    assert u1 and not u0
+    kappa_plain, kappa_pre = br0[1] / br0[0], br1[1] / br1[0]
+    print(f"\nSPAI: loss {loss0:.3e} -> {loss1:.3e}; kappa interval {kappa_plain:.3f} -> {kappa_pre:.3f}; "
+          f"passes {p0} -> {p1}; time {1e3 * t_plain:.2f} ms -> {1e3 * t_pre:.2f} ms")
+    assert kappa_pre < kappa_plain
+    B = oracle.to_csr(s, "B").dense()
+    ref = np.linalg.solve(B, rhs.cpu().numpy())
+    for x in (x0, x1):
+        xx = x.cpu().numpy()
+        assert np.abs(xx - ref).max() <= 1e-11 * np.abs(ref).max()

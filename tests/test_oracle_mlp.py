@@ -87,3 +87,16 @@ def test_targets_assemble_to_inverse_on_pattern(small):
     assert np.allclose(M, M.T, atol=1e-15)
     # mask counts: every valid entry of every upper block
     assert W.sum() == sum(int(s.n_orb[I]) * int(s.n_orb[J]) for I, J in P)
+
+
+def test_bf16_rounding_closed_forms():
+    one = 1.0
+    ulp = 2.0 ** -7  # spacing of bfloat16 at 1
+    x = np.array([one, one + ulp / 2, one + 3 * ulp / 2, one + ulp / 2 + 2 ** -20, -2.5, 3.0e38 * 0 + 65504.0])
+    r = mlp.bf16(x)
+    assert r[0] == 1.0
+    assert r[1] == 1.0                   # tie -> even
+    assert r[2] == one + 2 * ulp         # tie -> even (upwards)
+    assert r[3] == one + ulp             # above the tie -> up
+    assert r[4] == -2.5                  # exactly representable
+    assert r[5] == 65536.0               # 65504 rounds to 2^16 in bfloat16
