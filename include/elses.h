@@ -119,6 +119,8 @@ typedef struct {
     int32_t audit;       /* 1: recompute FP64 true residuals (ELSES_OUT_FULL only)          */
     int32_t variant;     /* sparse passes: 0 auto, 1 direct gathers, 2 / 3 LDS-staged       */
                          /* gathers (8- / 4-atom clusters), 4 row groups sharing gathers   */
+    int32_t graph;       /* 1: capture the outer iterations in a HIP graph and replay it    */
+                         /* on a private stream (pass timing is not sampled); default 0     */
 } elses_opts;
 
 /* Fill *o with the defaults listed above. */
@@ -196,6 +198,19 @@ elses_status elses_ctx_pass_stats(elses_ctx ctx, int64_t *launches, double *avg_
  */
 elses_status elses_time_pass(elses_ctx ctx, elses_mat mat, int32_t kind, int32_t variant, int32_t slots,
                              int32_t reps, double *avg_us);
+
+/*
+ * Autotuner of the sparse passes.  Times one Richardson step (FP64, or FP32
+ * with mixed != 0) for the grouped passes (4, 2 or 1 waves per row group x
+ * XCD placements 0, 1, 3) and the direct passes at 256 .. 2048 slots (at most
+ * max_slots; 0 = 2048), and keeps the configuration with the lowest time
+ * per column in the matrix: later solves with opts.variant == 0 and
+ * opts.slots == 0 use it (slots capped by the column count).  Outputs (HOST,
+ * may be NULL): the chosen variant code (as opts.variant, placement in bits
+ * 4-5), slot count and time per column and pass in nanoseconds.
+ */
+elses_status elses_autotune(elses_ctx ctx, elses_mat mat, int32_t mixed, int32_t max_slots, int32_t *variant_out,
+                            int32_t *slots_out, double *ns_per_column_out);
 
 /* Sparse products with the uploaded matrices (diagnostics and tests):
  * y = X x for X = A (which=0) or B (which=1); x, y DEVICE double [M][nvec]

@@ -58,7 +58,7 @@ class _System(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("out_mode", ctypes.c_int32), ("slots", ctypes.c_int32), ("use_mixed", ctypes.c_int32),
-                ("audit", ctypes.c_int32), ("variant", ctypes.c_int32)]
+                ("audit", ctypes.c_int32), ("variant", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 _lib = None
@@ -107,6 +107,8 @@ def lib():
         for fn in ("elses_spai_pairs", "elses_spai_features", "elses_spai_targets", "elses_mlp_loss_grad",
                    "elses_spai_train", "elses_spai_predict", "elses_spai_apply", "elses_overlap_solve"):
             getattr(L, fn).restype = ctypes.c_int
+        L.elses_autotune.argtypes = [P, P, I32, I32, P, P, P]
+        L.elses_autotune.restype = ctypes.c_int
         L.elses_regions_create.argtypes = [P, P, I32, P, P, I32, ctypes.POINTER(P)]
         L.elses_regions_create.restype = ctypes.c_int
         L.elses_regions_destroy.argtypes = [P]
@@ -242,7 +244,7 @@ def _variant(v) -> int:
 
 
 def make_opts(tol=1e-8, max_outer=20000, inner_tol=1e-13, full=False, slots=0, mixed=False, audit=False,
-              variant="auto") -> Opts:
+              variant="auto", graph=False) -> Opts:
     o = Opts()
     lib().elses_opts_default(ctypes.byref(o))
     o.tol = tol
@@ -253,6 +255,7 @@ def make_opts(tol=1e-8, max_outer=20000, inner_tol=1e-13, full=False, slots=0, m
     o.use_mixed = 1 if mixed else 0
     o.audit = 1 if audit else 0
     o.variant = _variant(variant)
+    o.graph = 1 if graph else 0
     return o
 
 
@@ -263,7 +266,7 @@ def _shifts_ri(shifts) -> np.ndarray:
 
 def shifted_solve(ctx: Context, mat: Matrix, cols, shifts, *, tol=1e-8, max_outer=20000, inner_tol=1e-13,
                   full=False, slots=0, mixed=False, audit=False, want_x=True, allow_not_converged=False,
-                  variant="auto"):
+                  variant="auto", graph=False):
     """(z_k B - A) x = e_j for j in cols and every shift; returns torch tensors on the device."""
     torch = _torch()
     cols = np.ascontiguousarray(cols, dtype=np.int32)
@@ -280,7 +283,7 @@ def shifted_solve(ctx: Context, mat: Matrix, cols, shifts, *, tol=1e-8, max_oute
     x = torch.empty(2 * nx, dtype=torch.float64, device=dev) if want_x else None
     iters = torch.empty(nc, dtype=torch.int32, device=dev)
     resid = torch.empty(nc * K, dtype=torch.float64, device=dev)
-    opts = make_opts(tol, max_outer, inner_tol, full, slots, mixed, audit, variant)
+    opts = make_opts(tol, max_outer, inner_tol, full, slots, mixed, audit, variant, graph)
     st = lib().elses_shifted_solve(ctx._h, mat._h, nc, _np_ptr(cols), K, _np_ptr(z), ctypes.byref(opts),
                                    _dev_ptr(x), _dev_ptr(iters), _dev_ptr(resid))
     ctx.check(st, allow_warn=allow_not_converged)
@@ -293,7 +296,7 @@ def shifted_solve(ctx: Context, mat: Matrix, cols, shifts, *, tol=1e-8, max_oute
 
 
 def density_matrix(ctx: Context, mat: Matrix, cols, shifts, c, *, tol=1e-8, max_outer=20000, inner_tol=1e-13,
-                   slots=0, mixed=False, want_x=False, allow_not_converged=False, variant="auto"):
+                   slots=0, mixed=False, want_x=False, allow_not_converged=False, variant="auto", graph=False):
     """rho_ij = sum_k Im(c_k x_{j,k,i}) on the pattern, plus the traces Tr[rho B], Tr[rho A] over cols."""
     torch = _torch()
     cols = np.ascontiguousarray(cols, dtype=np.int32)
@@ -311,7 +314,7 @@ def density_matrix(ctx: Context, mat: Matrix, cols, shifts, c, *, tol=1e-8, max_
     iters = torch.empty(nc, dtype=torch.int32, device=dev)
     resid = torch.empty(nc * K, dtype=torch.float64, device=dev)
     traces = np.zeros(2)
-    opts = make_opts(tol, max_outer, inner_tol, False, slots, mixed, False, variant)
+    opts = make_opts(tol, max_outer, inner_tol, False, slots, mixed, False, variant, graph)
     st = lib().elses_density_matrix(ctx._h, mat._h, nc, _np_ptr(cols), K, _np_ptr(z), _np_ptr(cw),
                                     ctypes.byref(opts), _dev_ptr(rho), _np_ptr(traces), _dev_ptr(col_tr),
                                     _dev_ptr(x), _dev_ptr(iters), _dev_ptr(resid))
@@ -387,7 +390,7 @@ class Regions:
 
 
 def region_solve(ctx: Context, reg: Regions, shifts, c=None, *, tol=1e-8, max_outer=20000, inner_tol=1e-13,
-                 mixed=False, want_x=True, allow_not_converged=False, variant="auto"):
+                 mixed=False, want_x=True, allow_not_converged=False, variant="auto", graph=False):
     """Solve every region's columns for every shift; density outputs when weights c are given."""
     torch = _torch()
     z = _shifts_ri(shifts)
@@ -404,7 +407,7 @@ def region_solve(ctx: Context, reg: Regions, shifts, c=None, *, tol=1e-8, max_ou
     iters = torch.empty(nc, dtype=torch.int32, device=dev)
     resid = torch.empty(nc * K, dtype=torch.float64, device=dev)
     traces = np.zeros(2)
-    opts = make_opts(tol, max_outer, inner_tol, False, 0, mixed, False, variant)
+    opts = make_opts(tol, max_outer, inner_tol, False, 0, mixed, False, variant, graph)
     st = lib().elses_regions_solve(ctx._h, reg._h, K, _np_ptr(z), None if cw is None else _np_ptr(cw),
                                    ctypes.byref(opts), _dev_ptr(x), _dev_ptr(rho),
                                    None if cw is None else _np_ptr(traces), _dev_ptr(col_tr), _dev_ptr(iters),
@@ -492,3 +495,11 @@ def overlap_solve(ctx: Context, mat: Matrix, s, M_vals=None, tol: float = 1e-13)
     ctx.check(lib().elses_overlap_solve(ctx._h, mat._h, _dev_ptr(M_vals), tol, s.shape[1], _dev_ptr(s), _dev_ptr(x),
                                         ctypes.byref(passes), _np_ptr(br), ctypes.byref(used)))
     return x, passes.value, tuple(br), bool(used.value)
+
+
+def autotune(ctx: Context, mat: Matrix, mixed: bool = False, max_slots: int = 0):
+    """Time the pass configurations and keep the fastest per column in `mat`; returns (variant, slots, ns/col)."""
+    v, sl, ns = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    ctx.check(lib().elses_autotune(ctx._h, mat._h, 1 if mixed else 0, max_slots, ctypes.byref(v), ctypes.byref(sl),
+                                   ctypes.byref(ns)))
+    return v.value, sl.value, ns.value

@@ -1114,6 +1114,15 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
     if (n_cols == 0) return ELSES_OK;
 
     hipStream_t st = ctx->stream;
+    // autotuned variant and slot count (global solves with both left at 0)
+    {
+        const int pk = o.use_mixed ? 1 : 0;
+        if (!rp && o.variant == 0 && o.slots == 0 && mat->tuned_slots[pk] > 0) {
+            o.variant = mat->tuned_variant[pk];
+            o.slots = std::max(64, std::min(mat->tuned_slots[pk], ((n_cols + 63) / 64) * 64));
+            if (o.slots > 128 && o.slots % 128 != 0) o.slots += 64;
+        }
+    }
     // ld: slots (columns advanced together); vw: width of a vector row
     const int ld = rp ? rp->n_tiles * rp->L : choose_slots(n_cols, M, o);
     const int vw = rp ? rp->L : ld;
@@ -1352,9 +1361,10 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
             ctx->prof_slots = ld;
         }
         EvPair* open_sample = nullptr;
+        bool capturing = false;
         auto timed_pass = [&](PassKind kind, int k) {
             const int first = 2, last = rich.d - 2;
-            if (k == first && last >= first && !prof.empty() && it % ctx->prof_stride == 0)
+            if (k == first && last >= first && !prof.empty() && !capturing && it % ctx->prof_stride == 0)
                 for (auto& p : prof)
                     if (!p.busy) {
                         open_sample = &p;
@@ -1389,99 +1399,175 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         const int64_t generations = (n_cols + ld - 1) / ld + 1;
         const int64_t cap = (int64_t)o.max_outer * generations + 64;
         bool pending = false;
-        for (;;) {
-            // w = A q_n, s' = w - beta t_{n-1} (in place of t_{n-1}), alpha_n
-            pa.vals = valsA;
-            pa.vals32 = valsA32;
-            pa.Xg = Vq;
-            pa.S = Tp;
-            pa.Vq = Vq;
-            launch_pass(mixed ? PASS_LANCZOS_A_MX : PASS_LANCZOS_A, pa, st);
-            reduce(part0, alpha, true);
-            // overlap solve v = p(B) s on s = s' - alpha t_n (Richardson steps
-            // with the Chebyshev roots in Leja order)
-            pa.vals = valsB;
-            pa.vals32 = valsB32;
-            pa.Tn = Tn;
-            pa.Sout = F1;
-            pa.tau = rich.tau[0];
-            double* vout = nullptr;
-            if (!mixed) {
-                pa.Xio = F2;
-                launch_pass(PASS_STEP_FIRST, pa, st);
-                double* xcur = F2;
-                double* xoth = Tp;
-                pa.S = F1;
-                for (int k = 2; k < rich.d; ++k) {
-                    pa.Xg = xcur;
-                    pa.Xio = xoth;
-                    pa.tau = rich.tau[k - 1];
-                    timed_pass(k == rich.d - 1 ? PASS_STEP_LAST : PASS_STEP, k);
-                    std::swap(xcur, xoth);
-                }
-                vout = xcur;
-                F2 = xoth;
-            } else {
-                // round 1: FP32 solve of B x = s (s kept in FP64 and FP32)
-                pa.R32o = S32;
-                pa.Xio32 = Xa32;
-                launch_pass(PASS_STEP32_FIRST, pa, st);
-                float* xcur = Xa32;
-                float* xoth = Xb32;
-                pa.R32 = S32;
-                for (int k = 2; k < rich.d; ++k) {
+        // one outer iteration: launches, then the rotation of the buffers
+        auto iteration = [&]() {
+                // w = A q_n, s' = w - beta t_{n-1} (in place of t_{n-1}), alpha_n
+                pa.vals = valsA;
+                pa.vals32 = valsA32;
+                pa.Xg = Vq;
+                pa.S = Tp;
+                pa.Vq = Vq;
+                launch_pass(mixed ? PASS_LANCZOS_A_MX : PASS_LANCZOS_A, pa, st);
+                reduce(part0, alpha, true);
+                // overlap solve v = p(B) s on s = s' - alpha t_n (Richardson steps
+                // with the Chebyshev roots in Leja order)
+                pa.vals = valsB;
+                pa.vals32 = valsB32;
+                pa.Tn = Tn;
+                pa.Sout = F1;
+                pa.tau = rich.tau[0];
+                double* vout = nullptr;
+                if (!mixed) {
+                    pa.Xio = F2;
+                    launch_pass(PASS_STEP_FIRST, pa, st);
+                    double* xcur = F2;
+                    double* xoth = Tp;
+                    pa.S = F1;
+                    for (int k = 2; k < rich.d; ++k) {
+                        pa.Xg = xcur;
+                        pa.Xio = xoth;
+                        pa.tau = rich.tau[k - 1];
+                        timed_pass(k == rich.d - 1 ? PASS_STEP_LAST : PASS_STEP, k);
+                        std::swap(xcur, xoth);
+                    }
+                    vout = xcur;
+                    F2 = xoth;
+                } else {
+                    // round 1: FP32 solve of B x = s (s kept in FP64 and FP32)
+                    pa.R32o = S32;
+                    pa.Xio32 = Xa32;
+                    launch_pass(PASS_STEP32_FIRST, pa, st);
+                    float* xcur = Xa32;
+                    float* xoth = Xb32;
+                    pa.R32 = S32;
+                    for (int k = 2; k < rich.d; ++k) {
+                        pa.Xg32 = xcur;
+                        pa.Xio32 = xoth;
+                        pa.tau = rich.tau[k - 1];
+                        timed_pass(PASS_STEP32, k);
+                        std::swap(xcur, xoth);
+                    }
+                    // FP64 residual r = s - B x, first correction iterate
+                    pa.S = F1;
                     pa.Xg32 = xcur;
-                    pa.Xio32 = xoth;
-                    pa.tau = rich.tau[k - 1];
-                    timed_pass(PASS_STEP32, k);
-                    std::swap(xcur, xoth);
+                    pa.R32o = R32;
+                    pa.Xio32 = Da32;
+                    launch_pass(PASS_REFINE, pa, st);
+                    // round 2: FP32 solve of B d = r; the last step forms v = x + d
+                    float* dcur = Da32;
+                    float* doth = Db32;
+                    pa.R32 = R32;
+                    pa.Xr1 = xcur;
+                    pa.Xio = F2;
+                    for (int k = 1; k < rich.d; ++k) {
+                        pa.Xg32 = dcur;
+                        pa.Xio32 = doth;
+                        pa.tau = rich.tau[k - 1];
+                        launch_pass(k == rich.d - 1 ? PASS_STEP32_LAST : PASS_STEP32, pa, st);
+                        std::swap(dcur, doth);
+                    }
+                    vout = F2;
+                    F2 = Tp;
                 }
-                // FP64 residual r = s - B x, first correction iterate
-                pa.S = F1;
-                pa.Xg32 = xcur;
-                pa.R32o = R32;
-                pa.Xio32 = Da32;
-                launch_pass(PASS_REFINE, pa, st);
-                // round 2: FP32 solve of B d = r; the last step forms v = x + d
-                float* dcur = Da32;
-                float* doth = Db32;
-                pa.R32 = R32;
-                pa.Xr1 = xcur;
-                pa.Xio = F2;
-                for (int k = 1; k < rich.d; ++k) {
-                    pa.Xg32 = dcur;
-                    pa.Xio32 = doth;
-                    pa.tau = rich.tau[k - 1];
-                    launch_pass(k == rich.d - 1 ? PASS_STEP32_LAST : PASS_STEP32, pa, st);
-                    std::swap(dcur, doth);
-                }
-                vout = F2;
-                F2 = Tp;
+                reduce(part0, vs, false);
+                reduce(part1, ss, false);
+                // multi-shift recurrences, convergence, slot refill
+                sa.Vq = Vq;
+                launch_shift_update(sa, st);
+                HCHECK(hipGetLastError());
+                // rotate: q <- v, t_{n-1} <- t_n, t_n <- s; the old q block is free
+                double* oldV = Vq;
+                Vq = vout;
+                Tp = Tn;
+                Tn = F1;
+                F1 = oldV;
+        };
+        auto poll_done = [&]() -> bool {
+            if (pending) {
+                HCHECK(hipEventSynchronize(ev));
+                harvest();
+                if (h_rem[0] == 0) return true;
             }
-            reduce(part0, vs, false);
-            reduce(part1, ss, false);
-            // multi-shift recurrences, convergence, slot refill
-            sa.Vq = Vq;
-            launch_shift_update(sa, st);
-            HCHECK(hipGetLastError());
-            // rotate: q <- v, t_{n-1} <- t_n, t_n <- s; the old q block is free
-            double* oldV = Vq;
-            Vq = vout;
-            Tp = Tn;
-            Tn = F1;
-            F1 = oldV;
-            ++it;
-            if (it % poll == 0) {
-                if (pending) {
-                    HCHECK(hipEventSynchronize(ev));
-                    harvest();
-                    if (h_rem[0] == 0) break;
-                }
-                HCHECK(hipMemcpyAsync(h_rem, sa.remaining, sizeof(int), hipMemcpyDeviceToHost, st));
-                HCHECK(hipEventRecord(ev, st));
-                pending = true;
+            HCHECK(hipMemcpyAsync(h_rem, sa.remaining, sizeof(int), hipMemcpyDeviceToHost, st));
+            HCHECK(hipEventRecord(ev, st));
+            pending = true;
+            return false;
+        };
+        if (!o.graph) {
+            for (;;) {
+                iteration();
+                ++it;
+                if (it % poll == 0 && poll_done()) break;
+                if (it > cap) throw HipFail{hipErrorUnknown, "solver loop did not terminate"};
             }
-            if (it > cap) throw HipFail{hipErrorUnknown, "solver loop did not terminate"};
+        } else {
+            // Capture G outer iterations (a whole number of periods of the
+            // buffer rotation, at least `poll`) into one graph on a private
+            // stream and replay it, polling between replays.
+            const double* start[5] = {Vq, Tp, Tn, F1, F2};
+            int period = 0;
+            {
+                double* p[5] = {Vq, Tp, Tn, F1, F2};
+                for (int q = 1; q <= 12 && period == 0; ++q) {
+                    // the rotation of `iteration` (FP64: v ends in F2 or the s' block by parity)
+                    double* vout = mixed ? p[4] : ((rich.d - 2) % 2 == 0 ? p[4] : p[1]);
+                    double* xoth = mixed ? p[1] : ((rich.d - 2) % 2 == 0 ? p[1] : p[4]);
+                    double* nv[5] = {vout, p[2], p[3], p[0], xoth};
+                    for (int r = 0; r < 5; ++r) p[r] = nv[r];
+                    bool same = true;
+                    for (int r = 0; r < 5; ++r) same = same && p[r] == start[r];
+                    if (same) period = q;
+                }
+            }
+            if (period == 0) throw HipFail{hipErrorUnknown, "buffer rotation has no short period"};
+            const int G = period * ((poll + period - 1) / period);
+            hipStream_t gs = nullptr;
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            hipEvent_t ready = nullptr;
+            const hipStream_t st0 = st;
+            auto cleanup = [&]() {
+                if (exec) (void)hipGraphExecDestroy(exec);
+                if (graph) (void)hipGraphDestroy(graph);
+                if (ready) (void)hipEventDestroy(ready);
+                if (gs) (void)hipStreamDestroy(gs);
+                st = st0;
+            };
+            try {
+                HCHECK(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+                HCHECK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+                HCHECK(hipEventRecord(ready, st0));
+                HCHECK(hipStreamWaitEvent(gs, ready, 0));
+                st = gs;  // every launch below (the lambdas capture st by reference)
+                capturing = true;
+                HCHECK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+                for (int q = 0; q < G; ++q) iteration();
+                HCHECK(hipStreamEndCapture(gs, &graph));
+                capturing = false;
+                for (int r = 0; r < 5; ++r)
+                    if ((r == 0 ? Vq : r == 1 ? Tp : r == 2 ? Tn : r == 3 ? F1 : F2) != start[r])
+                        throw HipFail{hipErrorUnknown, "graph capture did not return the buffers to their roles"};
+                HCHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+                for (;;) {
+                    HCHECK(hipGraphLaunch(exec, gs));
+                    it += G;
+                    if (poll_done()) break;
+                    if (it > cap) throw HipFail{hipErrorUnknown, "solver loop did not terminate"};
+                }
+                HCHECK(hipEventRecord(ready, gs));
+                HCHECK(hipStreamWaitEvent(st0, ready, 0));
+                HCHECK(hipStreamSynchronize(gs));
+            } catch (...) {
+                if (capturing) {
+                    hipGraph_t g2 = nullptr;
+                    (void)hipStreamEndCapture(gs, &g2);
+                    if (g2) (void)hipGraphDestroy(g2);
+                    capturing = false;
+                }
+                cleanup();
+                throw;
+            }
+            cleanup();
         }
         if (o.audit) launch_true_residual(d, mixed, n_cols, d_cols, K, d_z, x_out, resid_out, st);
         if (density) {
@@ -2215,6 +2301,50 @@ elses_status elses_overlap_solve(elses_ctx ctx, elses_mat mat, const double* M_v
     } catch (const HipFail& f) {
         return hip_err(ctx, f);
     }
+    return ELSES_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+elses_status elses_autotune(elses_ctx ctx, elses_mat mat, int32_t mixed, int32_t max_slots, int32_t* variant_out,
+                            int32_t* slots_out, double* ns_per_column_out) {
+    if (!ctx || !mat) return ELSES_ERR_INVALID_ARG;
+    if (mixed && mat->precision != ELSES_MIXED)
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "mixed tuning needs a matrix created with ELSES_MIXED");
+    const int kind = mixed ? PASS_STEP32 : PASS_STEP;
+    const int M = mat->d.M;
+    // candidates: grouped passes with 4 / 2 / 1 waves per group and the XCD
+    // placements 0, 1, 3; direct passes; slot counts up to the memory cap
+    std::vector<int> variants;
+    if (mat->d.grp.n > 0)
+        for (int vid : {4, 5, 6})
+            for (int place : {0, 1, 3}) variants.push_back(vid | (place << 4));
+    variants.push_back(1 | (1 << 4));
+    const int64_t cap_mem = (int64_t)(1.5 * 1024 * 1024 * 1024) / (5 * 8 * (int64_t)std::max(M, 1));
+    const int cap = (int)std::min<int64_t>(max_slots > 0 ? max_slots : 2048, std::max<int64_t>(64, cap_mem));
+    double best = 1e300;
+    int bv = 0, bs = 0;
+    for (int sl : {256, 512, 1024, 2048}) {
+        if (sl > cap) continue;
+        for (int v : variants) {
+            double us = 0.0;
+            if (elses_time_pass(ctx, mat, kind, v, sl, 10, &us) != ELSES_OK) continue;
+            const double per = us * 1e3 / sl;
+            if (per < best) {
+                best = per;
+                bv = v;
+                bs = sl;
+            }
+        }
+    }
+    if (bs == 0) return set_err(ctx, ELSES_ERR_HIP, "no pass configuration could be timed");
+    mat->tuned_variant[mixed ? 1 : 0] = bv;
+    mat->tuned_slots[mixed ? 1 : 0] = bs;
+    if (variant_out) *variant_out = bv;
+    if (slots_out) *slots_out = bs;
+    if (ns_per_column_out) *ns_per_column_out = best;
     return ELSES_OK;
 }
 

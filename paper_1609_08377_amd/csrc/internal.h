@@ -110,6 +110,10 @@ struct elses_mat_s {
     elses::HostMatrix h;
     elses::DevMatrix d;
     double b_lo = 0, b_hi = 0;  // interval enclosing the spectrum of B
+    // autotuned pass variant and slot count per precision (0 FP64, 1 mixed);
+    // slots 0: not tuned
+    int tuned_variant[2] = {0, 0};
+    int tuned_slots[2] = {0, 0};
 };
 
 namespace elses {
