@@ -847,8 +847,9 @@ struct elses_regions_s {
     int64_t* d_vidx = nullptr;
     int64_t* d_pat_off = nullptr;
     int* d_slot_map = nullptr;
+    int* d_row_tile = nullptr;  // tile of each row of bm
     ~elses_regions_s() {
-        void* p[] = {d_mask, d_col_row, d_rows, d_vidx, d_pat_off, d_slot_map};
+        void* p[] = {d_mask, d_col_row, d_rows, d_vidx, d_pat_off, d_slot_map, d_row_tile};
         for (void* q : p)
             if (q) (void)hipFree(q);
         if (bm) elses_mat_destroy(bm);
@@ -1025,9 +1026,9 @@ elses_status regions_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, con
         }
     }
     P->n_cols = (int)P->cols.size();
-    // tile of each row group
+    // tile of each row and of each row group
+    std::vector<int> row_tile(Mb);
     {
-        std::vector<int> row_tile(Mb);
         for (int t = 0; t < T; ++t)
             for (int row = tile_row0[t]; row < tile_row0[t + 1]; ++row) row_tile[row] = t;
         P->group_tile.resize(P->bm->h.grp_row0.size());
@@ -1045,6 +1046,8 @@ elses_status regions_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, con
         P->d_vidx = dalloc<int64_t>(P->vidx.size());
         P->d_pat_off = dalloc<int64_t>(P->pat_off.size());
         P->d_slot_map = dalloc<int>(P->slot_map.size());
+        P->d_row_tile = dalloc<int>(row_tile.size());
+        HCHECK(hipMemcpy(P->d_row_tile, row_tile.data(), sizeof(int) * row_tile.size(), hipMemcpyHostToDevice));
         HCHECK(hipMemcpy(P->d_mask, mask.data(), sizeof(uint64_t) * mask.size(), hipMemcpyHostToDevice));
         HCHECK(hipMemcpy(P->d_col_row, P->col_row.data(), sizeof(int) * P->col_row.size(), hipMemcpyHostToDevice));
         HCHECK(hipMemcpy(P->d_rows, P->rows.data(), sizeof(int) * P->rows.size(), hipMemcpyHostToDevice));
@@ -1164,6 +1167,7 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         pa.mask = rp->d_mask;
     }
     const int n_groups = pa.n_slabs;
+    const int* row_tile = rp ? rp->d_row_tile : nullptr;
     const bool mixed = o.use_mixed != 0;
     if (mixed && (pa.staged == 1 || pa.staged == 2))
         return set_err(ctx, ELSES_ERR_INVALID_ARG, "the LDS-staged passes have no mixed-precision form");
@@ -1414,16 +1418,15 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
                 pa.vals = valsB;
                 pa.vals32 = valsB32;
                 pa.Tn = Tn;
-                pa.Sout = F1;
-                pa.tau = rich.tau[0];
                 double* vout = nullptr;
                 if (!mixed) {
-                    pa.Xio = F2;
-                    launch_pass(PASS_STEP_FIRST, pa, st);
+                    // s = s' - alpha t_n into F1, x_1 = g0 s into F2; then steps 1 .. d-1
+                    launch_overlap_start(M, vw, Tp, Tn, alpha, inv_beta, row_tile, rich.g0, F1, F2, nullptr,
+                                         nullptr, st);
                     double* xcur = F2;
                     double* xoth = Tp;
                     pa.S = F1;
-                    for (int k = 2; k < rich.d; ++k) {
+                    for (int k = 1; k < rich.d; ++k) {
                         pa.Xg = xcur;
                         pa.Xio = xoth;
                         pa.tau = rich.tau[k - 1];
@@ -1434,13 +1437,12 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
                     F2 = xoth;
                 } else {
                     // round 1: FP32 solve of B x = s (s kept in FP64 and FP32)
-                    pa.R32o = S32;
-                    pa.Xio32 = Xa32;
-                    launch_pass(PASS_STEP32_FIRST, pa, st);
+                    launch_overlap_start(M, vw, Tp, Tn, alpha, inv_beta, row_tile, rich.g0, F1, nullptr, S32, Xa32,
+                                         st);
                     float* xcur = Xa32;
                     float* xoth = Xb32;
                     pa.R32 = S32;
-                    for (int k = 2; k < rich.d; ++k) {
+                    for (int k = 1; k < rich.d; ++k) {
                         pa.Xg32 = xcur;
                         pa.Xio32 = xoth;
                         pa.tau = rich.tau[k - 1];
@@ -1510,8 +1512,8 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
                 double* p[5] = {Vq, Tp, Tn, F1, F2};
                 for (int q = 1; q <= 12 && period == 0; ++q) {
                     // the rotation of `iteration` (FP64: v ends in F2 or the s' block by parity)
-                    double* vout = mixed ? p[4] : ((rich.d - 2) % 2 == 0 ? p[4] : p[1]);
-                    double* xoth = mixed ? p[1] : ((rich.d - 2) % 2 == 0 ? p[1] : p[4]);
+                    double* vout = mixed ? p[4] : ((rich.d - 1) % 2 == 0 ? p[4] : p[1]);
+                    double* xoth = mixed ? p[1] : ((rich.d - 1) % 2 == 0 ? p[1] : p[4]);
                     double* nv[5] = {vout, p[2], p[3], p[0], xoth};
                     for (int r = 0; r < 5; ++r) p[r] = nv[r];
                     bool same = true;

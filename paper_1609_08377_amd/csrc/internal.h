@@ -202,6 +202,10 @@ struct PassArgs {
 };
 
 void launch_pass(PassKind kind, const PassArgs &a, hipStream_t st);
+// s = s' - alpha_n t_n and x_1 = g0 s, element-wise over [M][vw] (FP32 copies when S32 != null)
+void launch_overlap_start(int M, int vw, const double *Sp, const double *Tn, const double *alpha,
+                          const double *inv_beta, const int *row_tile, double g0, double *S, double *X1, float *S32,
+                          float *X132, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Per-slot shift recurrences and bookkeeping.

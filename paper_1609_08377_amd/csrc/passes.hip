@@ -819,6 +819,38 @@ void launch_pass(PassKind kind, const PassArgs& a, hipStream_t st) {
     }
 }
 
+// Start of the overlap solve, element-wise over [M][vw]: s = s' - (alpha_n /
+// beta_{n-1}) t_n (t_n stored unnormalised), x_1 = g0 s.  The slot of
+// (row, c) is c, or with region tiles row_tile[row] * vw + c.  FP32 copies
+// of s and x_1 are written when S32 is given.
+__global__ void overlap_start_kernel(int64_t n, int vw, const double* __restrict__ Sp, const double* __restrict__ Tn,
+                                     const double* __restrict__ alpha, const double* __restrict__ inv_beta,
+                                     const int* __restrict__ row_tile, double g0, double* __restrict__ S,
+                                     double* __restrict__ X1, float* __restrict__ S32, float* __restrict__ X132) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int row = (int)(e / vw), c = (int)(e - (int64_t)row * vw);
+    const int slot = row_tile ? row_tile[row] * vw + c : c;
+    const double sv = fma(-(alpha[slot] * inv_beta[slot]), Tn[e], Sp[e]);
+    const double x1 = g0 * sv;
+    if (S32) {
+        S32[e] = static_cast<float>(sv);
+        X132[e] = static_cast<float>(x1);
+        S[e] = sv;
+    } else {
+        S[e] = sv;
+        X1[e] = x1;
+    }
+}
+
+void launch_overlap_start(int M, int vw, const double* Sp, const double* Tn, const double* alpha,
+                          const double* inv_beta, const int* row_tile, double g0, double* S, double* X1, float* S32,
+                          float* X132, hipStream_t st) {
+    const int64_t n = (int64_t)M * vw;
+    hipLaunchKernelGGL(overlap_start_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, vw, Sp, Tn,
+                       alpha, inv_beta, row_tile, g0, S, X1, S32, X132);
+}
+
 // out[c] = sum_k part[k*ld + c] in two deterministic stages:
 // stage 1 sums blocks of 64 partials per column, stage 2 the block sums.
 __global__ void col_reduce1_kernel(const double* __restrict__ part, int n_part, int ld, double* __restrict__ tmp) {
