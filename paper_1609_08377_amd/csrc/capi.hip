@@ -1215,7 +1215,7 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         HCHECK(hipMemsetAsync(part0, 0, sizeof(double) * n_groups * vw, st));
         HCHECK(hipMemsetAsync(part1, 0, sizeof(double) * n_groups * vw, st));
         double* red_tmp = pool.get<double>(rp ? chunk_s0.size() * (size_t)vw : (size_t)((n_groups + 63) / 64) * ld);
-        int *d_slab_group = nullptr, *d_slab_tile = nullptr, *d_chunk = nullptr;
+        int *d_slab_group = nullptr, *d_slab_tile = nullptr, *d_chunk = nullptr, *d_tile_live = nullptr;
         if (rp) {
             d_slab_group = pool.get<int>(slab_group.size());
             d_slab_tile = pool.get<int>(slab_tile.size());
@@ -1231,6 +1231,13 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
                                   sizeof(int) * tile_chunk_off.size(), hipMemcpyHostToDevice, st));
             pa.slab_group = d_slab_group;
             pa.slab_tile = d_slab_tile;
+            // running columns per tile (region tiles have no refill)
+            std::vector<int> live(rp->n_tiles, 0);
+            for (int t = 0; t < rp->n_tiles; ++t)
+                for (int c = 0; c < rp->L; ++c) live[t] += rp->slot_map[(size_t)t * rp->L + c] >= 0 ? 1 : 0;
+            d_tile_live = pool.get<int>(live.size());
+            HCHECK(hipMemcpyAsync(d_tile_live, live.data(), sizeof(int) * live.size(), hipMemcpyHostToDevice, st));
+            pa.tile_live = d_tile_live;
         }
         double* vs = pool.get<double>(ld);
         double* ss = pool.get<double>(ld);
@@ -1271,6 +1278,7 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
         sa.ld = ld;
         sa.vld = vw;
         sa.slot_map = rp ? rp->d_slot_map : nullptr;
+        sa.tile_live = d_tile_live;
         sa.K = K;
         sa.M = M;
         sa.z = d_z;

@@ -171,6 +171,7 @@ struct PassArgs {
     const int *slab_group, *slab_tile;
     const uint64_t *mask;
     int mask_words;
+    const int *tile_live;  // region tiles: columns of each tile still running (0: the tile is skipped)
     int place;               // workgroup placement (0 XCD regions tile by tile, 1 XCD regions tile-fastest, 2 plain)
     const int *g_R, *g_roff, *g_rows, *g_uoff, *g_u4, *g_uorb;
     const int64_t *g_voff;
@@ -243,6 +244,7 @@ struct ShiftArgs {
     double tol;
     int max_outer;
     const int *slot_map;           // initial column of each slot (-1 idle), or null: slot s takes column s
+    int *tile_live;                // region tiles: running columns per tile of vld slots (or null)
     int *queue;                    // next column to start
     int *remaining;                // columns not yet finished
     int *n_notconv;                // columns finished without convergence

@@ -710,7 +710,9 @@ __global__ __launch_bounds__(kBlock) void pass_group_kernel(PassArgs a, const in
     for (int c = 0; c < CPL; ++c) d0[c] = d1[c] = 0.0;
     const auto src = make_src<KIND, CPL>(a, c0, cs);
     const int g = a.slab_group ? a.slab_group[slab * GPW + gi] : slab * GPW + gi;
-    const bool live = a.slab_group ? g >= 0 : g < a.n_grp;
+    // a region tile whose columns have all finished is skipped
+    const bool tile_done = a.tile_live && a.tile_live[a.slab_tile[slab]] == 0;
+    const bool live = (a.slab_group ? g >= 0 : g < a.n_grp) && !tile_done;
     int R = 0;
     TA* pw = part + (size_t)wave * kMaxGroupRows * kWave * CPL;
     if (live) {

@@ -235,6 +235,7 @@ __global__ __launch_bounds__(kShiftThreads) void shift_update_kernel(ShiftArgs a
         a.inv_beta[slot] = 0.0;
         a.coefT[slot] = 0.0;
         atomicSub(a.remaining, 1);
+        if (a.tile_live) atomicSub(a.tile_live + slot / a.vld, 1);
     }
 }
 
