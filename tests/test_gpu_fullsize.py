@@ -1,0 +1,180 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch configurations the benchmark times.
+
+Outputs are compared on samples the CPU oracle computes one by one; the
+rest is checked through properties that hold at any size (every residual
+estimate <= tol, symmetry G_ij = G_ji, agreement of two solvers).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def el():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1609_08377_amd as el
+    el.lib()
+    return el
+
+
+@pytest.fixture(scope="module")
+def ctx(el):
+    return el.Context(0)
+
+
+def fermi_cw(z):
+    K = len(z)
+    return (-(1.0 / np.pi) * (2.0 / K) * 0.5 * (1.0 - np.tanh(0.5 * z.real / 0.01))).astype(np.complex128)
+
+
+def pattern_rows(s, j):
+    """Rows of the pattern of column j: the orbitals of the atoms coupled to j's atom, ascending."""
+    J = int(np.searchsorted(s.orb_off, j, side="right") - 1)
+    nb = s.blk_col[s.blk_row_ptr[J]:s.blk_row_ptr[J + 1]]
+    return np.concatenate([np.arange(s.orb_off[I], s.orb_off[I] + s.n_orb[I]) for I in nb])
+
+
+def rounded(s):
+    return dataclasses.replace(s, A_val=s.A_val.astype(np.float32).astype(np.float64),
+                               B_val=s.B_val.astype(np.float32).astype(np.float64))
+
+
+def test_c2_batch_of_1024_columns(el, ctx):
+    """4096-atom box, FP64, first batch of 1024 columns x 64 shifts at tol 1e-8 (1024 slots, default passes)."""
+    s = synth.make_system(4096, synth.config_seed(2))
+    mat = el.Matrix.from_system(ctx, s)
+    z = synth.shift_grid(64)
+    cw = fermi_cw(z)
+    cols = np.arange(1024, dtype=np.int32)
+    out = el.density_matrix(ctx, mat, cols, z, cw, want_x=True)
+    assert np.all(out["resid"].cpu().numpy() <= 1e-8)
+    K = len(z)
+    xg = out["x"].cpu().numpy()
+    pat_off = out["pat_off"]
+    A, B = oracle.to_csr(s, "A"), oracle.to_csr(s, "B")
+    # symmetry G_ij = G_ji for pairs inside the batch
+    worst, scale = 0.0, 0.0
+    for j in (5, 400, 777):
+        rows = B.ci[B.rp[j]:B.rp[j + 1]]
+        blk = xg[pat_off[j] * K:pat_off[j + 1] * K].reshape(K, -1)
+        for p, i in enumerate(rows):
+            if i >= 1024:
+                continue
+            ri = B.ci[B.rp[i]:B.rp[i + 1]]
+            q = int(np.searchsorted(ri, j))
+            other = xg[pat_off[i] * K:pat_off[i + 1] * K].reshape(K, -1)[:, q]
+            worst = max(worst, np.abs(blk[:, p] - other).max())
+            scale = max(scale, np.abs(blk[:, p]).max())
+    assert worst <= 2e-6 * scale
+    # sampled columns against the oracle (shifted COCG to 1e-10, one column per thread)
+    sample = np.array([0, 333, 700, 1023], dtype=np.int32)
+    ref = oracle.shifted_solve(A, B, sample, z, tol=1e-10, full=False, true_residual=False)
+    lo = mat.b_interval[0]
+    rho = out["rho"].cpu().numpy()
+    rho_ref, _, _ = oracle.density_from_x(B, A, sample, ref.x, ref.pat_off, cw)
+    for c, j in enumerate(sample):
+        blk = xg[pat_off[j] * K:pat_off[j + 1] * K].reshape(K, -1)
+        rb = ref.x[ref.pat_off[c] * K:ref.pat_off[c + 1] * K].reshape(K, -1)
+        for k in range(K):
+            assert np.abs(blk[k] - rb[k]).max() <= 1e-8 / (z[k].imag * lo)
+            assert np.abs(blk[k] - rb[k]).max() <= 5e-7 * np.abs(rb[k]).max()
+        rg = rho[pat_off[j]:pat_off[j + 1]]
+        rr = rho_ref[ref.pat_off[c]:ref.pat_off[c + 1]]
+        assert np.abs(rg - rr).max() <= 1e-6 * np.abs(rr).max()
+
+
+def test_c3_region_tiles(el, ctx):
+    """50000-atom box, the benchmark's region sample and packing (64-slot tiles), mixed precision."""
+    s = synth.make_system(50000, synth.config_seed(3))
+    mat = el.Matrix.from_system(ctx, s, precision="mixed")
+    centres, radii = synth.sample_regions(s, 2048, synth.config_seed(3))
+    centres, radii = centres[:96], radii[:96]
+    reg = el.Regions(ctx, mat, centres, radii, 64)
+    z = synth.shift_grid(64)
+    out = el.region_solve(ctx, reg, z, fermi_cw(z), mixed=True)
+    assert np.all(out["resid"].cpu().numpy() <= 1e-8)
+    xg = out["x"].cpu().numpy()
+    K = len(z)
+    s32 = rounded(s)
+    col_region = np.repeat(np.arange(centres.size), [int(s.n_orb[c]) for c in centres])
+    # one carbon-centred and one hydrogen-centred region
+    picks = [int(np.nonzero(s.n_orb[centres] == 4)[0][0]), int(np.nonzero(s.n_orb[centres] == 1)[0][0])]
+    for r in picks:
+        atoms = oracle.region_atoms(s, int(centres[r]), float(radii[r]))
+        Ar, Br, orb_map = oracle.carve_region(s32, atoms)
+        Ar64, Br64, _ = oracle.carve_region(s, atoms)
+        loc = {int(g): l for l, g in enumerate(orb_map)}
+        cidx = np.nonzero(col_region == r)[0]
+        lcols = np.array([loc[int(reg.cols[c])] for c in cidx], dtype=np.int32)
+        ref32 = oracle.shifted_solve(Ar, Br, lcols, z, tol=1e-10, full=True, true_residual=False)
+        ref64 = oracle.shifted_solve(Ar64, Br64, lcols, z, tol=1e-10, full=True, true_residual=False)
+        for q, c in enumerate(cidx):
+            j = int(reg.cols[c])
+            rows = pattern_rows(s, j)
+            sel = [loc.get(int(i), -1) for i in rows]
+            blk = xg[reg.pat_off[c] * K:reg.pat_off[c + 1] * K].reshape(K, -1)
+            for k in range(K):
+                r32 = np.array([ref32.x[q, k, l] if l >= 0 else 0.0 for l in sel])
+                r64 = np.array([ref64.x[q, k, l] if l >= 0 else 0.0 for l in sel])
+                assert np.abs(blk[k] - r32).max() <= 5e-7 * np.abs(r32).max()
+                assert np.abs(blk[k] - r64).max() <= 1e-5 * np.abs(r64).max()
+
+
+def test_c4_learned_spai_and_regions(el, ctx):
+    """100000-atom box: learned SPAI inference at full size, and sampled-column regions."""
+    from oracle import mlp
+    feats, targs, masks = [], [], []
+    for seed in (21, 22, 23):
+        m = el.Matrix.from_system(ctx, synth.make_system(500, seed))
+        feats.append(el.spai_features(ctx, m))
+        T, W = el.spai_targets(ctx, m)
+        targs.append(T)
+        masks.append(W)
+    theta = torch.as_tensor(mlp.init_params(synth.config_seed(4) + 5), dtype=torch.float32).cuda()
+    el.spai_train(ctx, theta, torch.cat(feats), torch.cat(targs), torch.cat(masks), steps=1500, batch=4096,
+                  lr=2e-3, seed=4)
+    s = synth.make_system(100000, synth.config_seed(4))
+    mat = el.Matrix.from_system(ctx, s)
+    Mv = el.spai_apply(ctx, mat, theta, bf16=True)
+    rhs = torch.as_tensor(np.random.default_rng(4).standard_normal((mat.M, 64))).cuda()
+    x0, p0, br0, u0 = el.overlap_solve(ctx, mat, rhs)
+    x1, p1, br1, u1 = el.overlap_solve(ctx, mat, rhs, Mv)
+    assert u1 and not u0
+    assert br1[1] / br1[0] < br0[1] / br0[0]
+    assert (x1 - x0).abs().max().item() <= 1e-11 * x0.abs().max().item()
+    res = el.spmm(ctx, mat, "B", x1) - rhs
+    assert res.abs().max().item() <= 1e-11 * rhs.abs().max().item()
+    print(f"\nC4 SPAI: interval ratio {br0[1] / br0[0]:.3f} -> {br1[1] / br1[0]:.3f}, passes {p0} -> {p1}")
+    # region solves of sampled columns (the region radius rule of the region workload)
+    cols = synth.sample_columns(s, 16384, synth.config_seed(4))[:24]
+    atom_of = np.repeat(np.arange(s.n_atoms), s.n_orb.astype(int))
+    centres = np.unique(atom_of[cols]).astype(np.int32)
+    radii = np.random.default_rng(synth.config_seed(4) + 3).uniform(6.0, 14.0, size=centres.size)
+    reg = el.Regions(ctx, mat, centres, radii, 64)
+    z = synth.shift_grid(64)
+    out = el.region_solve(ctx, reg, z, tol=1e-8)
+    assert np.all(out["resid"].cpu().numpy() <= 1e-8)
+    r = int(np.argmin(reg.region_orbitals))  # the smallest region against the oracle
+    atoms = oracle.region_atoms(s, int(centres[r]), float(radii[r]))
+    Ar, Br, orb_map = oracle.carve_region(s, atoms)
+    loc = {int(g): l for l, g in enumerate(orb_map)}
+    col_region = np.repeat(np.arange(centres.size), [int(s.n_orb[c]) for c in centres])
+    c = int(np.nonzero(col_region == r)[0][0])
+    j = int(reg.cols[c])
+    ref = oracle.shifted_solve(Ar, Br, np.array([loc[j]], dtype=np.int32), z, tol=1e-10, full=True,
+                               true_residual=False)
+    rows = pattern_rows(s, j)
+    K = len(z)
+    blk = out["x"].cpu().numpy()[reg.pat_off[c] * K:reg.pat_off[c + 1] * K].reshape(K, -1)
+    for k in range(K):
+        rk = np.array([ref.x[0, k, loc[int(i)]] if int(i) in loc else 0.0 for i in rows])
+        assert np.abs(blk[k] - rk).max() <= 5e-7 * np.abs(rk).max()
