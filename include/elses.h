@@ -200,6 +200,46 @@ elses_status elses_time_pass(elses_ctx ctx, elses_mat mat, int32_t kind, int32_t
                              int32_t reps, double *avg_us);
 
 /*
+ * Observables from stored solutions (no new solves).
+ *
+ * Pattern blocks: the pattern P_j of a column j lists, for each atom I
+ * coupled to j's atom (ascending), the orbitals of I.  blk_off (HOST
+ * [n_cols+1]) receives the prefix sums of the number of coupled atoms over
+ * `cols`, blk_atom (HOST, may be NULL) the atom I of each block.
+ */
+elses_status elses_pattern_blocks(elses_mat mat, int32_t n_cols, const int32_t *cols, int64_t *blk_off,
+                                  int32_t *blk_atom);
+/*
+ * Density matrix on the pattern for new weights c (HOST complex [n_shifts])
+ * from solutions x (DEVICE, pattern layout of elses_shifted_solve for the
+ * same cols and shifts): rho_ij = sum_k Im(c_k x_{j,k,i}) (Eq. 12 on the
+ * shifts).  rho_out (DEVICE, pattern layout), col_traces_out (DEVICE
+ * [n_cols][2]: e_j^T rho B e_j, e_j^T rho A e_j, Eq. 7) and traces_out (HOST
+ * [2], their sums) may be NULL.  icohp_out (DEVICE double [blk_off[n_cols]],
+ * may be NULL) receives for every column j and coupled atom I the sum over
+ * I's orbitals alpha of rho_{(I,alpha), j} A_{j, (I,alpha)}: summed over the
+ * orbitals of j's atom J this is the connectivity (ICOHP) C_IJ of the
+ * paper's network analysis (Sec. V-A), whose total over all atom pairs is
+ * the energy Tr[rho A] (Eq. 4).
+ */
+elses_status elses_density_reweight(elses_ctx ctx, elses_mat mat, int32_t n_cols, const int32_t *cols,
+                                    int32_t n_shifts, const double *c, const double *x, double *rho_out,
+                                    double *traces_out, double *col_traces_out, double *icohp_out);
+/*
+ * Chemical potential (Eq. 3): with the Fermi-weighted midpoint rule
+ * c_k = -(1/pi) w_k f(Re z_k; mu, tau) (w HOST [n_shifts] quadrature
+ * widths), bisect mu in [mu_lo, mu_hi] until the interval is below mu_tol so
+ * that sum_j e_j^T rho B e_j over cols equals `target`, re-weighting the
+ * stored solutions x (DEVICE, pattern layout).  mu_out / count_out (HOST)
+ * receive mu and the count there.  The target must lie between the counts
+ * at mu_lo and mu_hi.
+ */
+elses_status elses_chemical_potential(elses_ctx ctx, elses_mat mat, int32_t n_cols, const int32_t *cols,
+                                      int32_t n_shifts, const double *shifts, const double *w, const double *x,
+                                      double tau, double target, double mu_lo, double mu_hi, double mu_tol,
+                                      double *mu_out, double *count_out);
+
+/*
  * Autotuner of the sparse passes.  Times one Richardson step (FP64, or FP32
  * with mixed != 0) for the grouped passes (4, 2 or 1 waves per row group x
  * XCD placements 0, 1, 3) and the direct passes at 256 .. 2048 slots (at most

@@ -107,6 +107,12 @@ def lib():
         for fn in ("elses_spai_pairs", "elses_spai_features", "elses_spai_targets", "elses_mlp_loss_grad",
                    "elses_spai_train", "elses_spai_predict", "elses_spai_apply", "elses_overlap_solve"):
             getattr(L, fn).restype = ctypes.c_int
+        L.elses_pattern_blocks.argtypes = [P, I32, P, P, P]
+        L.elses_pattern_blocks.restype = ctypes.c_int
+        L.elses_density_reweight.argtypes = [P, P, I32, P, I32, P, P, P, P, P, P]
+        L.elses_density_reweight.restype = ctypes.c_int
+        L.elses_chemical_potential.argtypes = [P, P, I32, P, I32, P, P, P, D, D, D, D, D, P, P]
+        L.elses_chemical_potential.restype = ctypes.c_int
         L.elses_autotune.argtypes = [P, P, I32, I32, P, P, P]
         L.elses_autotune.restype = ctypes.c_int
         L.elses_regions_create.argtypes = [P, P, I32, P, P, I32, ctypes.POINTER(P)]
@@ -503,3 +509,47 @@ def autotune(ctx: Context, mat: Matrix, mixed: bool = False, max_slots: int = 0)
     ctx.check(lib().elses_autotune(ctx._h, mat._h, 1 if mixed else 0, max_slots, ctypes.byref(v), ctypes.byref(sl),
                                    ctypes.byref(ns)))
     return v.value, sl.value, ns.value
+
+
+# ---------------------------------------------------------------------------
+# Observables from stored solutions
+# ---------------------------------------------------------------------------
+def pattern_blocks(mat: Matrix, cols):
+    """(blk_off, blk_atom): coupled-atom blocks of each column's pattern."""
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    off = np.zeros(cols.shape[0] + 1, dtype=np.int64)
+    lib().elses_pattern_blocks(mat._h, cols.shape[0], _np_ptr(cols), _np_ptr(off), None)
+    atoms = np.zeros(int(off[-1]), dtype=np.int32)
+    lib().elses_pattern_blocks(mat._h, cols.shape[0], _np_ptr(cols), _np_ptr(off), _np_ptr(atoms))
+    return off, atoms
+
+
+def density_reweight(ctx: Context, mat: Matrix, cols, c, x):
+    """rho, traces, per-column traces and per-(column, coupled atom) ICOHP for weights c from stored x."""
+    torch = _torch()
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    cw = _shifts_ri(c)
+    K = cw.shape[0] // 2
+    pat_off, _ = pattern(mat, cols)
+    blk_off, blk_atom = pattern_blocks(mat, cols)
+    dev = x.device
+    rho = torch.empty(int(pat_off[-1]), dtype=torch.float64, device=dev)
+    ctr = torch.empty(2 * cols.shape[0], dtype=torch.float64, device=dev)
+    ic = torch.empty(int(blk_off[-1]), dtype=torch.float64, device=dev)
+    tr = np.zeros(2)
+    xr = torch.view_as_real(x).contiguous() if x.is_complex() else x
+    ctx.check(lib().elses_density_reweight(ctx._h, mat._h, cols.shape[0], _np_ptr(cols), K, _np_ptr(cw),
+                                           _dev_ptr(xr), _dev_ptr(rho), _np_ptr(tr), _dev_ptr(ctr), _dev_ptr(ic)))
+    return dict(rho=rho, traces=tr, col_traces=ctr.view(-1, 2), icohp=ic, blk_off=blk_off, blk_atom=blk_atom)
+
+
+def chemical_potential(ctx: Context, mat: Matrix, cols, shifts, w, x, tau, target, mu_lo, mu_hi, mu_tol=1e-10):
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    z = _shifts_ri(shifts)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    xr = _torch().view_as_real(x).contiguous() if x.is_complex() else x
+    mu, cnt = ctypes.c_double(), ctypes.c_double()
+    ctx.check(lib().elses_chemical_potential(ctx._h, mat._h, cols.shape[0], _np_ptr(cols), z.shape[0] // 2,
+                                             _np_ptr(z), _np_ptr(w), _dev_ptr(xr), tau, target, mu_lo, mu_hi,
+                                             mu_tol, ctypes.byref(mu), ctypes.byref(cnt)))
+    return mu.value, cnt.value

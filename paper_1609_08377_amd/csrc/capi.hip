@@ -2359,3 +2359,151 @@ elses_status elses_autotune(elses_ctx ctx, elses_mat mat, int32_t mixed, int32_t
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Observables from stored solutions: re-weighting, ICOHP, chemical potential
+// ---------------------------------------------------------------------------
+namespace {
+
+struct ObsLayout {
+    std::vector<int64_t> pat_off, blk_off, pbo;
+    std::vector<int> blk_atom;
+};
+
+const char* obs_layout(const HostMatrix& h, int n_cols, const int32_t* cols, ObsLayout& L) {
+    std::vector<int> orb_atom(h.M);
+    for (int I = 0; I < h.n_atoms; ++I)
+        for (int q = h.atom_off[I]; q < h.atom_off[I + 1]; ++q) orb_atom[q] = I;
+    L.pat_off.assign(1, 0);
+    L.blk_off.assign(1, 0);
+    L.pbo.assign(1, 0);
+    for (int c = 0; c < n_cols; ++c) {
+        if (cols[c] < 0 || cols[c] >= h.M) return "column out of range";
+        const int J = orb_atom[cols[c]];
+        for (int b = h.brow[J]; b < h.brow[J + 1]; ++b) {
+            const int I = h.bcol[b];
+            L.blk_atom.push_back(I);
+            L.pbo.push_back(L.pbo.back() + (h.atom_off[I + 1] - h.atom_off[I]));
+        }
+        L.blk_off.push_back((int64_t)L.blk_atom.size());
+        L.pat_off.push_back(L.pbo.back());
+    }
+    return nullptr;
+}
+
+// Fermi weights of the midpoint rule: c_k = -(1/pi) w_k f(Re z_k)
+void fermi_weights(int K, const double* shifts, const double* w, double mu, double tau, std::vector<double>& cw) {
+    cw.assign(2 * K, 0.0);
+    for (int k = 0; k < K; ++k) {
+        const double t = (shifts[2 * k] - mu) / tau;
+        const double f = t > 0 ? std::exp(-t) / (1.0 + std::exp(-t)) : 1.0 / (1.0 + std::exp(t));
+        cw[2 * k] = -w[k] * f / 3.14159265358979323846;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+elses_status elses_pattern_blocks(elses_mat mat, int32_t n_cols, const int32_t* cols, int64_t* blk_off,
+                                  int32_t* blk_atom) {
+    if (!mat || n_cols < 0 || (n_cols > 0 && !cols) || !blk_off) return ELSES_ERR_INVALID_ARG;
+    ObsLayout L;
+    const char* e = obs_layout(mat->h, n_cols, cols, L);
+    if (e) return set_err(mat->ctx, ELSES_ERR_INVALID_ARG, e);
+    std::copy(L.blk_off.begin(), L.blk_off.end(), blk_off);
+    if (blk_atom) std::copy(L.blk_atom.begin(), L.blk_atom.end(), blk_atom);
+    return ELSES_OK;
+}
+
+elses_status elses_density_reweight(elses_ctx ctx, elses_mat mat, int32_t n_cols, const int32_t* cols,
+                                    int32_t n_shifts, const double* c, const double* x, double* rho_out,
+                                    double* traces_out, double* col_traces_out, double* icohp_out) {
+    if (!ctx || !mat) return ELSES_ERR_INVALID_ARG;
+    if (n_cols < 0 || n_shifts < 1 || !c || (n_cols > 0 && (!cols || !x)))
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "bad arguments");
+    for (int k = 0; k < 2 * n_shifts; ++k)
+        if (!std::isfinite(c[k])) return set_err(ctx, ELSES_ERR_INVALID_ARG, "non-finite weight");
+    if (traces_out) traces_out[0] = traces_out[1] = 0.0;
+    if (n_cols == 0) return ELSES_OK;
+    ObsLayout L;
+    const char* e = obs_layout(mat->h, n_cols, cols, L);
+    if (e) return set_err(ctx, ELSES_ERR_INVALID_ARG, e);
+    hipStream_t st = ctx->stream;
+    const DevMatrix& d = mat->d;
+    try {
+        HCHECK(hipSetDevice(ctx->device));
+        DevPool pool;
+        const int64_t np = L.pat_off.back();
+        int* d_cols = pool.get<int>(n_cols);
+        int64_t* d_pat = pool.get<int64_t>(n_cols + 1);
+        int* d_rows = pool.get<int>(np);
+        int64_t* d_vidx = pool.get<int64_t>(np);
+        int64_t* d_blk = pool.get<int64_t>(L.blk_off.size());
+        int64_t* d_pbo = pool.get<int64_t>(L.pbo.size());
+        double* d_cw = pool.get<double>(2 * n_shifts);
+        double* rho = rho_out ? rho_out : pool.get<double>(np);
+        double* ctr = col_traces_out ? col_traces_out : pool.get<double>(2 * (size_t)n_cols);
+        double* tr2 = pool.get<double>(2);
+        HCHECK(hipMemcpyAsync(d_cols, cols, sizeof(int) * n_cols, hipMemcpyHostToDevice, st));
+        HCHECK(hipMemcpyAsync(d_pat, L.pat_off.data(), sizeof(int64_t) * L.pat_off.size(), hipMemcpyHostToDevice,
+                              st));
+        HCHECK(hipMemcpyAsync(d_blk, L.blk_off.data(), sizeof(int64_t) * L.blk_off.size(), hipMemcpyHostToDevice,
+                              st));
+        HCHECK(hipMemcpyAsync(d_pbo, L.pbo.data(), sizeof(int64_t) * L.pbo.size(), hipMemcpyHostToDevice, st));
+        HCHECK(hipMemcpyAsync(d_cw, c, sizeof(double) * 2 * n_shifts, hipMemcpyHostToDevice, st));
+        launch_pattern_setup(d, n_cols, d_cols, d_pat, d_rows, d_vidx, st);
+        launch_reweight(n_cols, n_shifts, d_cw, d_pat, d_vidx, d_blk, d_pbo, d.B, d.A, x, rho, ctr, icohp_out, st);
+        launch_sum_pairs(ctr, n_cols, tr2, st);
+        double h2[2];
+        HCHECK(hipMemcpyAsync(h2, tr2, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+        HCHECK(hipGetLastError());
+        HCHECK(hipStreamSynchronize(st));
+        if (traces_out) {
+            traces_out[0] = h2[0];
+            traces_out[1] = h2[1];
+        }
+    } catch (const HipFail& f) {
+        return hip_err(ctx, f);
+    }
+    return ELSES_OK;
+}
+
+elses_status elses_chemical_potential(elses_ctx ctx, elses_mat mat, int32_t n_cols, const int32_t* cols,
+                                      int32_t n_shifts, const double* shifts, const double* w, const double* x,
+                                      double tau, double target, double mu_lo, double mu_hi, double mu_tol,
+                                      double* mu_out, double* count_out) {
+    if (!ctx || !mat || !shifts || !w || !mu_out) return ELSES_ERR_INVALID_ARG;
+    if (!(tau > 0.0) || !(mu_hi > mu_lo) || !(mu_tol > 0.0))
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "need tau > 0, mu_hi > mu_lo, mu_tol > 0");
+    std::vector<double> cw;
+    double tr[2] = {0.0, 0.0};
+    auto count = [&](double mu) -> elses_status {
+        fermi_weights(n_shifts, shifts, w, mu, tau, cw);
+        return elses_density_reweight(ctx, mat, n_cols, cols, n_shifts, cw.data(), x, nullptr, tr, nullptr,
+                                      nullptr);
+    };
+    double lo = mu_lo, hi = mu_hi;
+    elses_status s = count(lo);
+    if (s != ELSES_OK) return s;
+    const double n_lo = tr[0];
+    if ((s = count(hi)) != ELSES_OK) return s;
+    const double n_hi = tr[0];
+    if (!(n_lo <= target && target <= n_hi))
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "target electron count is not bracketed by [mu_lo, mu_hi]");
+    // the count tr(rho B) grows with mu: bisection
+    for (int it = 0; it < 200 && hi - lo > mu_tol; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if ((s = count(mid)) != ELSES_OK) return s;
+        if (tr[0] < target)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    *mu_out = 0.5 * (lo + hi);
+    if ((s = count(*mu_out)) != ELSES_OK) return s;
+    if (count_out) *count_out = tr[0];
+    return ELSES_OK;
+}
+
+}  // extern "C"

@@ -280,6 +280,10 @@ void launch_spmm_generic(const DevMatrix &m, const double *vals, int nvec, int l
 void launch_true_residual(const DevMatrix &m, bool fp32_values, int n_cols, const int *cols, int K,
                           const double *z, const double *x_full, double *res_out, hipStream_t st);
 void launch_sum_pairs(const double *v, int n, double *out2, hipStream_t st);
+// rho, per-column traces and per-(column, coupled atom) ICOHP from stored pattern-mode x
+void launch_reweight(int n_cols, int K, const double *cw, const int64_t *pat_off, const int64_t *vidx,
+                     const int64_t *blk_off, const int64_t *pbo, const double *Bv, const double *Av,
+                     const double *x, double *rho, double *ctr, double *icohp, hipStream_t st);
 
 // Partial dot products (deterministic two-stage): out[b] = sum over block b
 void launch_dot_partial(const double *a, const double *b, int n, double *part, int nblocks, hipStream_t st);

@@ -422,3 +422,65 @@ void launch_dot_partial(const double* a, const double* b, int n, double* part, i
 }
 
 }  // namespace elses
+
+namespace elses {
+
+// Re-weighting of stored pattern-mode solutions (one workgroup per column):
+//   rho_ij = sum_k Im(c_k x_{j,k,i}),  i in P_j            (Eq. 12 on the shifts)
+//   e_j^T rho B e_j, e_j^T rho A e_j                        (Eq. 7)
+//   icohp(j, I) = sum_{alpha} rho_{(I,alpha), j} A_{j, (I,alpha)} for each atom I
+//                 coupled to j's atom (the ICOHP of the paper's network
+//                 analysis, before the sum over the orbitals of j's atom)
+// x: column c at pat_off[c] * K complex entries laid out [K][|P_j|].  Block b
+// of the pattern blocks (one per coupled atom, columns in order) covers the
+// pattern entries [pbo[b], pbo[b+1]); column c owns blocks [blk_off[c],
+// blk_off[c+1]).  All sums run in a fixed order.
+__global__ __launch_bounds__(256) void reweight_kernel(int K, const double* __restrict__ cw,
+                                                       const int64_t* __restrict__ pat_off,
+                                                       const int64_t* __restrict__ vidx,
+                                                       const int64_t* __restrict__ blk_off,
+                                                       const int64_t* __restrict__ pbo, const double* __restrict__ Bv,
+                                                       const double* __restrict__ Av, const double* __restrict__ x,
+                                                       double* __restrict__ rho, double* __restrict__ ctr,
+                                                       double* __restrict__ icohp) {
+    __shared__ double sh[16];
+    const int c = blockIdx.x;
+    const int64_t p0 = pat_off[c];
+    const int len = (int)(pat_off[c + 1] - p0);
+    const double* xc = x + p0 * K * 2;
+    double tb = 0.0, ta = 0.0;
+    for (int p = threadIdx.x; p < len; p += blockDim.x) {
+        double r = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const size_t e = ((size_t)k * len + p) * 2;
+            r += cw[2 * k] * xc[e + 1] + cw[2 * k + 1] * xc[e];
+        }
+        rho[p0 + p] = r;
+        const int64_t vi = vidx[p0 + p];
+        tb += r * Bv[vi];
+        ta += r * Av[vi];
+    }
+    tb = block_sum(tb, sh);
+    ta = block_sum(ta, sh);
+    if (threadIdx.x == 0 && ctr) {
+        ctr[2 * (size_t)c] = tb;
+        ctr[2 * (size_t)c + 1] = ta;
+    }
+    __syncthreads();  // rho of this column visible to the whole workgroup
+    if (icohp)
+        for (int64_t b = blk_off[c] + threadIdx.x; b < blk_off[c + 1]; b += blockDim.x) {
+            double h = 0.0;
+            for (int64_t q = pbo[b]; q < pbo[b + 1]; ++q) h += rho[q] * Av[vidx[q]];
+            icohp[b] = h;
+        }
+}
+
+void launch_reweight(int n_cols, int K, const double* cw, const int64_t* pat_off, const int64_t* vidx,
+                     const int64_t* blk_off, const int64_t* pbo, const double* Bv, const double* Av,
+                     const double* x, double* rho, double* ctr, double* icohp, hipStream_t st) {
+    if (n_cols == 0) return;
+    hipLaunchKernelGGL(reweight_kernel, dim3(n_cols), dim3(256), 0, st, K, cw, pat_off, vidx, blk_off, pbo, Bv,
+                       Av, x, rho, ctr, icohp);
+}
+
+}  // namespace elses
