@@ -20,6 +20,10 @@ Contents
 * `carve_region`      principal sub-pencil of the atoms within a radius of a
                       centre atom (real-space projection, Sec. III-B).
 * `dense`             brute-force dense checks (Eqs. 1, 6, 10, 11).
+* `arnoldi`           the multiple Arnoldi method: Rayleigh-Ritz on the
+                      direct sum of two Krylov spaces and the analytic energy
+                      integration (Eqs. 15-18).
+* `mlp`               the learned block sparse approximate inverse of B.
 """
 from __future__ import annotations
 
