@@ -114,6 +114,24 @@ def test_basis_independence():
         np.testing.assert_allclose(r1["w" + w], r2["w" + w], atol=1e-10)
 
 
+def test_block_construction_spans_the_two_krylov_spaces():
+    """The vector-by-vector block construction spans the same space as the union of
+    the two Krylov sequences built separately (orthonormalised by an SVD) when the
+    union is well conditioned."""
+    A, B = pencil(80, 13)
+    for j, nu in ((4, 6), (30, 10)):
+        e = np.eye(80)[:, j]
+        u = np.linalg.solve(B, e)
+        P = np.concatenate([ma.krylov_chain(A, e, nu // 2), ma.krylov_chain(A, u, nu // 2)], axis=1)
+        U, sv, _ = np.linalg.svd(P, full_matrices=False)
+        assert sv[-1] > 1e-6
+        Q = ma.subspace(A, B, j, nu)
+        assert Q.shape[1] == nu
+        np.testing.assert_allclose(Q.T @ Q, np.eye(nu), atol=1e-13)
+        # same span: the projector difference vanishes
+        assert np.abs(Q @ Q.T - U @ U.T).max() < 1e-9
+
+
 @pytest.mark.parametrize("centre,radius", [(0, 2.5), (1, 2.5), (2, 2.0)])
 def test_exhausted_sequences_small_region(c1_system, centre, radius):
     """A region smaller than nu: both sequences exhaust, the result is the dense one."""
