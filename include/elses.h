@@ -368,6 +368,55 @@ elses_status elses_overlap_solve(elses_ctx ctx, elses_mat mat, const double *M_v
 elses_status elses_spmm32(elses_ctx ctx, elses_mat mat, int which, int32_t variant, int32_t nvec, const float *x,
                           float *y);
 
+/*
+ * Multiple Arnoldi method with analytic energy integration (paper Sec. III-B,
+ * Eqs. 15-18).
+ *
+ * For each column j the generalized problem is restricted to the direct sum
+ * of two Krylov spaces of A (Eq. 15):
+ *     L_nu = K_{nu/2}(A; e_j) + K_{nu/2}(A; B^{-1} e_j),   nu even.
+ * Rayleigh-Ritz of the pencil (A, B) on L_nu gives Ritz values eps_m and
+ * B-orthonormal Ritz vectors v_m (m < dim_j <= nu; Eqs. 16-17), and the energy
+ * integral of a projected quantity becomes a finite sum (Eq. 18):
+ *     e_j^T rho X e_j = sum_m f(eps_m) (e_j^T v_m)(v_m^T X e_j).
+ * B^{-1} e_j is the Richardson/Chebyshev overlap solve to inner_tol.  A Krylov
+ * sequence that is exhausted (new direction below 1e-10 of its candidate)
+ * stops early, so dim_j < nu for regions smaller than the subspace.
+ *
+ * Outputs (HOST, each may be NULL), per column in the order given:
+ *   eps [n_cols][nu]  Ritz values, ascending in the first dim_j entries, 0 after;
+ *   w_I, w_B, w_A [n_cols][nu]  (e_j^T v_m)(v_m^T X e_j) for X = I, B, A
+ *                     (0 beyond dim_j): any f then gives Eq. 18 on the host;
+ *   dim [n_cols]      subspace dimension dim_j;
+ *   rho_out           rho_ij = sum_m f(eps_m)(e_i^T v_m)(v_m^T e_j) on the
+ *                     column patterns (layout of elses_density_matrix) for the
+ *                     Fermi function f(eps) = 1 / (1 + exp((eps - mu) / kT))
+ *                     (kT = 0: step, 1/2 at mu);
+ *   col_traces_out [n_cols][2]  e_j^T rho B e_j and e_j^T rho A e_j for that f.
+ * Errors: ELSES_ERR_INVALID_ARG for nu odd or outside [2, 48], kT < 0,
+ * non-finite mu, bad or duplicate columns; ELSES_ERR_OOM when the nu + 5
+ * vector blocks of a batch do not fit.
+ */
+typedef struct {
+    int32_t nu;        /* subspace dimension, even, 2..48 (the paper uses 30); the
+                        * per-column work arrays then fit in 64 KB of LDS */
+    int32_t variant;   /* pass variant as in elses_opts (0: default) */
+    int32_t slots;     /* global solves: columns per batch, multiple of 64 (0: up to 1024) */
+    double inner_tol;  /* overlap solve tolerance for B^{-1} e_j (<= 0: 1e-13) */
+    double mu, kT;     /* Fermi function of rho_out and col_traces_out */
+} elses_arnoldi_opts;
+void elses_arnoldi_opts_default(elses_arnoldi_opts *o);
+/* Global solve: columns cols[n_cols] (HOST, distinct) of the whole pencil. */
+elses_status elses_arnoldi(elses_ctx ctx, elses_mat mat, int32_t n_cols, const int32_t *cols,
+                           const elses_arnoldi_opts *o, double *eps, double *w_I, double *w_B, double *w_A,
+                           int32_t *dim, double *rho_out, double *col_traces_out);
+/* Region solve (real-space projection): every column of a region set on its
+ * region's principal sub-pencil, outputs in the column order of
+ * elses_regions_info (pattern rows outside the region hold 0). */
+elses_status elses_regions_arnoldi(elses_ctx ctx, elses_regions reg, const elses_arnoldi_opts *o, double *eps,
+                                   double *w_I, double *w_B, double *w_A, int32_t *dim, double *rho_out,
+                                   double *col_traces_out);
+
 /* Library version string. */
 const char *elses_version(void);
 

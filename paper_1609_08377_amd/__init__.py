@@ -61,6 +61,11 @@ class Opts(ctypes.Structure):
                 ("audit", ctypes.c_int32), ("variant", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
+class ArnoldiOpts(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_int32), ("variant", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("mu", ctypes.c_double), ("kT", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -123,6 +128,12 @@ def lib():
         L.elses_regions_info.restype = ctypes.c_int
         L.elses_regions_solve.argtypes = [P, P, I32, P, P, ctypes.POINTER(Opts), P, P, P, P, P, P]
         L.elses_regions_solve.restype = ctypes.c_int
+        L.elses_arnoldi_opts_default.argtypes = [ctypes.POINTER(ArnoldiOpts)]
+        L.elses_arnoldi_opts_default.restype = None
+        L.elses_arnoldi.argtypes = [P, P, I32, P, ctypes.POINTER(ArnoldiOpts), P, P, P, P, P, P, P]
+        L.elses_arnoldi.restype = ctypes.c_int
+        L.elses_regions_arnoldi.argtypes = [P, P, ctypes.POINTER(ArnoldiOpts), P, P, P, P, P, P, P]
+        L.elses_regions_arnoldi.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -553,3 +564,53 @@ def chemical_potential(ctx: Context, mat: Matrix, cols, shifts, w, x, tau, targe
                                              _np_ptr(z), _np_ptr(w), _dev_ptr(xr), tau, target, mu_lo, mu_hi,
                                              mu_tol, ctypes.byref(mu), ctypes.byref(cnt)))
     return mu.value, cnt.value
+
+
+# ---------------------------------------------------------------------------
+# Multiple Arnoldi method with analytic energy integration
+# ---------------------------------------------------------------------------
+def _arnoldi_opts(nu, mu, kT, variant, slots, inner_tol) -> ArnoldiOpts:
+    o = ArnoldiOpts()
+    lib().elses_arnoldi_opts_default(ctypes.byref(o))
+    o.nu, o.mu, o.kT = int(nu), float(mu), float(kT)
+    o.variant, o.slots, o.inner_tol = _variant(variant), int(slots), float(inner_tol)
+    return o
+
+
+def _arnoldi_out(n_cols, nu, npat, want_rho):
+    return dict(eps=np.zeros((n_cols, nu)), w_I=np.zeros((n_cols, nu)), w_B=np.zeros((n_cols, nu)),
+                w_A=np.zeros((n_cols, nu)), dim=np.zeros(n_cols, dtype=np.int32),
+                rho=np.zeros(npat) if want_rho else None, col_traces=np.zeros((n_cols, 2)))
+
+
+def arnoldi(ctx: Context, mat: Matrix, cols, nu: int = 30, mu: float = 0.0, kT: float = 0.0, want_rho: bool = False,
+            variant="auto", slots: int = 0, inner_tol: float = 1e-13):
+    """Ritz values and Eq. 18 weights of every column on L_nu (host arrays), rho on the
+    column patterns and e_j^T rho X e_j (X = B, A) for the Fermi function (mu, kT)."""
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    nc = cols.shape[0]
+    off = None
+    if want_rho:
+        off, _ = pattern(mat, cols)
+    out = _arnoldi_out(nc, nu, 0 if off is None else int(off[-1]), want_rho)
+    o = _arnoldi_opts(nu, mu, kT, variant, slots, inner_tol)
+    st = lib().elses_arnoldi(ctx._h, mat._h, nc, _np_ptr(cols), ctypes.byref(o), _np_ptr(out["eps"]),
+                             _np_ptr(out["w_I"]), _np_ptr(out["w_B"]), _np_ptr(out["w_A"]), _np_ptr(out["dim"]),
+                             _np_ptr(out["rho"]), _np_ptr(out["col_traces"]))
+    ctx.check(st)
+    out["pat_off"] = off
+    return out
+
+
+def region_arnoldi(ctx: Context, reg: Regions, nu: int = 30, mu: float = 0.0, kT: float = 0.0,
+                   want_rho: bool = False, variant="auto", inner_tol: float = 1e-13):
+    """The same for every column of a region set, each on its region's sub-pencil."""
+    out = _arnoldi_out(reg.n_cols, nu, int(reg.pat_off[-1]), want_rho)
+    o = _arnoldi_opts(nu, mu, kT, variant, 0, inner_tol)
+    st = lib().elses_regions_arnoldi(ctx._h, reg._h, ctypes.byref(o), _np_ptr(out["eps"]), _np_ptr(out["w_I"]),
+                                     _np_ptr(out["w_B"]), _np_ptr(out["w_A"]), _np_ptr(out["dim"]),
+                                     _np_ptr(out["rho"]), _np_ptr(out["col_traces"]))
+    ctx.check(st)
+    out["pat_off"] = reg.pat_off
+    out["cols"] = reg.cols
+    return out

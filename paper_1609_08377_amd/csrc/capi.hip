@@ -840,6 +840,7 @@ struct elses_regions_s {
     std::vector<int> group_tile;   // tile of each row group of bm (non-decreasing)
     std::vector<int> region_orbs;  // orbitals of each region
     std::vector<int> region_tile;
+    std::vector<int> tile_row0;    // [n_tiles + 1] first row of each tile in bm
     int64_t useful = 0;            // sum over columns of their region's orbitals
     uint64_t* d_mask = nullptr;
     int* d_col_row = nullptr;
@@ -960,6 +961,7 @@ elses_status regions_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, con
     }
     tile_atom0.push_back(atom_base);
     tile_row0.push_back(row_base);
+    P->tile_row0 = tile_row0;
     elses_system bsys{};
     bsys.n_atoms = atom_base;
     bsys.n_orb = bn_orb.data();
@@ -1065,6 +1067,44 @@ elses_status regions_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, con
     return ELSES_OK;
 }
 
+// Slab tables of the grouped passes over region tiles: every slab holds row
+// groups of one tile; chunks of up to 64 slabs of one tile feed the per-tile
+// reductions.  Sets the slab count, mask and tile fields of pa.
+const char* region_slabs(const elses_regions_s* rp, PassArgs& pa, std::vector<int>& slab_group,
+                         std::vector<int>& slab_tile, std::vector<int>& chunk_s0, std::vector<int>& chunk_s1,
+                         std::vector<int>& tile_chunk_off) {
+    if (pa.staged != 9) return "region solves use the grouped passes";
+    const int gpw = kWavesPerBlock / pa.group_split;
+    const int ng = (int)rp->group_tile.size();
+    if (ng == 0) return "region tiles have no row groups";
+    tile_chunk_off.push_back(0);
+    int g = 0;
+    for (int t = 0; t < rp->n_tiles; ++t) {
+        const int g0 = g;
+        while (g < ng && rp->group_tile[g] == t) ++g;
+        const int s0 = (int)slab_tile.size();
+        for (int q = g0; q < g; q += gpw) {
+            for (int i = 0; i < gpw; ++i) slab_group.push_back(q + i < g ? q + i : -1);
+            slab_tile.push_back(t);
+        }
+        const int s1 = (int)slab_tile.size();
+        for (int q = s0; q < s1; q += 64) {
+            chunk_s0.push_back(q);
+            chunk_s1.push_back(std::min(q + 64, s1));
+        }
+        tile_chunk_off.push_back((int)chunk_s0.size());
+    }
+    while (slab_tile.size() % 8 != 0) {
+        for (int i = 0; i < gpw; ++i) slab_group.push_back(-1);
+        slab_tile.push_back(0);
+    }
+    pa.n_slabs = (int)slab_tile.size();
+    pa.n_tiles = pa.n_tiles32 = 1;
+    pa.mask_words = rp->L / 64;
+    pa.mask = rp->d_mask;
+    return nullptr;
+}
+
 elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t* cols, int K,
                         const double* shifts, const double* cw, const elses_opts* opts_in, double* x_out,
                         int32_t* iters_out, double* resid_out, double* rho_out, double* traces_out,
@@ -1136,35 +1176,8 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
     // region tiles: slabs of groups of one tile, chunks of slabs for the reductions
     std::vector<int> slab_group, slab_tile, chunk_s0, chunk_s1, tile_chunk_off;
     if (rp) {
-        if (pa.staged != 9) return set_err(ctx, ELSES_ERR_INVALID_ARG, "region solves use the grouped passes");
-        const int gpw = kWavesPerBlock / pa.group_split;
-            const int ng = (int)rp->group_tile.size();
-        if (ng == 0) return set_err(ctx, ELSES_ERR_INVALID_ARG, "region tiles have no row groups");
-        tile_chunk_off.push_back(0);
-        int g = 0;
-        for (int t = 0; t < rp->n_tiles; ++t) {
-            const int g0 = g;
-            while (g < ng && rp->group_tile[g] == t) ++g;
-            const int s0 = (int)slab_tile.size();
-            for (int q = g0; q < g; q += gpw) {
-                for (int i = 0; i < gpw; ++i) slab_group.push_back(q + i < g ? q + i : -1);
-                slab_tile.push_back(t);
-            }
-            const int s1 = (int)slab_tile.size();
-            for (int q = s0; q < s1; q += 64) {
-                chunk_s0.push_back(q);
-                chunk_s1.push_back(std::min(q + 64, s1));
-            }
-            tile_chunk_off.push_back((int)chunk_s0.size());
-        }
-        while (slab_tile.size() % 8 != 0) {
-            for (int i = 0; i < gpw; ++i) slab_group.push_back(-1);
-            slab_tile.push_back(0);
-        }
-        pa.n_slabs = (int)slab_tile.size();
-        pa.n_tiles = pa.n_tiles32 = 1;
-        pa.mask_words = rp->L / 64;
-        pa.mask = rp->d_mask;
+        const char* rerr = region_slabs(rp, pa, slab_group, slab_tile, chunk_s0, chunk_s1, tile_chunk_off);
+        if (rerr) return set_err(ctx, ELSES_ERR_INVALID_ARG, rerr);
     }
     const int n_groups = pa.n_slabs;
     const int* row_tile = rp ? rp->d_row_tile : nullptr;
@@ -2504,6 +2517,296 @@ elses_status elses_chemical_potential(elses_ctx ctx, elses_mat mat, int32_t n_co
     if ((s = count(*mu_out)) != ELSES_OK) return s;
     if (count_out) *count_out = tr[0];
     return ELSES_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Multiple Arnoldi method with analytic energy integration (Eqs. 15-18)
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kMaChunkRows = 256;
+
+elses_status arnoldi_core(elses_ctx ctx, elses_mat mat, const elses_regions_s* rp, int n_cols, const int32_t* cols,
+                          const elses_arnoldi_opts* o_in, double* eps_out, double* wI_out, double* wB_out,
+                          double* wA_out, int32_t* dim_out, double* rho_out, double* ctr_out) {
+    elses_arnoldi_opts o;
+    elses_arnoldi_opts_default(&o);
+    if (o_in) o = *o_in;
+    const int nu = o.nu;
+    if (nu < 2 || nu > 48 || nu % 2 != 0) return set_err(ctx, ELSES_ERR_INVALID_ARG, "nu must be even and in [2, 48]");
+    if (!std::isfinite(o.mu) || !(o.kT >= 0.0) || !std::isfinite(o.kT))
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "mu must be finite and kT >= 0");
+    if (o.slots < 0 || o.slots % 64 != 0 || o.slots > 65536)
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "slots must be 0 or a multiple of 64 up to 65536");
+    const double inner_tol = o.inner_tol > 0.0 ? o.inner_tol : 1e-13;
+    if (!(inner_tol < 1.0)) return set_err(ctx, ELSES_ERR_INVALID_ARG, "inner_tol must be < 1");
+    if (n_cols < 0) return set_err(ctx, ELSES_ERR_INVALID_ARG, "n_cols < 0");
+    if (n_cols > 0 && !cols) return set_err(ctx, ELSES_ERR_INVALID_ARG, "cols is null");
+    const DevMatrix& gd = mat->d;
+    const DevMatrix& d = rp ? rp->bm->d : mat->d;
+    const HostMatrix& h = mat->h;
+    const int M = d.M;
+    if (!rp) {
+        std::vector<char> seen(gd.M, 0);
+        for (int c = 0; c < n_cols; ++c) {
+            if (cols[c] < 0 || cols[c] >= gd.M) return set_err(ctx, ELSES_ERR_INVALID_ARG, "column out of range");
+            if (seen[cols[c]]) return set_err(ctx, ELSES_ERR_INVALID_ARG, "duplicate column");
+            seen[cols[c]] = 1;
+        }
+    }
+    if (n_cols == 0) return ELSES_OK;
+    // lanes per vector row and segments (a global batch is one segment)
+    const int Lw = rp ? rp->L : (o.slots > 0 ? o.slots : std::min(1024, ((n_cols + 63) / 64) * 64));
+    const int n_seg = rp ? rp->n_tiles : 1;
+    const int NS = n_seg * Lw;
+    PassArgs pa{};
+    const char* verr = configure_pass(d, o.variant, Lw, pa);
+    if (verr) return set_err(ctx, ELSES_ERR_INVALID_ARG, verr);
+    std::vector<int> slab_group, slab_tile, cs0, cs1, tco;
+    if (rp) {
+        const char* rerr = region_slabs(rp, pa, slab_group, slab_tile, cs0, cs1, tco);
+        if (rerr) return set_err(ctx, ELSES_ERR_INVALID_ARG, rerr);
+    }
+    const double* valsA = (pa.staged == 9) ? d.grp.A : d.A;
+    const double* valsB = (pa.staged == 9) ? d.grp.B : d.B;
+    // row chunks inside segments
+    std::vector<int> ch_r0, ch_r1, ch_seg, seg_ch0{0};
+    for (int t = 0; t < n_seg; ++t) {
+        const int r0 = rp ? rp->tile_row0[t] : 0, r1 = rp ? rp->tile_row0[t + 1] : M;
+        for (int r = r0; r < r1; r += kMaChunkRows) {
+            ch_r0.push_back(r);
+            ch_r1.push_back(std::min(r + kMaChunkRows, r1));
+            ch_seg.push_back(t);
+        }
+        seg_ch0.push_back((int)ch_r0.size());
+    }
+    const int n_ch = (int)ch_r0.size();
+    const int Kmax = 4 * nu + 4;
+    const Rich rich = richardson_plan(mat->b_lo, mat->b_hi, inner_tol);
+    // pattern of each column (rows in the matrix of the passes)
+    std::vector<int64_t> row_off(n_cols + 1, 0);
+    if (rp) {
+        row_off = rp->pat_off;
+    } else {
+        std::vector<int> orb_atom(gd.M);
+        for (int I = 0; I < h.n_atoms; ++I)
+            for (int q = h.atom_off[I]; q < h.atom_off[I + 1]; ++q) orb_atom[q] = I;
+        for (int c = 0; c < n_cols; ++c) row_off[c + 1] = row_off[c] + h.atom_plen[orb_atom[cols[c]]];
+    }
+    const bool want_rho = rho_out != nullptr;
+    hipStream_t st = ctx->stream;
+    try {
+        HCHECK(hipSetDevice(ctx->device));
+        DevPool pool;
+        const size_t plane = (size_t)M * Lw;
+        double* W = pool.get<double>(plane * nu);
+        double* Cd = pool.get<double>(plane * 4);  // A W_{2b-2}, A W_{2b-1}, B W_{2b-2}, B W_{2b-1}
+        double* Xr = pool.get<double>(plane);      // Richardson iterate
+        double* Z = pool.get<double>(plane);       // zero
+        HCHECK(hipMemsetAsync(W, 0, sizeof(double) * plane * nu, st));
+        HCHECK(hipMemsetAsync(Cd, 0, sizeof(double) * plane * 4, st));
+        HCHECK(hipMemsetAsync(Xr, 0, sizeof(double) * plane, st));
+        HCHECK(hipMemsetAsync(Z, 0, sizeof(double) * plane, st));
+        double* part = pool.get<double>((size_t)n_ch * Kmax * Lw);
+        double* coef = pool.get<double>((size_t)NS * Kmax);
+        double* Hm = pool.get<double>((size_t)NS * nu * nu);
+        double* Bm = pool.get<double>((size_t)NS * nu * nu);
+        double* stt = pool.get<double>((size_t)NS * 5);
+        unsigned long long* dead = pool.get<unsigned long long>(NS);
+        double* gv = want_rho ? pool.get<double>((size_t)NS * nu) : nullptr;
+        int* tabs = pool.get<int>(3 * (size_t)n_ch + seg_ch0.size());
+        int *d_r0 = tabs, *d_r1 = tabs + n_ch, *d_seg = tabs + 2 * n_ch, *d_sc0 = tabs + 3 * n_ch;
+        HCHECK(hipMemcpyAsync(d_r0, ch_r0.data(), sizeof(int) * n_ch, hipMemcpyHostToDevice, st));
+        HCHECK(hipMemcpyAsync(d_r1, ch_r1.data(), sizeof(int) * n_ch, hipMemcpyHostToDevice, st));
+        HCHECK(hipMemcpyAsync(d_seg, ch_seg.data(), sizeof(int) * n_ch, hipMemcpyHostToDevice, st));
+        HCHECK(hipMemcpyAsync(d_sc0, seg_ch0.data(), sizeof(int) * seg_ch0.size(), hipMemcpyHostToDevice, st));
+        if (rp) {
+            int* d_sg = pool.get<int>(slab_group.size());
+            int* d_stl = pool.get<int>(slab_tile.size());
+            HCHECK(hipMemcpyAsync(d_sg, slab_group.data(), sizeof(int) * slab_group.size(), hipMemcpyHostToDevice, st));
+            HCHECK(hipMemcpyAsync(d_stl, slab_tile.data(), sizeof(int) * slab_tile.size(), hipMemcpyHostToDevice, st));
+            pa.slab_group = d_sg;
+            pa.slab_tile = d_stl;
+        }
+        // column -> slot tables
+        const int n_out = rp ? n_cols : std::min(n_cols, Lw);  // columns per batch
+        int* slot_row = pool.get<int>(NS);
+        int* slot_col = pool.get<int>(NS);
+        int* col_slot = pool.get<int>(n_out);
+        double* d_eps = pool.get<double>((size_t)n_out * nu);
+        double* d_wI = pool.get<double>((size_t)n_out * nu);
+        double* d_wB = pool.get<double>((size_t)n_out * nu);
+        double* d_wA = pool.get<double>((size_t)n_out * nu);
+        int* d_dim = pool.get<int>(n_out);
+        double* d_ctr = pool.get<double>(2 * (size_t)n_out);
+        int* d_rows = nullptr;
+        int64_t* d_pat = nullptr;
+        double* d_rho = nullptr;
+        if (want_rho) {
+            d_pat = rp ? rp->d_pat_off : pool.get<int64_t>(n_cols + 1);
+            d_rows = rp ? rp->d_rows : pool.get<int>((size_t)row_off[n_cols]);
+            d_rho = pool.get<double>((size_t)row_off[n_cols]);
+            if (!rp) {
+                int* d_cols = pool.get<int>(n_cols);
+                int64_t* d_vidx = pool.get<int64_t>((size_t)row_off[n_cols]);
+                HCHECK(hipMemcpyAsync(d_cols, cols, sizeof(int) * n_cols, hipMemcpyHostToDevice, st));
+                HCHECK(hipMemcpyAsync(d_pat, row_off.data(), sizeof(int64_t) * (n_cols + 1), hipMemcpyHostToDevice, st));
+                launch_pattern_setup(gd, n_cols, d_cols, d_pat, d_rows, d_vidx, st);
+            }
+        }
+        auto reduce = [&](int K) { launch_ma_reduce(part, K, Lw, n_seg, d_sc0, coef, st); };
+        auto book = [&](int op, int b, int nq, int K) {
+            launch_ma_book(op, b, nu, nq, K, coef, Hm, Bm, stt, dead, slot_row, NS, st);
+        };
+        auto plain = [&](const double* vals, const double* x, double* y) {
+            pa.vals = vals;
+            pa.Xg = x;
+            pa.Xio = y;
+            launch_pass(PASS_PLAIN, pa, st);
+        };
+        auto Wk = [&](int k) { return W + (size_t)k * plane; };
+        double* C0 = Cd;
+        double* C1 = Cd + plane;
+        for (int c0 = 0; c0 < n_cols; c0 += n_out) {
+            const int nb = std::min(n_out, n_cols - c0);
+            std::vector<int> srow(NS, -1), scol(NS, -1), cslot(n_out, -1);
+            if (rp) {
+                for (int s = 0; s < NS; ++s) {
+                    const int c = rp->slot_map[s];
+                    if (c < 0) continue;
+                    srow[s] = rp->col_row[c];
+                    scol[s] = c;
+                    cslot[c] = s;
+                }
+            } else {
+                for (int c = 0; c < nb; ++c) {
+                    srow[c] = cols[c0 + c];
+                    scol[c] = c;
+                    cslot[c] = c;
+                }
+            }
+            HCHECK(hipMemcpyAsync(slot_row, srow.data(), sizeof(int) * NS, hipMemcpyHostToDevice, st));
+            HCHECK(hipMemcpyAsync(slot_col, scol.data(), sizeof(int) * NS, hipMemcpyHostToDevice, st));
+            HCHECK(hipMemcpyAsync(col_slot, cslot.data(), sizeof(int) * n_out, hipMemcpyHostToDevice, st));
+            HCHECK(hipMemsetAsync(Hm, 0, sizeof(double) * NS * nu * nu, st));
+            HCHECK(hipMemsetAsync(Bm, 0, sizeof(double) * NS * nu * nu, st));
+            HCHECK(hipMemsetAsync(stt, 0, sizeof(double) * NS * 5, st));
+            HCHECK(hipMemsetAsync(dead, 0, sizeof(unsigned long long) * NS, st));
+            HCHECK(hipMemsetAsync(W, 0, sizeof(double) * plane, st));
+            // block 0: W_0 = e_j, candidate u = p(B) e_j (Richardson from x = 0)
+            launch_ma_unit(NS, Lw, slot_row, W, st);
+            pa.vals = valsB;
+            pa.S = W;
+            pa.Xg = Z;
+            pa.Xio = (rich.d % 2 == 1) ? C1 : Xr;
+            pa.tau = rich.g0;
+            launch_pass(PASS_STEP, pa, st);
+            for (int k = 1; k < rich.d; ++k) {
+                double* cur = const_cast<double*>(pa.Xio);
+                pa.Xg = cur;
+                pa.Xio = (cur == C1) ? Xr : C1;
+                pa.tau = rich.tau[k - 1];
+                launch_pass(PASS_STEP, pa, st);
+            }
+            launch_ma_dots(1, C1, plane, W, plane, 1, Lw, n_ch, d_r0, d_r1, part, 2, st);
+            reduce(2);
+            book(MA_BOOK_START, 0, 1, 2);
+            for (int pass = 0; pass < 2; ++pass) {
+                launch_ma_vec(1, C1, W, nullptr, Lw, n_ch, d_r0, d_r1, d_seg, stt + 4, 5, part, st);
+                reduce(2);
+                book(pass == 0 ? MA_BOOK_GAMMA : MA_BOOK_NORM1, 0, 0, 2);
+            }
+            launch_ma_vec(0, Wk(1), C1, C1, Lw, n_ch, d_r0, d_r1, d_seg, stt + 3, 5, part, st);
+            // blocks b = 1 .. nu/2 - 1
+            for (int b = 1; b < nu / 2; ++b) {
+                plain(valsA, Wk(2 * b - 2), C0);
+                plain(valsA, Wk(2 * b - 1), C1);
+                plain(valsB, Wk(2 * b - 2), Cd + 2 * plane);
+                plain(valsB, Wk(2 * b - 1), Cd + 3 * plane);
+                const int nq = 2 * b;
+                const int K1 = 4 * nq + 4, K2 = 2 * nq + 2;
+                launch_ma_dots(4, Cd, plane, W, plane, nq, Lw, n_ch, d_r0, d_r1, part, K1, st);
+                reduce(K1);
+                book(MA_BOOK_FIRST, b, nq, K1);
+                launch_ma_update(2, Cd, plane, W, plane, nq, Lw, n_ch, d_r0, d_r1, d_seg, coef, K1, 0, part, st);
+                launch_ma_dots(2, Cd, plane, W, plane, nq, Lw, n_ch, d_r0, d_r1, part, K2, st);
+                reduce(K2);
+                book(MA_BOOK_SECOND, b, nq, K2);
+                launch_ma_update(2, Cd, plane, W, plane, nq, Lw, n_ch, d_r0, d_r1, d_seg, coef, K2, 1, part, st);
+                reduce(3);
+                book(MA_BOOK_NORM0, b, nq, 3);
+                launch_ma_vec(0, Wk(2 * b), C0, C1, Lw, n_ch, d_r0, d_r1, d_seg, stt + 2, 5, part, st);
+                reduce(2);
+                book(MA_BOOK_GAMMA, b, nq, 2);
+                for (int pass = 0; pass < 2; ++pass) {
+                    launch_ma_vec(1, C1, Wk(2 * b), nullptr, Lw, n_ch, d_r0, d_r1, d_seg, stt + 4, 5, part, st);
+                    reduce(2);
+                    book(pass == 0 ? MA_BOOK_GAMMA : MA_BOOK_NORM1, b, nq, 2);
+                }
+                launch_ma_vec(0, Wk(2 * b + 1), C1, C1, Lw, n_ch, d_r0, d_r1, d_seg, stt + 3, 5, part, st);
+            }
+            // the last two columns of A_r and B_r
+            plain(valsA, Wk(nu - 2), C0);
+            plain(valsA, Wk(nu - 1), C1);
+            plain(valsB, Wk(nu - 2), Cd + 2 * plane);
+            plain(valsB, Wk(nu - 1), Cd + 3 * plane);
+            launch_ma_dots(4, Cd, plane, W, plane, nu, Lw, n_ch, d_r0, d_r1, part, Kmax, st);
+            reduce(Kmax);
+            book(MA_BOOK_LAST, nu / 2, nu, Kmax);
+            launch_ma_eig(NS, nu, Hm, Bm, dead, slot_row, slot_col, W, plane, Lw, o.mu, o.kT, d_eps, d_wI, d_wB, d_wA,
+                          d_dim, gv, d_ctr, st);
+            if (want_rho)
+                launch_ma_rho(nb, d_pat + c0, d_rows, col_slot, gv, nu, W, plane, Lw, d_rho, st);
+            HCHECK(hipGetLastError());
+            const size_t off = (size_t)c0 * nu, cnt = (size_t)nb * nu;
+            if (eps_out) HCHECK(hipMemcpyAsync(eps_out + off, d_eps, sizeof(double) * cnt, hipMemcpyDeviceToHost, st));
+            if (wI_out) HCHECK(hipMemcpyAsync(wI_out + off, d_wI, sizeof(double) * cnt, hipMemcpyDeviceToHost, st));
+            if (wB_out) HCHECK(hipMemcpyAsync(wB_out + off, d_wB, sizeof(double) * cnt, hipMemcpyDeviceToHost, st));
+            if (wA_out) HCHECK(hipMemcpyAsync(wA_out + off, d_wA, sizeof(double) * cnt, hipMemcpyDeviceToHost, st));
+            if (dim_out) HCHECK(hipMemcpyAsync(dim_out + c0, d_dim, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+            if (ctr_out)
+                HCHECK(hipMemcpyAsync(ctr_out + 2 * (size_t)c0, d_ctr, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost,
+                                      st));
+            HCHECK(hipStreamSynchronize(st));
+        }
+        if (want_rho)
+            HCHECK(hipMemcpyAsync(rho_out, d_rho, sizeof(double) * (size_t)row_off[n_cols], hipMemcpyDeviceToHost, st));
+        HCHECK(hipStreamSynchronize(st));
+    } catch (const HipFail& f) {
+        return hip_err(ctx, f);
+    }
+    return ELSES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void elses_arnoldi_opts_default(elses_arnoldi_opts* o) {
+    if (!o) return;
+    o->nu = 30;
+    o->variant = 0;
+    o->slots = 0;
+    o->inner_tol = 1e-13;
+    o->mu = 0.0;
+    o->kT = 0.0;
+}
+
+elses_status elses_arnoldi(elses_ctx ctx, elses_mat mat, int32_t n_cols, const int32_t* cols,
+                           const elses_arnoldi_opts* o, double* eps, double* w_I, double* w_B, double* w_A,
+                           int32_t* dim, double* rho_out, double* col_traces_out) {
+    if (!ctx || !mat) return ELSES_ERR_INVALID_ARG;
+    return arnoldi_core(ctx, mat, nullptr, n_cols, cols, o, eps, w_I, w_B, w_A, dim, rho_out, col_traces_out);
+}
+
+elses_status elses_regions_arnoldi(elses_ctx ctx, elses_regions reg, const elses_arnoldi_opts* o, double* eps,
+                                   double* w_I, double* w_B, double* w_A, int32_t* dim, double* rho_out,
+                                   double* col_traces_out) {
+    if (!ctx || !reg) return ELSES_ERR_INVALID_ARG;
+    return arnoldi_core(ctx, reg->gm, reg, reg->n_cols, reg->cols.data(), o, eps, w_I, w_B, w_A, dim, rho_out,
+                        col_traces_out);
 }
 
 }  // extern "C"

@@ -310,4 +310,28 @@ void launch_infer_bf16(int64_t n, const uint16_t *Wbf, const float *params, cons
 void launch_spai_assemble(int64_t n, const int *pI, const int *pJ, const int *pb, const int *pbt,
                           const DevMatrix &d, const float *out, double *Mv, hipStream_t st);
 
+// Multiple Arnoldi method (arnoldi.hip).  Vector blocks are [rows][Lw]; row
+// chunks (ch_r0, ch_r1, ch_seg) lie inside one segment each, seg_ch0 lists
+// each segment's chunks; partials are [chunk][K][Lw], per-slot results
+// [slot][K] with slot = segment * Lw + lane.
+enum MaBookOp { MA_BOOK_START = 0, MA_BOOK_FIRST, MA_BOOK_SECOND, MA_BOOK_NORM0, MA_BOOK_GAMMA, MA_BOOK_NORM1,
+                MA_BOOK_LAST };
+void launch_ma_dots(int nc, const double *cand, size_t cstride, const double *W, size_t wstride, int nq, int Lw,
+                    int n_chunks, const int *ch_r0, const int *ch_r1, double *part, int K, hipStream_t st);
+void launch_ma_reduce(const double *part, int K, int Lw, int n_seg, const int *seg_ch0, double *out, hipStream_t st);
+void launch_ma_update(int nc, double *cand, size_t cstride, const double *W, size_t wstride, int nq, int Lw,
+                      int n_chunks, const int *ch_r0, const int *ch_r1, const int *ch_seg, const double *coef, int K,
+                      int stats, double *part, hipStream_t st);
+void launch_ma_vec(int op, double *D, const double *X, const double *Y, int Lw, int n_chunks, const int *ch_r0,
+                   const int *ch_r1, const int *ch_seg, const double *s, int s_stride, double *part, hipStream_t st);
+void launch_ma_unit(int n_slots, int Lw, const int *slot_row, double *W0, hipStream_t st);
+void launch_ma_book(int op, int b, int nu, int nq, int K, const double *coef, double *H, double *Br, double *stt,
+                    unsigned long long *dead, const int *slot_row, int n_slots, hipStream_t st);
+void launch_ma_eig(int n_slots, int nu, const double *H, const double *Br, const unsigned long long *dead,
+                   const int *slot_row, const int *slot_col, const double *W, size_t wstride, int Lw, double mu,
+                   double kT, double *eps, double *wI, double *wB, double *wA, int *dim, double *g, double *ctr,
+                   hipStream_t st);
+void launch_ma_rho(int n_cols, const int64_t *pat_off, const int *rows, const int *col_slot, const double *g, int nu,
+                   const double *W, size_t wstride, int Lw, double *rho, hipStream_t st);
+
 }  // namespace elses
