@@ -47,6 +47,8 @@ METRIC = "column×shift solves/sec at 1e-8 rel. residual; SpMV HBM GB/s vs peak"
 
 PASS_SOURCE = os.path.join(ROOT, "paper_1609_08377_amd", "csrc", "passes.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pass_group_step_c2_traffic.md")
+MA_SOURCE = os.path.join(ROOT, "paper_1609_08377_amd", "csrc", "arnoldi.hip")
+MA_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ma_update_regions4096_traffic.md")
 
 WORKLOADS = {
     # name: (n_atoms, n_shifts, description)
@@ -90,20 +92,20 @@ def cpu_baseline(sysm, shifts, gpu_iters_mean: float, budget_s: float = 20.0):
     return {"value": value, "unit": "column-shift solves/s", "cores": nthreads, "kind": "oracle", "sample": sample}
 
 
-def source_digest() -> str:
-    with open(PASS_SOURCE, "rb") as f:
+def source_digest(path: str = PASS_SOURCE) -> str:
+    with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def committed_traffic(kernel_tag: str):
+def committed_traffic(kernel_tag: str, summary: str = TRAFFIC_SUMMARY, source: str = PASS_SOURCE):
     """HBM bytes per launch of the timed kernel from the committed counter summary.
 
     The summary holds lines `traffic <tag> <source digest> <bytes per launch>`;
-    the figure counts only if it was taken on the current pass source."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+    the figure counts only if it was taken on the current kernel source."""
+    if not os.path.exists(summary):
         return None
-    digest = source_digest()
-    with open(TRAFFIC_SUMMARY) as f:
+    digest = source_digest(source)
+    with open(summary) as f:
         for line in f:
             m = re.match(r"^traffic\s+(\S+)\s+(\S+)\s+([0-9.eE+]+)\s*$", line.strip().strip("`"))
             if m and m.group(1) == kernel_tag and m.group(2) == digest:
@@ -121,6 +123,114 @@ def copy_calibration(nbytes: int):
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
                       "launches": 5}), flush=True)
+
+
+def cpu_baseline_arnoldi(sysm, centres, radii, nu, budget_s: float = 15.0):
+    """Time the multiple Arnoldi oracle (region carving + numpy/LAPACK) on a
+    bounded sample of the benchmark's columns."""
+    import oracle
+    from oracle import arnoldi as oma
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = 1
+    rng = np.random.default_rng(11)
+    order = rng.permutation(centres.size)
+    n_cols = 0
+    t0 = time.perf_counter()
+    for i in order:
+        atoms = oracle.region_atoms(sysm, int(centres[i]), float(radii[i]))
+        for q in range(int(sysm.n_orb[centres[i]])):
+            oma.region_column(sysm, atoms, int(sysm.orb_off[centres[i]]) + q, nu)
+            n_cols += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    t = time.perf_counter() - t0
+    return {"value": n_cols / t, "unit": "columns/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_cols} columns of randomly chosen regions of the timed set, one after another "
+                      f"(region carving, block Krylov basis, dense Rayleigh-Ritz) in {t:.1f} s; numpy/LAPACK "
+                      f"with {cores} BLAS threads"}
+
+
+def run_arnoldi(args):
+    """One step = the multiple Arnoldi method (Eqs. 15-18) for every column of a
+    set of kappa-atom regions: the subspace basis, the reduced pencils, the
+    Eq. 18 weights, and rho on the column patterns plus e_j^T rho X e_j."""
+    import ctypes
+
+    import torch
+
+    import synth
+    import paper_1609_08377_amd as el
+
+    n_atoms = WORKLOADS["c3"][0]
+    sysm = synth.make_system(n_atoms, synth.config_seed(3))
+    centres = np.arange(min(args.centres, n_atoms), dtype=np.int32)
+    t_plan = time.perf_counter()
+    radii = synth.kappa_radii(sysm, centres, args.kappa)
+    ctx = el.Context(0)
+    mat = el.Matrix.from_system(ctx, sysm)
+    reg = el.Regions(ctx, mat, centres, radii, args.tile)
+    t_plan = time.perf_counter() - t_plan
+    lib = el.lib()
+    lib.elses_ctx_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.elses_ctx_pass_stats.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 6
+    mu, kT = 0.0, 0.01
+    small = el.Regions(ctx, mat, centres[:8], radii[:8], args.tile)
+    el.region_arnoldi(ctx, small, nu=args.nu, mu=mu, kT=kT, want_rho=True)
+    for w in range(args.warmup):
+        print(f"warmup {w + 1}/{args.warmup}", file=sys.stderr, flush=True)
+        el.region_arnoldi(ctx, reg, nu=args.nu, mu=mu, kT=kT, want_rho=True)
+    lib.elses_ctx_set_profiling(ctx._h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for st in range(args.steps):
+        out = el.region_arnoldi(ctx, reg, nu=args.nu, mu=mu, kT=kT, want_rho=True)
+        print(f"step {st + 1}/{args.steps} done ({reg.n_cols} columns)", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launches, avg_us, nbytes, flops = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    total, slots = ctypes.c_int64(), ctypes.c_int32()
+    lib.elses_ctx_pass_stats(ctx._h, ctypes.byref(launches), ctypes.byref(avg_us), ctypes.byref(nbytes),
+                             ctypes.byref(flops), ctypes.byref(total), ctypes.byref(slots))
+    achieved = nbytes.value / (avg_us.value * 1e-6) / 1e9 if avg_us.value > 0 else 0.0
+    value = reg.n_cols * args.steps / dt
+    ma_tag = f"ma_update_regions{centres.size}"
+    traffic = (committed_traffic(ma_tag, MA_TRAFFIC_SUMMARY, MA_SOURCE)
+               if args.kappa == 100 and args.nu == 30 and args.tile == 64 else None)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_tag": ma_tag,
+            "kernel": "ma_update_kernel<2> (Gram-Schmidt update: 2 candidates minus their projections on the 2b "
+                      "basis vectors)",
+            "bytes_per_launch": nbytes.value, "avg_launch_us": round(avg_us.value, 2),
+            "timed_launches": launches.value}
+    res = {
+        "metric": "multiple-Arnoldi columns/sec (nu=%d, Eq. 18 sums and rho on the column patterns)" % args.nu,
+        "value": round(value, 2), "unit": "columns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * dt / args.steps, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"multiple Arnoldi on {centres.size} regions of {args.kappa} atoms (the centre "
+                               f"atoms are {centres.size} consecutive atoms of the 50000-atom box's Morton order, "
+                               f"a compact sub-volume) of the 50000-atom amorphous hydrocarbon box, all orbitals "
+                               f"of each centre, nu={args.nu}, FP64",
+                   "n_atoms": n_atoms, "regions": int(centres.size), "kappa": args.kappa, "nu": args.nu,
+                   "columns": reg.n_cols, "region_tiles": reg.n_tiles, "tile_width": args.tile,
+                   "tile_rows_total": reg.rows_total,
+                   "useful_lane_fraction": round(reg.useful_rows / (reg.rows_total * args.tile), 4),
+                   "region_orbitals_min_mean_max": [int(reg.region_orbitals.min()),
+                                                    round(float(reg.region_orbitals.mean()), 1),
+                                                    int(reg.region_orbitals.max())],
+                   "subspace_dim_mean": round(float(out["dim"].mean()), 2),
+                   "trace_rhoB_sum": round(float(out["col_traces"][:, 0].sum()), 6),
+                   "region_set_build_s": round(t_plan, 2)},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        print("timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline_arnoldi(sysm, centres, radii, args.nu, args.cpu_budget)
+    print(json.dumps(res), flush=True)
 
 
 def main():
@@ -141,6 +251,11 @@ def main():
     ap.add_argument("--max-outer", type=int, default=20000,
                     help="cap on outer iterations (profiling runs only: capped runs do not converge)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--method", default="shifted", choices=["shifted", "arnoldi"],
+                    help="arnoldi: the multiple Arnoldi method on kappa-atom regions of the 50000-atom box")
+    ap.add_argument("--centres", type=int, default=4096, help="arnoldi: region centres (consecutive atoms)")
+    ap.add_argument("--nu", type=int, default=30, help="arnoldi: subspace dimension")
+    ap.add_argument("--kappa", type=int, default=100, help="arnoldi: atoms per region")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU: sharding the columns over several GPUs "
@@ -149,6 +264,9 @@ def main():
 
     if args.copy_calib:
         copy_calibration(args.copy_calib)
+        return
+    if args.method == "arnoldi":
+        run_arnoldi(args)
         return
 
     import torch

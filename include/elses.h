@@ -178,6 +178,13 @@ elses_status elses_density_matrix(elses_ctx ctx, elses_mat mat, int32_t n_cols, 
  *                  iterate; 8 or 4 bytes per entry)
  *   flops          2 * nnz * slots + 3 * M * slots
  *   total_passes   all passes (A and B products) launched by solves
+ * Multiple Arnoldi calls (elses_arnoldi, elses_regions_arnoldi) sample their
+ * Gram-Schmidt update passes instead (every stride-th launch, one launch per
+ * sample; block b subtracts the projections of two candidates on the 2b basis
+ * vectors so far): bytes = the mean over samples of 2b basis blocks and two
+ * candidate blocks read, two candidate blocks written, the coefficients read
+ * and the partial Gram entries written; flops = 2 (4b [+ 3]) per row and
+ * lane; slots = lanes (segments x lane width).
  */
 elses_status elses_ctx_set_profiling(elses_ctx ctx, int32_t stride);
 elses_status elses_ctx_pass_stats(elses_ctx ctx, int64_t *launches, double *avg_us, double *bytes, double *flops,

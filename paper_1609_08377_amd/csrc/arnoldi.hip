@@ -346,13 +346,14 @@ __global__ void __launch_bounds__(kWave) ma_eig_kernel(MaEig a) {
     const int col = a.slot_col[s];
     if (a.slot_row[s] < 0 || col < 0) return;
     const int nu = a.nu;
-    double* Cm = lds;              // [nu][nu] C, then eigenvalues on the diagonal
-    double* Lm = Cm + nu * nu;     // [nu][nu] Cholesky factor (lower)
-    double* Zm = Lm + nu * nu;     // [nu][nu] Jacobi vectors, then Y
-    double* av = Zm + nu * nu;     // [nu] a_i = (W_i)_j over compact indices
+    const int ldn = nu | 1;        // odd row stride: conflict-free LDS banks for row and column walks
+    double* Cm = lds;              // [nu][ldn] C, then eigenvalues on the diagonal
+    double* Lm = Cm + nu * ldn;    // [nu][ldn] Cholesky factor (lower)
+    double* Zm = Lm + nu * ldn;    // [nu][ldn] Jacobi vectors, then Y
+    double* av = Zm + nu * ldn;    // [nu] a_i = (W_i)_j over compact indices
     double* bv = av + nu;          // [nu] (W^T B e_j)_i
     double* cv = bv + nu;          // [nu] (W^T A e_j)_i
-    double* rot = cv + nu;         // rotation broadcast {c, s, t, flag}
+    double* rot = cv + nu;         // [0..7] scalars, [8..71] rotations, [72..135] f(eps_m) a_m
     __shared__ int idx[64];
     __shared__ int n_sh, perm[64];
     const double* H = a.H + (size_t)s * nu * nu;
@@ -372,8 +373,8 @@ __global__ void __launch_bounds__(kWave) ma_eig_kernel(MaEig a) {
     for (int e = t; e < n * n; e += kWave) {
         const int i = e / n, k = e % n;
         const int ii = idx[i], kk = idx[k];
-        Cm[e] = 0.5 * (H[ii * nu + kk] + H[kk * nu + ii]);
-        Lm[e] = ii <= kk ? Br[ii * nu + kk] : Br[kk * nu + ii];
+        Cm[i * ldn + k] = 0.5 * (H[ii * nu + kk] + H[kk * nu + ii]);
+        Lm[i * ldn + k] = ii <= kk ? Br[ii * nu + kk] : Br[kk * nu + ii];
     }
     if (t < n) {
         const int ii = idx[t];
@@ -385,129 +386,143 @@ __global__ void __launch_bounds__(kWave) ma_eig_kernel(MaEig a) {
     // Cholesky B_r = L L^T in place (lower triangle of Lm)
     for (int j = 0; j < n; ++j) {
         if (t == 0) {
-            double d = Lm[j * n + j];
-            for (int k = 0; k < j; ++k) d -= Lm[j * n + k] * Lm[j * n + k];
-            Lm[j * n + j] = sqrt(fmax(d, 1e-300));
+            double d = Lm[j * ldn + j];
+            for (int k = 0; k < j; ++k) d -= Lm[j * ldn + k] * Lm[j * ldn + k];
+            Lm[j * ldn + j] = sqrt(fmax(d, 1e-300));
         }
         __syncthreads();
         if (t > j && t < n) {
-            double v = Lm[t * n + j];
-            for (int k = 0; k < j; ++k) v -= Lm[t * n + k] * Lm[j * n + k];
-            Lm[t * n + j] = v / Lm[j * n + j];
+            double v = Lm[t * ldn + j];
+            for (int k = 0; k < j; ++k) v -= Lm[t * ldn + k] * Lm[j * ldn + k];
+            Lm[t * ldn + j] = v / Lm[j * ldn + j];
         }
         __syncthreads();
     }
     // X = L^{-1} A_r (thread t: column t), stored in Zm
     if (t < n) {
         for (int i = 0; i < n; ++i) {
-            double v = Cm[i * n + t];
-            for (int k = 0; k < i; ++k) v -= Lm[i * n + k] * Zm[k * n + t];
-            Zm[i * n + t] = v / Lm[i * n + i];
+            double v = Cm[i * ldn + t];
+            for (int k = 0; k < i; ++k) v -= Lm[i * ldn + k] * Zm[k * ldn + t];
+            Zm[i * ldn + t] = v / Lm[i * ldn + i];
         }
     }
     __syncthreads();
     // C = L^{-1} X^T (thread t: column t, from row t of X)
     if (t < n) {
         for (int i = 0; i < n; ++i) {
-            double v = Zm[t * n + i];
-            for (int k = 0; k < i; ++k) v -= Lm[i * n + k] * Cm[k * n + t];
-            Cm[i * n + t] = v / Lm[i * n + i];
+            double v = Zm[t * ldn + i];
+            for (int k = 0; k < i; ++k) v -= Lm[i * ldn + k] * Cm[k * ldn + t];
+            Cm[i * ldn + t] = v / Lm[i * ldn + i];
         }
     }
     __syncthreads();
     for (int e = t; e < n * n; e += kWave) {
         const int i = e / n, k = e % n;
         if (i < k) {
-            const double v = 0.5 * (Cm[i * n + k] + Cm[k * n + i]);
-            Cm[i * n + k] = v;
-            Cm[k * n + i] = v;
+            const double v = 0.5 * (Cm[i * ldn + k] + Cm[k * ldn + i]);
+            Cm[i * ldn + k] = v;
+            Cm[k * ldn + i] = v;
         }
-        Zm[e] = (i == k) ? 1.0 : 0.0;
+        Zm[i * ldn + k] = (i == k) ? 1.0 : 0.0;
     }
     __syncthreads();
-    // cyclic Jacobi; rotations stop below 1e-16 of the Frobenius norm of C
+    // Parallel Jacobi (round-robin ordering): each step rotates up to P/2
+    // disjoint index pairs at once (P = n rounded up to even; pairs with the
+    // padding index are skipped).  C <- J^T C J by a row pass and a column
+    // pass, Z <- Z J.  Rotations stop below 1e-16 of the Frobenius norm of C.
+    double* pc = rot + 8;       // [32] cos
+    double* ps = pc + 32;       // [32] sin
+    __shared__ int pp[32], pq[32];
+    __shared__ int any_rot;
     if (t == 0) {
         double f2 = 0.0;
-        for (int e = 0; e < n * n; ++e) f2 += Cm[e] * Cm[e];
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) f2 += Cm[i * ldn + k] * Cm[i * ldn + k];
         rot[5] = 1e-16 * sqrt(f2);
     }
     __syncthreads();
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        if (t == 0) rot[3] = 0.0;
+    const int P = n + (n & 1);
+    const int npair = P / 2;
+    for (int sweep = 0; sweep < 30 && n > 1; ++sweep) {
+        if (t == 0) any_rot = 0;
         __syncthreads();
-        for (int p = 0; p < n - 1; ++p) {
-            for (int q = p + 1; q < n; ++q) {
+        for (int step = 0; step < P - 1; ++step) {
+            if (t < npair) {
+                int a, b;
                 if (t == 0) {
-                    const double apq = Cm[p * n + q];
-                    const double app = Cm[p * n + p], aqq = Cm[q * n + q];
+                    a = step;
+                    b = P - 1;
+                } else {
+                    a = (step + t) % (P - 1);
+                    b = (step - t + P - 1) % (P - 1);
+                }
+                const int p = min(a, b), q = max(a, b);
+                double c = 1.0, sn = 0.0;
+                if (q < n) {
+                    const double apq = Cm[p * ldn + q];
                     if (fabs(apq) > rot[5]) {
+                        const double app = Cm[p * ldn + p], aqq = Cm[q * ldn + q];
                         const double th = (aqq - app) / (2.0 * apq);
                         const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                        const double c = 1.0 / sqrt(tt * tt + 1.0);
-                        rot[0] = c;
-                        rot[1] = tt * c;
-                        rot[2] = tt;
-                        rot[3] = 1.0;
-                        rot[4] = 1.0;
-                    } else {
-                        rot[4] = 0.0;
+                        c = 1.0 / sqrt(tt * tt + 1.0);
+                        sn = tt * c;
+                        any_rot = 1;
                     }
                 }
-                __syncthreads();
-                if (rot[4] != 0.0) {
-                    const double c = rot[0], sn = rot[1], tt = rot[2];
-                    double cpp = 0.0, cqq = 0.0, apq = 0.0;
-                    if (t == 0) {
-                        apq = Cm[p * n + q];
-                        cpp = Cm[p * n + p] - tt * apq;
-                        cqq = Cm[q * n + q] + tt * apq;
-                    }
-                    if (t < n && t != p && t != q) {
-                        const double gk = Cm[t * n + p], hk = Cm[t * n + q];
-                        const double np_ = c * gk - sn * hk, nq_ = sn * gk + c * hk;
-                        Cm[t * n + p] = np_;
-                        Cm[p * n + t] = np_;
-                        Cm[t * n + q] = nq_;
-                        Cm[q * n + t] = nq_;
-                    }
-                    if (t < n) {
-                        const double zp = Zm[t * n + p], zq = Zm[t * n + q];
-                        Zm[t * n + p] = c * zp - sn * zq;
-                        Zm[t * n + q] = sn * zp + c * zq;
-                    }
-                    __syncthreads();
-                    if (t == 0) {
-                        Cm[p * n + p] = cpp;
-                        Cm[q * n + q] = cqq;
-                        Cm[p * n + q] = 0.0;
-                        Cm[q * n + p] = 0.0;
-                    }
-                    __syncthreads();
-                }
+                pp[t] = p;
+                pq[t] = q;
+                pc[t] = c;
+                ps[t] = (q < n) ? sn : 0.0;
             }
+            __syncthreads();
+            // rows p, q of C (thread t: column t)
+            if (t < n)
+                for (int r = 0; r < npair; ++r) {
+                    const double sn = ps[r];
+                    if (sn == 0.0) continue;
+                    const int p = pp[r], q = pq[r];
+                    const double c = pc[r];
+                    const double x = Cm[p * ldn + t], y = Cm[q * ldn + t];
+                    Cm[p * ldn + t] = c * x - sn * y;
+                    Cm[q * ldn + t] = sn * x + c * y;
+                }
+            __syncthreads();
+            // columns p, q of C and Z (thread t: row t)
+            if (t < n)
+                for (int r = 0; r < npair; ++r) {
+                    const double sn = ps[r];
+                    if (sn == 0.0) continue;
+                    const int p = pp[r], q = pq[r];
+                    const double c = pc[r];
+                    const double x = Cm[t * ldn + p], y = Cm[t * ldn + q];
+                    Cm[t * ldn + p] = c * x - sn * y;
+                    Cm[t * ldn + q] = sn * x + c * y;
+                    const double zx = Zm[t * ldn + p], zy = Zm[t * ldn + q];
+                    Zm[t * ldn + p] = c * zx - sn * zy;
+                    Zm[t * ldn + q] = sn * zx + c * zy;
+                }
+            __syncthreads();
         }
-        __syncthreads();
-        if (rot[3] == 0.0) break;
+        if (any_rot == 0) break;
         __syncthreads();
     }
     // Y = L^{-T} Z (thread t: column t), in place
     if (t < n) {
         for (int i = n - 1; i >= 0; --i) {
-            double v = Zm[i * n + t];
-            for (int k = i + 1; k < n; ++k) v -= Lm[k * n + i] * Zm[k * n + t];
-            Zm[i * n + t] = v / Lm[i * n + i];
+            double v = Zm[i * ldn + t];
+            for (int k = i + 1; k < n; ++k) v -= Lm[k * ldn + i] * Zm[k * ldn + t];
+            Zm[i * ldn + t] = v / Lm[i * ldn + i];
         }
     }
-    if (t == 0) {
-        for (int m = 0; m < n; ++m) perm[m] = m;
-        for (int m = 0; m < n; ++m) {
-            int best = m;
-            for (int k = m + 1; k < n; ++k)
-                if (Cm[perm[k] * n + perm[k]] < Cm[perm[best] * n + perm[best]]) best = k;
-            const int tmp = perm[m];
-            perm[m] = perm[best];
-            perm[best] = tmp;
+    // ascending order of the eigenvalues: perm[rank] = index (ties by index)
+    if (t < n) {
+        const double e = Cm[t * ldn + t];
+        int rank = 0;
+        for (int k = 0; k < n; ++k) {
+            const double f = Cm[k * ldn + k];
+            rank += (f < e || (f == e && k < t)) ? 1 : 0;
         }
+        perm[rank] = t;
     }
     __syncthreads();
     double fw = 0.0, trB = 0.0, trA = 0.0;
@@ -515,10 +530,10 @@ __global__ void __launch_bounds__(kWave) ma_eig_kernel(MaEig a) {
     if (t < nu) {
         if (t < n) {
             const int m = perm[t];
-            const double e = Cm[m * n + m];
+            const double e = Cm[m * ldn + m];
             double am = 0.0, bm = 0.0, cm = 0.0;
             for (int i = 0; i < n; ++i) {
-                const double y = Zm[i * n + m];
+                const double y = Zm[i * ldn + m];
                 am = fma(av[i], y, am);
                 bm = fma(bv[i], y, bm);
                 cm = fma(cv[i], y, cm);
@@ -530,7 +545,7 @@ __global__ void __launch_bounds__(kWave) ma_eig_kernel(MaEig a) {
             fw = ma_fermi(e, a.mu, a.kT);
             trB = fw * am * bm;
             trA = fw * am * cm;
-            rot[8 + t] = fw * am;  // f(eps_m) a_m by sorted position
+            rot[72 + t] = fw * am;  // f(eps_m) a_m by sorted position
         } else {
             a.eps[o + t] = 0.0;
             a.wI[o + t] = 0.0;
@@ -547,7 +562,7 @@ __global__ void __launch_bounds__(kWave) ma_eig_kernel(MaEig a) {
         for (int i = 0; i < n; ++i)
             if (idx[i] == t) ci = i;
         if (ci >= 0)
-            for (int k = 0; k < n; ++k) v = fma(Zm[ci * n + perm[k]], rot[8 + k], v);
+            for (int k = 0; k < n; ++k) v = fma(Zm[ci * ldn + perm[k]], rot[72 + k], v);
         a.g[(size_t)s * nu + t] = v;
     }
     if (a.ctr) {
@@ -635,7 +650,7 @@ void launch_ma_eig(int n_slots, int nu, const double* H, const double* Br, const
                    double kT, double* eps, double* wI, double* wB, double* wA, int* dim, double* g, double* ctr,
                    hipStream_t st) {
     MaEig a{nu, H, Br, dead, slot_row, slot_col, W, wstride, Lw, mu, kT, eps, wI, wB, wA, dim, g, ctr};
-    const size_t lds = sizeof(double) * (3 * (size_t)nu * nu + 3 * nu + 8 + 64);
+    const size_t lds = sizeof(double) * (3 * (size_t)nu * (nu | 1) + 3 * nu + 72 + 64);
     hipLaunchKernelGGL(ma_eig_kernel, dim3(n_slots), dim3(kWave), lds, st, a);
 }
 

@@ -2669,6 +2669,37 @@ elses_status arnoldi_core(elses_ctx ctx, elses_mat mat, const elses_regions_s* r
         auto Wk = [&](int k) { return W + (size_t)k * plane; };
         double* C0 = Cd;
         double* C1 = Cd + plane;
+        // Sampled event timing of the Gram-Schmidt update passes (two per
+        // block: both candidates minus their projections on the 2b basis
+        // vectors so far), the kernel with the largest share of the time.
+        struct EvList : std::vector<std::pair<hipEvent_t, hipEvent_t>> {
+            ~EvList() {
+                for (auto& e : *this) {
+                    (void)hipEventDestroy(e.first);
+                    (void)hipEventDestroy(e.second);
+                }
+            }
+        } evs;
+        double s_bytes = 0.0, s_flops = 0.0;
+        int64_t n_upd = 0;
+        auto update = [&](int nq, int K, int stats) {
+            const bool timed = ctx->prof_stride > 0 && (n_upd++ % ctx->prof_stride) == 0;
+            if (timed) {
+                evs.emplace_back(nullptr, nullptr);
+                HCHECK(hipEventCreate(&evs.back().first));
+                HCHECK(hipEventCreate(&evs.back().second));
+                HCHECK(hipEventRecord(evs.back().first, st));
+            }
+            launch_ma_update(2, Cd, plane, W, plane, nq, Lw, n_ch, d_r0, d_r1, d_seg, coef, K, stats, part, st);
+            if (timed) {
+                HCHECK(hipEventRecord(evs.back().second, st));
+                // read nq basis + 2 candidate blocks, write 2 candidate blocks,
+                // coefficients, partial Gram entries
+                s_bytes += (double)(nq + 4) * plane * 8.0 + (double)n_ch * Lw * 2.0 * nq * 8.0 +
+                           (stats ? (double)n_ch * 3 * Lw * 8.0 : 0.0);
+                s_flops += 2.0 * (2.0 * nq + (stats ? 3.0 : 0.0)) * (double)plane;
+            }
+        };
         for (int c0 = 0; c0 < n_cols; c0 += n_out) {
             const int nb = std::min(n_out, n_cols - c0);
             std::vector<int> srow(NS, -1), scol(NS, -1), cslot(n_out, -1);
@@ -2730,11 +2761,11 @@ elses_status arnoldi_core(elses_ctx ctx, elses_mat mat, const elses_regions_s* r
                 launch_ma_dots(4, Cd, plane, W, plane, nq, Lw, n_ch, d_r0, d_r1, part, K1, st);
                 reduce(K1);
                 book(MA_BOOK_FIRST, b, nq, K1);
-                launch_ma_update(2, Cd, plane, W, plane, nq, Lw, n_ch, d_r0, d_r1, d_seg, coef, K1, 0, part, st);
+                update(nq, K1, 0);
                 launch_ma_dots(2, Cd, plane, W, plane, nq, Lw, n_ch, d_r0, d_r1, part, K2, st);
                 reduce(K2);
                 book(MA_BOOK_SECOND, b, nq, K2);
-                launch_ma_update(2, Cd, plane, W, plane, nq, Lw, n_ch, d_r0, d_r1, d_seg, coef, K2, 1, part, st);
+                update(nq, K2, 1);
                 reduce(3);
                 book(MA_BOOK_NORM0, b, nq, 3);
                 launch_ma_vec(0, Wk(2 * b), C0, C1, Lw, n_ch, d_r0, d_r1, d_seg, stt + 2, 5, part, st);
@@ -2774,6 +2805,17 @@ elses_status arnoldi_core(elses_ctx ctx, elses_mat mat, const elses_regions_s* r
         if (want_rho)
             HCHECK(hipMemcpyAsync(rho_out, d_rho, sizeof(double) * (size_t)row_off[n_cols], hipMemcpyDeviceToHost, st));
         HCHECK(hipStreamSynchronize(st));
+        if (!evs.empty()) {
+            for (auto& e : evs) {
+                float ms = 0.f;
+                HCHECK(hipEventElapsedTime(&ms, e.first, e.second));
+                ctx->prof_ms += ms;
+            }
+            ctx->prof_launches += (int64_t)evs.size();
+            ctx->prof_bytes = s_bytes / (double)evs.size();
+            ctx->prof_flops = s_flops / (double)evs.size();
+            ctx->prof_slots = NS;
+        }
     } catch (const HipFail& f) {
         return hip_err(ctx, f);
     }

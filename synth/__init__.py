@@ -264,6 +264,59 @@ def sample_regions(sysm: System, n_regions: int, seed: int, r_lo: float = 6.0,
     return centres, radii
 
 
+def kappa_radii(sysm: System, centres: np.ndarray, kappa: int) -> np.ndarray:
+    """Radius of each centre's sphere that holds its kappa nearest atoms (the
+    centre included; minimum-image distances): the midpoint between the
+    kappa-th and (kappa+1)-th nearest distances, so the sphere holds exactly
+    kappa atoms unless distances tie.  Cell lists (side >= 1.25 x the radius
+    that kappa + 1 atoms need at the mean density) keep this linear in the
+    number of centres; a centre whose (kappa+1)-th neighbour is not surely
+    inside its 27 cells falls back to all atoms."""
+    centres = np.asarray(centres, dtype=np.int64)
+    L = float(sysm.L)
+    pos = np.mod(sysm.pos, L)
+    dens = sysm.n_atoms / L ** 3
+    r_need = (3.0 * (kappa + 1) / (4.0 * np.pi * dens)) ** (1.0 / 3.0)
+    nc = int(L // (1.25 * r_need))
+    out = np.empty(centres.size)
+
+    def kth(cidx, cand):
+        d = pos[cand][None, :, :] - pos[cidx][:, None, :]
+        d -= L * np.rint(d / L)
+        r = np.sqrt((d * d).sum(-1))
+        part = np.partition(r, (kappa - 1, kappa), axis=1)
+        return part[:, kappa - 1], part[:, kappa]
+
+    if nc < 3 or sysm.n_atoms <= kappa + 1:
+        for i0 in range(0, centres.size, 256):
+            a, b = kth(centres[i0:i0 + 256], np.arange(sysm.n_atoms))
+            out[i0:i0 + 256] = 0.5 * (a + b)
+        return out
+    side = L / nc
+    cell = np.minimum((pos / side).astype(np.int64), nc - 1)
+    key = (cell[:, 0] * nc + cell[:, 1]) * nc + cell[:, 2]
+    order = np.argsort(key, kind="stable")
+    start = np.searchsorted(key[order], np.arange(nc ** 3 + 1))
+    ckey = key[centres]
+    for k in np.unique(ckey):
+        sel = np.nonzero(ckey == k)[0]
+        cx, cy, cz = k // (nc * nc), (k // nc) % nc, k % nc
+        ids = [order[start[q]:start[q + 1]]
+               for q in ((((cx + dx) % nc) * nc + (cy + dy) % nc) * nc + (cz + dz) % nc
+                         for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1))]
+        cand = np.concatenate(ids)
+        if cand.size > kappa:
+            a, b = kth(centres[sel], cand)
+        else:
+            a = b = np.full(sel.size, np.inf)
+        bad = ~(b <= side)  # beyond one cell side the 27 cells may miss nearer atoms
+        if bad.any():
+            a2, b2 = kth(centres[sel[bad]], np.arange(sysm.n_atoms))
+            a[bad], b[bad] = a2, b2
+        out[sel] = 0.5 * (a + b)
+    return out
+
+
 def config_seed(cfg_index: int) -> int:
     """Base seed of configuration i (1-based): 1000 + i."""
     return 1000 + cfg_index
