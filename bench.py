@@ -233,6 +233,87 @@ def run_arnoldi(args):
     print(json.dumps(res), flush=True)
 
 
+def tile_idle(sysm, centres, iters, L):
+    """Idle share of the lane-iterations of region tiles: consecutive regions fill
+    tiles of L column slots, a tile runs until its slowest column converges, and a
+    lane whose column has converged waits (region tiles have no refill)."""
+    it = np.asarray(iters, dtype=np.float64)
+    busy = lanes = 0.0
+    c = used = 0
+    tile = []
+    for cen in centres:
+        nc = int(sysm.n_orb[cen])
+        if used + nc > L:
+            t = it[tile]
+            busy += t.sum()
+            lanes += t.size * t.max()
+            tile, used = [], 0
+        tile.extend(range(c, c + nc))
+        c += nc
+        used += nc
+    if tile:
+        t = it[tile]
+        busy += t.sum()
+        lanes += t.size * t.max()
+    return 1.0 - busy / lanes
+
+
+def run_balance(args):
+    """Ordered against disordered input (the paper's ideal diamond crystal against
+    its amorphous polymers, Table II): the same region-mode shifted solve on
+    kappa-atom regions of each, and the share of idle lane-iterations in the
+    region tiles, the analogue of the barrier time the paper attributes to load
+    imbalance (0.014 of the elapsed time for the crystal, 0.19 for the polymer)."""
+    import torch
+
+    import synth
+    import paper_1609_08377_amd as el
+
+    z = synth.shift_grid(64)
+    cw = (-(1.0 / np.pi) * (2.0 / 64) * 0.5 * (1.0 - np.tanh(0.5 * (z.real - 0.0) / 0.01))).astype(np.complex128)
+    ctx = el.Context(0)
+    cases = {}
+    for name, make in (("amorphous", lambda: synth.make_system(WORKLOADS["c3"][0], synth.config_seed(3))),
+                       ("diamond", lambda: synth.make_diamond(18, synth.config_seed(6)))):
+        sysm = make()
+        n_cen = args.centres if name == "amorphous" else max(1, args.centres // 2)
+        centres = np.arange(min(n_cen, sysm.n_atoms), dtype=np.int32)
+        radii = synth.kappa_radii(sysm, centres, args.kappa)
+        mat = el.Matrix.from_system(ctx, sysm)
+        reg = el.Regions(ctx, mat, centres, radii, args.tile)
+        small = el.Regions(ctx, mat, centres[:4], radii[:4], args.tile)
+        el.region_solve(ctx, small, z, cw, want_x=False, max_outer=16, allow_not_converged=True)
+        torch.cuda.synchronize()
+        print(f"{name}: solving {reg.n_cols} columns", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        out = el.region_solve(ctx, reg, z, cw, want_x=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        iters = out["iters"].cpu().numpy()
+        idle = tile_idle(sysm, centres, iters, args.tile)
+        cases[name] = {"atoms": int(sysm.n_atoms), "regions": int(centres.size), "columns": int(reg.n_cols),
+                       "region_orbitals_min_max": [int(reg.region_orbitals.min()), int(reg.region_orbitals.max())],
+                       "outer_iters_min_mean_max": [int(iters.min()), round(float(iters.mean()), 1),
+                                                    int(iters.max())],
+                       "idle_lane_fraction": round(idle, 4), "solve_s": round(dt, 3),
+                       "column_shift_solves_per_s": round(reg.n_cols * 64 / dt, 1)}
+        del reg, small, mat
+    res = {"metric": "idle share of region-tile lane-iterations (load imbalance), amorphous vs diamond",
+           "value": cases["amorphous"]["idle_lane_fraction"], "unit": "fraction", "n_gpus": 1, "steps": 1,
+           "warmup": 0, "ms_per_step": round(1000.0 * cases["amorphous"]["solve_s"], 1),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"region-mode shifted solves (64 shifts, tol 1e-8, FP64) on {args.kappa}-atom "
+                                  f"regions around consecutive (Morton-order) atoms of the 50000-atom amorphous box "
+                                  f"and of a 46656-atom ideal diamond crystal, {args.tile}-lane tiles",
+                      "kappa": args.kappa, "tile_width": args.tile, "disordered": cases["amorphous"],
+                      "ordered": cases["diamond"],
+                      "idle_ratio_disordered_over_ordered": round(
+                          cases["amorphous"]["idle_lane_fraction"] /
+                          max(cases["diamond"]["idle_lane_fraction"], 1e-12), 2)}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,8 +332,9 @@ def main():
     ap.add_argument("--max-outer", type=int, default=20000,
                     help="cap on outer iterations (profiling runs only: capped runs do not converge)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--method", default="shifted", choices=["shifted", "arnoldi"],
-                    help="arnoldi: the multiple Arnoldi method on kappa-atom regions of the 50000-atom box")
+    ap.add_argument("--method", default="shifted", choices=["shifted", "arnoldi", "balance"],
+                    help="arnoldi: the multiple Arnoldi method on kappa-atom regions of the 50000-atom box; "
+                         "balance: idle lanes of region tiles, amorphous box against a diamond crystal")
     ap.add_argument("--centres", type=int, default=4096, help="arnoldi: region centres (consecutive atoms)")
     ap.add_argument("--nu", type=int, default=30, help="arnoldi: subspace dimension")
     ap.add_argument("--kappa", type=int, default=100, help="arnoldi: atoms per region")
@@ -267,6 +349,9 @@ def main():
         return
     if args.method == "arnoldi":
         run_arnoldi(args)
+        return
+    if args.method == "balance":
+        run_balance(args)
         return
 
     import torch

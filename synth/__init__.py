@@ -188,6 +188,16 @@ def make_system(n_atoms: int, seed: int, r_cut: float = R_CUT, density: float = 
     blkA = gA * decay[:, None, None]
     blkB = b_scale * gB * decay[:, None, None]
 
+    sysm = _assemble(n_atoms, n_c, L, pos, n_orb, orb_off, pi, pj, blkA, blkB, gA_site, seed)
+    sysm.extra["pairs"] = (pi, pj, pr, pd)
+    return sysm
+
+
+def _assemble(n_atoms, n_c, L, pos, n_orb, orb_off, pi, pj, blkA, blkB, gA_site, seed) -> System:
+    """Atom-block rows (diagonal + both directions of every pair, sorted by column)
+    from per-pair 4 x 4 blocks (top-left n_I x n_J used for the stored (I, J), I < J;
+    the mirrored (J, I) block is its transpose), on-site A = diag(gA_site), B = I."""
+    npair = pi.shape[0]
     # full block rows: diagonal + both directions, sorted by column
     rows = np.concatenate([np.arange(n_atoms, dtype=np.int32), pi, pj])
     cols = np.concatenate([np.arange(n_atoms, dtype=np.int32), pj, pi])
@@ -233,10 +243,67 @@ def make_system(n_atoms: int, seed: int, r_cut: float = R_CUT, density: float = 
             offs = base[:, None] + np.arange(ni * nj)[None, :]
             A_val[offs] = va.reshape(sel.size, ni * nj)
             B_val[offs] = vb.reshape(sel.size, ni * nj)
-    sysm = System(n_atoms=n_atoms, n_c=n_c, L=L, pos=pos, n_orb=n_orb, orb_off=orb_off,
+    return System(n_atoms=n_atoms, n_c=n_c, L=L, pos=pos, n_orb=n_orb, orb_off=orb_off,
                   blk_row_ptr=blk_row_ptr, blk_col=cols.astype(np.int32), val_ptr=val_ptr,
                   A_val=A_val, B_val=B_val, seed=seed)
+
+
+DIAMOND_A = 3.567      # cubic lattice constant of diamond, Angstrom
+DIAMOND_RCUT = 2.6459  # 5 bohr: first and second neighbours (1.545 and 2.522 A)
+
+
+def make_diamond(n_cells: int, seed: int, r_cut: float = DIAMOND_RCUT, b_scale: float = 0.1) -> System:
+    """Ideal periodic diamond crystal of n_cells^3 conventional cells (8 carbon
+    atoms, 4 orbitals each), the ordered counterpart of the amorphous boxes.
+
+    Values follow make_system's rule, A = exp(-r/1.5) g and B = 0.1 exp(-r/1.5) g
+    off site, except that the random factors g are drawn once and shared: one
+    symmetric 4 x 4 factor for every A pair, one for every B pair, and one set of
+    four on-site factors for every atom.  Every atom is then equivalent to every
+    other under the crystal's translations and its inversion through bond
+    centres, so all atoms' subproblems are the same.  Atoms are numbered along a
+    Morton curve as in make_system."""
+    if n_cells < 2:
+        raise ValueError("need at least 2 cells per side for the minimum image at the diamond cutoff")
+    lib = _geom()
+    fcc = np.array([[0, 0, 0], [0, 0.5, 0.5], [0.5, 0, 0.5], [0.5, 0.5, 0]])
+    basis = np.concatenate([fcc, fcc + 0.25])
+    cells = np.stack(np.meshgrid(*(np.arange(n_cells),) * 3, indexing="ij"), -1).reshape(-1, 3)
+    pos = ((cells[:, None, :] + basis[None, :, :]).reshape(-1, 3) * DIAMOND_A).astype(np.float64)
+    n_atoms = pos.shape[0]
+    L = n_cells * DIAMOND_A
+    g = max(1, int(L // 2.0))
+    cell = np.minimum((pos / (L / g)).astype(np.int64), g - 1)
+    order = np.lexsort((np.arange(n_atoms), _morton3(cell[:, 0], cell[:, 1], cell[:, 2])))
+    pos = np.ascontiguousarray(pos[order])
+    n_orb = np.full(n_atoms, 4, dtype=np.int8)
+    orb_off = np.arange(n_atoms + 1, dtype=np.int64) * 4
+    cnt = np.zeros(n_atoms, dtype=np.int64)
+    if lib.count_pairs(n_atoms, _ptr(pos), L, r_cut, _ptr(cnt)) != 0:
+        raise RuntimeError("count_pairs failed")
+    off = np.zeros(n_atoms + 1, dtype=np.int64)
+    np.cumsum(cnt, out=off[1:])
+    npair = int(off[-1])
+    pj = np.zeros(npair, dtype=np.int32)
+    pr = np.zeros(npair, dtype=np.float64)
+    pd = np.zeros((npair, 3), dtype=np.float64)
+    if lib.fill_pairs(n_atoms, _ptr(pos), L, r_cut, _ptr(off), _ptr(pj), _ptr(pr), _ptr(pd)) != 0:
+        raise RuntimeError("fill_pairs failed")
+    pi = np.repeat(np.arange(n_atoms, dtype=np.int32), cnt)
+    rngA = np.random.Generator(np.random.PCG64(seed + 1))
+    rngB = np.random.Generator(np.random.PCG64(seed + 2))
+    FA = rngA.normal(1.0, 0.1, size=(4, 4))
+    FA = 0.5 * (FA + FA.T)
+    site = rngA.normal(1.0, 0.1, size=4)
+    FB = rngB.normal(1.0, 0.1, size=(4, 4))
+    FB = 0.5 * (FB + FB.T)
+    decay = np.exp(-pr / DECAY)
+    blkA = FA[None, :, :] * decay[:, None, None]
+    blkB = b_scale * FB[None, :, :] * decay[:, None, None]
+    sysm = _assemble(n_atoms, n_atoms, L, pos, n_orb, orb_off, pi, pj, blkA, blkB,
+                     np.broadcast_to(site, (n_atoms, 4)), seed)
     sysm.extra["pairs"] = (pi, pj, pr, pd)
+    sysm.extra["lattice"] = "diamond"
     return sysm
 
 
@@ -268,7 +335,7 @@ def kappa_radii(sysm: System, centres: np.ndarray, kappa: int) -> np.ndarray:
     """Radius of each centre's sphere that holds its kappa nearest atoms (the
     centre included; minimum-image distances): the midpoint between the
     kappa-th and (kappa+1)-th nearest distances, so the sphere holds exactly
-    kappa atoms unless distances tie.  Cell lists (side >= 1.25 x the radius
+    kappa atoms unless distances tie (then the whole tied shell: kappa or more).  Cell lists (side >= 1.25 x the radius
     that kappa + 1 atoms need at the mean density) keep this linear in the
     number of centres; a centre whose (kappa+1)-th neighbour is not surely
     inside its 27 cells falls back to all atoms."""
@@ -290,7 +357,7 @@ def kappa_radii(sysm: System, centres: np.ndarray, kappa: int) -> np.ndarray:
     if nc < 3 or sysm.n_atoms <= kappa + 1:
         for i0 in range(0, centres.size, 256):
             a, b = kth(centres[i0:i0 + 256], np.arange(sysm.n_atoms))
-            out[i0:i0 + 256] = 0.5 * (a + b)
+            out[i0:i0 + 256] = _kappa_cut(a, b)
         return out
     side = L / nc
     cell = np.minimum((pos / side).astype(np.int64), nc - 1)
@@ -313,8 +380,14 @@ def kappa_radii(sysm: System, centres: np.ndarray, kappa: int) -> np.ndarray:
         if bad.any():
             a2, b2 = kth(centres[sel[bad]], np.arange(sysm.n_atoms))
             a[bad], b[bad] = a2, b2
-        out[sel] = 0.5 * (a + b)
+        out[sel] = _kappa_cut(a, b)
     return out
+
+
+def _kappa_cut(a, b):
+    """Midpoint of the kappa-th and (kappa+1)-th distances; when they tie (a
+    crystal shell) the whole shell is taken, robustly against rounding."""
+    return np.where(b - a > 1e-9, 0.5 * (a + b), b + 1e-9)
 
 
 def config_seed(cfg_index: int) -> int:
