@@ -57,6 +57,8 @@ WORKLOADS = {
     "c2": (4096, 64, "4096-atom amorphous hydrocarbon box (C:H=1:2, 1.0 g/cm^3), M=8191 (4x4/4x1/1x1 atom "
                      "blocks, ~71 nnz/row), all 8191 columns x 64 shifts z=eps_k+0.01i on [-1,1] Ha, FP64, "
                      "tol 1e-8, global"),
+    "c5": (1000000, 128, "one-GPU share of a 10^6-atom amorphous hydrocarbon box (M=2.0e6, FP32-stored A and "
+                         "B), the FP32 Richardson pass of the overlap solve on a block of right-hand sides"),
     "c3": (50000, 64, "2048 local regions (centre atoms sampled without replacement, radius U[6,14] A, "
                       "187-3079 orbitals) carved from a 50000-atom amorphous hydrocarbon box (M=100001), all "
                       "orbitals of each centre x 64 shifts, packed into tiles and advanced by one launch "
@@ -314,6 +316,49 @@ def run_balance(args):
     print(json.dumps(res), flush=True)
 
 
+def run_pass(args):
+    """The sparse pass alone at a workload's full matrix size: the Richardson step
+    of the overlap solve (FP32-stored B with FP32 vectors for c5, FP64
+    otherwise) on `--slots` right-hand sides, timed with HIP events over
+    back-to-back launches, against the HBM roofline."""
+    import ctypes
+
+    import synth
+    import paper_1609_08377_amd as el
+
+    n_atoms, _, desc = WORKLOADS[args.config]
+    precision = args.precision or ("mixed" if args.config == "c5" else "fp64")
+    slots = args.slots or 256
+    t0 = time.perf_counter()
+    sysm = synth.make_system(n_atoms, synth.config_seed(int(args.config[1:])))
+    ctx = el.Context(0)
+    mat = el.Matrix.from_system(ctx, sysm, precision=precision)
+    t_build = time.perf_counter() - t0
+    lib = el.lib()
+    lib.elses_time_pass.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    kind, w = (5, 4.0) if precision == "mixed" else (1, 8.0)
+    us = ctypes.c_double()
+    ctx.check(lib.elses_time_pass(ctx._h, mat._h, kind, el._variant(args.variant), slots, max(args.steps, 1) * 25,
+                                  ctypes.byref(us)))
+    nnzb = int(sysm.blk_row_ptr[-1])
+    nbytes = sysm.nnz * w + nnzb * 4.0 + n_atoms * 20.0 + 3.0 * sysm.M * slots * w
+    achieved = nbytes / (us.value * 1e-6) / 1e9
+    res = {"metric": "SpMV HBM GB/s vs peak (Richardson pass of the overlap solve at full matrix size)",
+           "value": round(achieved, 1), "unit": "GB/s", "n_gpus": 1, "steps": max(args.steps, 1) * 25,
+           "warmup": 1, "ms_per_step": round(us.value / 1000.0, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32" if precision == "mixed" else "f64", "data": "synthetic",
+           "config": {"workload": args.config + ": " + desc, "n_atoms": n_atoms, "M": int(sysm.M),
+                      "nnz": int(sysm.nnz), "atom_blocks": nnzb, "slots": slots, "variant": args.variant,
+                      "matrix_build_s": round(t_build, 1)},
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "pass_group_kernel<PASS_STEP32>" if precision == "mixed" else
+                                  "pass_group_kernel<PASS_STEP>",
+                        "bytes_per_launch": nbytes, "avg_launch_us": round(us.value, 2)}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,7 +377,7 @@ def main():
     ap.add_argument("--max-outer", type=int, default=20000,
                     help="cap on outer iterations (profiling runs only: capped runs do not converge)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--method", default="shifted", choices=["shifted", "arnoldi", "balance"],
+    ap.add_argument("--method", default="shifted", choices=["shifted", "arnoldi", "balance", "pass"],
                     help="arnoldi: the multiple Arnoldi method on kappa-atom regions of the 50000-atom box; "
                          "balance: idle lanes of region tiles, amorphous box against a diamond crystal")
     ap.add_argument("--centres", type=int, default=4096, help="arnoldi: region centres (consecutive atoms)")
@@ -353,6 +398,13 @@ def main():
     if args.method == "balance":
         run_balance(args)
         return
+    if args.method == "pass":
+        run_pass(args)
+        return
+    if args.config == "c5":
+        print(json.dumps({"error": "c5 is measured with --method pass (the sparse pass at full matrix size); "
+                                   "its columns are solved in the full-size tests"}), flush=True)
+        sys.exit(2)
 
     import torch
 

@@ -339,7 +339,11 @@ struct MaEig {
     double* ctr;          // [col][2] (may be null)
 };
 
+// MAXP: the largest number of rotation pairs per Jacobi step (nu / 2), a
+// compile-time bound for the per-lane operand registers.
+template <int MAXP>
 __global__ void __launch_bounds__(kWave) ma_eig_kernel(MaEig a) {
+    constexpr int kMaxPairs = MAXP;
     extern __shared__ double lds[];
     const int s = blockIdx.x;
     const int t = threadIdx.x;
@@ -475,32 +479,62 @@ __global__ void __launch_bounds__(kWave) ma_eig_kernel(MaEig a) {
                 ps[t] = (q < n) ? sn : 0.0;
             }
             __syncthreads();
+            // The pairs of a step are disjoint, so every operand of a pass is
+            // loaded before any result is stored (the loads overlap instead of
+            // waiting behind each store).  The pair data are wave-uniform.
+            int P_[kMaxPairs], Q_[kMaxPairs];
+            double C_[kMaxPairs], S_[kMaxPairs], X_[kMaxPairs], Y_[kMaxPairs];
+#pragma unroll
+            for (int r = 0; r < kMaxPairs; ++r) {
+                const bool on = r < npair;
+                P_[r] = on ? pp[r] : 0;
+                Q_[r] = on ? pq[r] : 0;
+                C_[r] = on ? pc[r] : 1.0;
+                S_[r] = on ? ps[r] : 0.0;
+            }
             // rows p, q of C (thread t: column t)
-            if (t < n)
-                for (int r = 0; r < npair; ++r) {
-                    const double sn = ps[r];
-                    if (sn == 0.0) continue;
-                    const int p = pp[r], q = pq[r];
-                    const double c = pc[r];
-                    const double x = Cm[p * ldn + t], y = Cm[q * ldn + t];
-                    Cm[p * ldn + t] = c * x - sn * y;
-                    Cm[q * ldn + t] = sn * x + c * y;
-                }
+            if (t < n) {
+#pragma unroll
+                for (int r = 0; r < kMaxPairs; ++r)
+                    if (S_[r] != 0.0) {
+                        X_[r] = Cm[P_[r] * ldn + t];
+                        Y_[r] = Cm[Q_[r] * ldn + t];
+                    }
+#pragma unroll
+                for (int r = 0; r < kMaxPairs; ++r)
+                    if (S_[r] != 0.0) {
+                        Cm[P_[r] * ldn + t] = C_[r] * X_[r] - S_[r] * Y_[r];
+                        Cm[Q_[r] * ldn + t] = S_[r] * X_[r] + C_[r] * Y_[r];
+                    }
+            }
             __syncthreads();
-            // columns p, q of C and Z (thread t: row t)
-            if (t < n)
-                for (int r = 0; r < npair; ++r) {
-                    const double sn = ps[r];
-                    if (sn == 0.0) continue;
-                    const int p = pp[r], q = pq[r];
-                    const double c = pc[r];
-                    const double x = Cm[t * ldn + p], y = Cm[t * ldn + q];
-                    Cm[t * ldn + p] = c * x - sn * y;
-                    Cm[t * ldn + q] = sn * x + c * y;
-                    const double zx = Zm[t * ldn + p], zy = Zm[t * ldn + q];
-                    Zm[t * ldn + p] = c * zx - sn * zy;
-                    Zm[t * ldn + q] = sn * zx + c * zy;
-                }
+            // columns p, q of C, then of Z (thread t: row t)
+            if (t < n) {
+#pragma unroll
+                for (int r = 0; r < kMaxPairs; ++r)
+                    if (S_[r] != 0.0) {
+                        X_[r] = Cm[t * ldn + P_[r]];
+                        Y_[r] = Cm[t * ldn + Q_[r]];
+                    }
+#pragma unroll
+                for (int r = 0; r < kMaxPairs; ++r)
+                    if (S_[r] != 0.0) {
+                        Cm[t * ldn + P_[r]] = C_[r] * X_[r] - S_[r] * Y_[r];
+                        Cm[t * ldn + Q_[r]] = S_[r] * X_[r] + C_[r] * Y_[r];
+                    }
+#pragma unroll
+                for (int r = 0; r < kMaxPairs; ++r)
+                    if (S_[r] != 0.0) {
+                        X_[r] = Zm[t * ldn + P_[r]];
+                        Y_[r] = Zm[t * ldn + Q_[r]];
+                    }
+#pragma unroll
+                for (int r = 0; r < kMaxPairs; ++r)
+                    if (S_[r] != 0.0) {
+                        Zm[t * ldn + P_[r]] = C_[r] * X_[r] - S_[r] * Y_[r];
+                        Zm[t * ldn + Q_[r]] = S_[r] * X_[r] + C_[r] * Y_[r];
+                    }
+            }
             __syncthreads();
         }
         if (any_rot == 0) break;
@@ -651,7 +685,10 @@ void launch_ma_eig(int n_slots, int nu, const double* H, const double* Br, const
                    hipStream_t st) {
     MaEig a{nu, H, Br, dead, slot_row, slot_col, W, wstride, Lw, mu, kT, eps, wI, wB, wA, dim, g, ctr};
     const size_t lds = sizeof(double) * (3 * (size_t)nu * (nu | 1) + 3 * nu + 72 + 64);
-    hipLaunchKernelGGL(ma_eig_kernel, dim3(n_slots), dim3(kWave), lds, st, a);
+    if (nu <= 32)
+        hipLaunchKernelGGL(ma_eig_kernel<16>, dim3(n_slots), dim3(kWave), lds, st, a);
+    else
+        hipLaunchKernelGGL(ma_eig_kernel<24>, dim3(n_slots), dim3(kWave), lds, st, a);
 }
 
 void launch_ma_rho(int n_cols, const int64_t* pat_off, const int* rows, const int* col_slot, const double* g, int nu,

@@ -178,3 +178,80 @@ def test_c4_learned_spai_and_regions(el, ctx):
     for k in range(K):
         rk = np.array([ref.x[0, k, loc[int(i)]] if int(i) in loc else 0.0 for i in rows])
         assert np.abs(blk[k] - rk).max() <= 5e-7 * np.abs(rk).max()
+
+
+def _row_products(s, rows, x, which):
+    """Exact FP64 products (X x)[r] of sampled rows r from the atom blocks (values
+    rounded to FP32 first when `x` is FP32, as the FP32 product reads them)."""
+    vals = s.A_val if which == "A" else s.B_val
+    fp32 = x.dtype == np.float32
+    atom_of = np.repeat(np.arange(s.n_atoms), s.n_orb.astype(int))
+    out = np.zeros((len(rows), x.shape[1]))
+    mag = np.zeros((len(rows), x.shape[1]))
+    for i, r in enumerate(rows):
+        I = int(atom_of[r])
+        a = int(r - s.orb_off[I])
+        nI = int(s.n_orb[I])
+        for b in range(int(s.blk_row_ptr[I]), int(s.blk_row_ptr[I + 1])):
+            J = int(s.blk_col[b])
+            nJ = int(s.n_orb[J])
+            v = vals[s.val_ptr[b]:s.val_ptr[b + 1]].reshape(nI, nJ)[a]
+            if fp32:
+                v = v.astype(np.float32).astype(np.float64)
+            xs = x[s.orb_off[J]:s.orb_off[J] + nJ].astype(np.float64)
+            out[i] += v @ xs
+            mag[i] += np.abs(v) @ np.abs(xs)
+    return out, mag
+
+
+def test_c5_one_gpu_share(el, ctx):
+    """10^6-atom box (M = 2.0e6, FP32-stored matrices), in the launch configuration
+    of `bench.py --method pass --config c5` (256 right-hand sides, default
+    passes): sampled rows of the FP32 and FP64 products against exact products
+    from the atom blocks, and sampled columns solved as mixed-precision regions
+    against the oracle on the FP32-rounded carved sub-pencil."""
+    s = synth.make_system(1000000, synth.config_seed(5))
+    mat = el.Matrix.from_system(ctx, s, precision="mixed")
+    assert mat.M == s.M and s.M > 1_990_000
+    rng = np.random.default_rng(5)
+    rows = np.sort(rng.choice(s.M, size=48, replace=False))
+    for which in ("A", "B"):
+        x32 = torch.as_tensor(rng.standard_normal((s.M, 256)).astype(np.float32)).cuda()
+        y32 = el.spmm32(ctx, mat, which, x32)
+        ref, mag = _row_products(s, rows, x32.cpu().numpy(), which)
+        got = y32[torch.as_tensor(rows).cuda()].cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(got - ref) <= 8e-6 * mag + 1e-30)
+        del x32, y32
+    x64 = torch.as_tensor(rng.standard_normal((s.M, 64))).cuda()
+    y64 = el.spmm(ctx, mat, "B", x64)
+    ref, mag = _row_products(s, rows, x64.cpu().numpy(), "B")
+    got = y64[torch.as_tensor(rows).cuda()].cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 1e-14 * mag + 1e-300)
+    del x64, y64
+    # sampled columns as regions (radius rule of the region workload), mixed precision
+    cols = synth.sample_columns(s, 65536, synth.config_seed(5))[:16]
+    atom_of = np.repeat(np.arange(s.n_atoms), s.n_orb.astype(int))
+    centres = np.unique(atom_of[cols]).astype(np.int32)
+    radii = np.random.default_rng(synth.config_seed(5) + 3).uniform(6.0, 10.0, size=centres.size)
+    reg = el.Regions(ctx, mat, centres, radii, 64)
+    z = synth.shift_grid(128)
+    cw = fermi_cw(z)
+    out = el.region_solve(ctx, reg, z, cw, tol=1e-8, mixed=True)
+    assert np.all(out["resid"].cpu().numpy() <= 1e-8)
+    r = int(np.argmin(reg.region_orbitals))
+    atoms = oracle.region_atoms(s, int(centres[r]), float(radii[r]))
+    Ar, Br, orb_map = oracle.carve_region(rounded(s), atoms)
+    loc = {int(g): l for l, g in enumerate(orb_map)}
+    col_region = np.repeat(np.arange(centres.size), [int(s.n_orb[c]) for c in centres])
+    c = int(np.nonzero(col_region == r)[0][0])
+    j = int(reg.cols[c])
+    ref = oracle.shifted_solve(Ar, Br, np.array([loc[j]], dtype=np.int32), z, tol=1e-10, full=True,
+                               true_residual=False)
+    rows_j = pattern_rows(s, j)
+    K = len(z)
+    blk = out["x"].cpu().numpy()[reg.pat_off[c] * K:reg.pat_off[c + 1] * K].reshape(K, -1)
+    for k in range(K):
+        rk = np.array([ref.x[0, k, loc[int(i)]] if int(i) in loc else 0.0 for i in rows_j])
+        assert np.abs(blk[k] - rk).max() <= 5e-7 * np.abs(rk).max()
+    print(f"\nC5: {reg.n_cols} sampled columns, regions of {reg.region_orbitals.min()}-{reg.region_orbitals.max()} "
+          f"orbitals, outer iterations max {int(out['iters'].max())}")
