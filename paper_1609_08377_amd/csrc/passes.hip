@@ -674,6 +674,38 @@ __device__ __forceinline__ void group_partial(int u0, int u4, int u1, int sub, c
         for (int c = 0; c < CPL; ++c) pw[(r * kWave + lane) * CPL + c] = acc[r][c];
 }
 
+// Two waves per group (KS = 2): each wave keeps the rows it finishes in
+// registers and hands the other wave's rows over through LDS, half of the
+// group's partial rows (rows of parity p go to wave p, at slot row / 2).
+// Exactly one workgroup barrier.
+constexpr int kHalfRows = kMaxGroupRows / 2;
+
+template <int KIND, int R, int CPL, typename TA, typename TV, typename Src>
+__device__ __forceinline__ void group_rows2(const PassArgs& a, int u0, int u4, int u1, int sub,
+                                            const int* __restrict__ uorb, const TV* __restrict__ v,
+                                            const Src& src, TA* pg, int lane, const int* __restrict__ rows,
+                                            int c0, const ColState (&cs)[CPL], double (&d0)[CPL],
+                                            double (&d1)[CPL]) {
+    TA acc[R][CPL];
+    block_product<R, CPL, 2>(u0, u4, u1, sub, uorb, v, src, acc);
+    TA* mine = pg + (size_t)sub * kHalfRows * kWave * CPL;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if ((r & 1) != sub)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) mine[((r >> 1) * kWave + lane) * CPL + c] = acc[r][c];
+    __syncthreads();
+    const TA* other = pg + (size_t)(1 - sub) * kHalfRows * kWave * CPL;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if ((r & 1) == sub) {
+            TA t[1][CPL];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) t[0][c] = acc[r][c] + other[((r >> 1) * kWave + lane) * CPL + c];
+            epilogue<KIND, 1, CPL>(a, rows[r], c0, t, 0, cs, d0, d1);
+        }
+}
+
 template <int KIND, int CPL, int KS>
 __global__ __launch_bounds__(kBlock) void pass_group_kernel(PassArgs a, const int* __restrict__ gR,
                                                             const int* __restrict__ groff,
@@ -686,7 +718,7 @@ __global__ __launch_bounds__(kBlock) void pass_group_kernel(PassArgs a, const in
     using TA = typename KindTypes<KIND>::TA;
     using TX = typename KindTypes<KIND>::TX;
     constexpr int GPW = kWavesPerBlock / KS;  // groups per workgroup
-    constexpr size_t kPartBytes = sizeof(TA) * kWavesPerBlock * kMaxGroupRows * kWave * CPL;
+    constexpr size_t kPartBytes = sizeof(TA) * kWavesPerBlock * (KS == 2 ? kHalfRows : kMaxGroupRows) * kWave * CPL;
     constexpr size_t kRedBytes = sizeof(double) * 2 * kWavesPerBlock * kWave * CPL;
     __shared__ __align__(16) unsigned char smem[kPartBytes > kRedBytes ? kPartBytes : kRedBytes];
     TA* part = reinterpret_cast<TA*>(smem);
@@ -714,6 +746,27 @@ __global__ __launch_bounds__(kBlock) void pass_group_kernel(PassArgs a, const in
     const bool tile_done = a.tile_live && a.tile_live[a.slab_tile[slab]] == 0;
     const bool live = (a.slab_group ? g >= 0 : g < a.n_grp) && !tile_done;
     int R = 0;
+    if constexpr (KS == 2) {
+        if (live) {
+            R = gR[g];
+            const int u0 = guoff[g], u4 = gu4[g], u1 = guoff[g + 1];
+            const auto* __restrict__ v = vals + gvoff[g];
+            const int* __restrict__ rows = grows + groff[g];
+            TA* pg = part + (size_t)(gi * 2) * kHalfRows * kWave * CPL;
+            switch (R) {
+                case 1: group_rows2<KIND, 1, CPL>(a, u0, u4, u1, sub, guorb, v, src, pg, lane, rows, c0, cs, d0, d1); break;
+                case 4: group_rows2<KIND, 4, CPL>(a, u0, u4, u1, sub, guorb, v, src, pg, lane, rows, c0, cs, d0, d1); break;
+                case 5: group_rows2<KIND, 5, CPL>(a, u0, u4, u1, sub, guorb, v, src, pg, lane, rows, c0, cs, d0, d1); break;
+                case 6: group_rows2<KIND, 6, CPL>(a, u0, u4, u1, sub, guorb, v, src, pg, lane, rows, c0, cs, d0, d1); break;
+                case 7: group_rows2<KIND, 7, CPL>(a, u0, u4, u1, sub, guorb, v, src, pg, lane, rows, c0, cs, d0, d1); break;
+                default: group_rows2<KIND, 8, CPL>(a, u0, u4, u1, sub, guorb, v, src, pg, lane, rows, c0, cs, d0, d1); break;
+            }
+        } else {
+            __syncthreads();
+        }
+        store_partials<KIND, CPL, kWavesPerBlock>(a, slab, c0, wave, lane, d0, d1, reinterpret_cast<double*>(smem));
+        return;
+    }
     TA* pw = part + (size_t)wave * kMaxGroupRows * kWave * CPL;
     if (live) {
         R = gR[g];
