@@ -371,6 +371,9 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default: fp64 for c1/c2, mixed (FP32-stored A, B) for c3")
     ap.add_argument("--tile", type=int, default=64, help="column slots per region tile (c3)")
+    ap.add_argument("--regions", type=int, default=N_REGIONS, help="c3: number of regions")
+    ap.add_argument("--region-order", default="index", choices=["index", "size"],
+                    help="c3: pack regions in atom order, or largest radius first")
     ap.add_argument("--copy-calib", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--variant", default="auto", choices=["auto", "direct", "staged8", "staged4", "grouped", "grouped2", "grouped1"])
     ap.add_argument("--no-cpu", action="store_true")
@@ -433,7 +436,10 @@ def main():
 
     extra = {}
     if region_mode:
-        centres, radii = synth.sample_regions(sysm, N_REGIONS, seed)
+        centres, radii = synth.sample_regions(sysm, args.regions, seed)
+        if args.region_order == "size":
+            o = np.argsort(-radii, kind="stable")
+            centres, radii = centres[o], radii[o]
         t_plan = time.perf_counter()
         reg = el.Regions(ctx, mat, centres, radii, args.tile)
         extra = {"regions": int(centres.size), "region_tiles": reg.n_tiles, "tile_width": args.tile,
@@ -442,7 +448,8 @@ def main():
                  "region_orbitals_min_mean_max": [int(reg.region_orbitals.min()),
                                                   round(float(reg.region_orbitals.mean()), 1),
                                                   int(reg.region_orbitals.max())],
-                 "region_set_build_s": round(time.perf_counter() - t_plan, 2)}
+                 "region_set_build_s": round(time.perf_counter() - t_plan, 2),
+                 "region_order": args.region_order}
         small = el.Regions(ctx, mat, centres[:8], radii[:8], args.tile)
         batches = [reg.cols]
 
@@ -517,6 +524,7 @@ def main():
     if region_mode:
         res["config"].pop("columns_per_step", None)
         res["config"]["batches_in_job"] = 1
+        res["config"]["idle_lane_fraction"] = round(tile_idle(sysm, centres, iters, args.tile), 4)
     if not args.no_cpu and not region_mode:
         print("timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(sysm, z, float(iters.mean()), args.cpu_budget)
