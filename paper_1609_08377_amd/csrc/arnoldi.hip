@@ -611,6 +611,268 @@ __global__ void __launch_bounds__(kWave) ma_eig_kernel(MaEig a) {
     }
 }
 
+// The same eigensolve for two columns per wavefront (nu <= 32): half-wave h
+// (lanes 32 h .. 32 h + 31) owns slot 2 * blockIdx.x + h and its own copy of
+// the work arrays, so every instruction serves two columns.  Loop bounds that
+// contain barriers use the larger of the two subspace dimensions; each half
+// skips indices beyond its own.
+__global__ void __launch_bounds__(kWave) ma_eig2_kernel(MaEig a, int n_slots) {
+    extern __shared__ double lds2[];
+    constexpr int kMaxPairs = 16;
+    const int t = threadIdx.x;
+    const int h = t >> 5, u = t & 31;
+    const int s = 2 * blockIdx.x + h;
+    const int nu = a.nu;
+    const int ldn = nu | 1;
+    const size_t per_half = 3 * (size_t)nu * ldn + 3 * nu + 104;
+    double* Cm = lds2 + h * per_half;
+    double* Lm = Cm + nu * ldn;
+    double* Zm = Lm + nu * ldn;
+    double* av = Zm + nu * ldn;
+    double* bv = av + nu;
+    double* cv = bv + nu;
+    double* rot = cv + nu;      // [0..7] scalars, [8..23] cos, [24..39] sin, [40..71] f(eps_m) a_m
+    double* pc = rot + 8;
+    double* ps = rot + 24;
+    double* fa = rot + 40;
+    __shared__ int idx[2][32], perm[2][32], pp[2][16], pq[2][16], n_sh[2], any_rot[2];
+    const bool valid = s < n_slots && a.slot_row[s] >= 0 && a.slot_col[s] >= 0;
+    const int col = valid ? a.slot_col[s] : -1;
+    const double* H = a.H + (size_t)(valid ? s : 0) * nu * nu;
+    const double* Br = a.Br + (size_t)(valid ? s : 0) * nu * nu;
+    if (u == 0) {
+        int n = 0;
+        if (valid) {
+            const unsigned long long dm = a.dead[s];
+            for (int i = 0; i < nu; ++i)
+                if (!((dm >> i) & 1ull)) idx[h][n++] = i;
+        }
+        n_sh[h] = n;
+    }
+    __syncthreads();
+    const int n = n_sh[h];
+    const int nmax = max(n_sh[0], n_sh[1]);
+    if (nmax == 0) return;
+    const int row_j = valid ? a.slot_row[s] : 0;
+    const int lane = s % a.Lw;
+    for (int e = u; e < n * n; e += 32) {
+        const int i = e / n, k = e % n;
+        const int ii = idx[h][i], kk = idx[h][k];
+        Cm[i * ldn + k] = 0.5 * (H[ii * nu + kk] + H[kk * nu + ii]);
+        Lm[i * ldn + k] = ii <= kk ? Br[ii * nu + kk] : Br[kk * nu + ii];
+    }
+    if (u < n) {
+        const int ii = idx[h][u];
+        av[u] = a.W[(size_t)ii * a.wstride + (size_t)row_j * a.Lw + lane];
+        bv[u] = Br[ii];
+        cv[u] = 0.5 * (H[ii * nu] + H[ii]);
+    }
+    __syncthreads();
+    // Cholesky B_r = L L^T
+    for (int j = 0; j < nmax; ++j) {
+        if (u == 0 && j < n) {
+            double d = Lm[j * ldn + j];
+            for (int k = 0; k < j; ++k) d -= Lm[j * ldn + k] * Lm[j * ldn + k];
+            Lm[j * ldn + j] = sqrt(fmax(d, 1e-300));
+        }
+        __syncthreads();
+        if (j < n && u > j && u < n) {
+            double v = Lm[u * ldn + j];
+            for (int k = 0; k < j; ++k) v -= Lm[u * ldn + k] * Lm[j * ldn + k];
+            Lm[u * ldn + j] = v / Lm[j * ldn + j];
+        }
+        __syncthreads();
+    }
+    if (u < n)
+        for (int i = 0; i < n; ++i) {
+            double v = Cm[i * ldn + u];
+            for (int k = 0; k < i; ++k) v -= Lm[i * ldn + k] * Zm[k * ldn + u];
+            Zm[i * ldn + u] = v / Lm[i * ldn + i];
+        }
+    __syncthreads();
+    if (u < n)
+        for (int i = 0; i < n; ++i) {
+            double v = Zm[u * ldn + i];
+            for (int k = 0; k < i; ++k) v -= Lm[i * ldn + k] * Cm[k * ldn + u];
+            Cm[i * ldn + u] = v / Lm[i * ldn + i];
+        }
+    __syncthreads();
+    for (int e = u; e < n * n; e += 32) {
+        const int i = e / n, k = e % n;
+        if (i < k) {
+            const double v = 0.5 * (Cm[i * ldn + k] + Cm[k * ldn + i]);
+            Cm[i * ldn + k] = v;
+            Cm[k * ldn + i] = v;
+        }
+        Zm[i * ldn + k] = (i == k) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (u == 0) {
+        double f2 = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) f2 += Cm[i * ldn + k] * Cm[i * ldn + k];
+        rot[5] = 1e-16 * sqrt(f2);
+    }
+    __syncthreads();
+    // parallel Jacobi, round-robin pairs of the larger dimension
+    const int P = nmax + (nmax & 1);
+    const int npair = P / 2;
+    for (int sweep = 0; sweep < 30 && nmax > 1; ++sweep) {
+        if (u == 0) any_rot[h] = 0;
+        __syncthreads();
+        for (int step = 0; step < P - 1; ++step) {
+            if (u < npair) {
+                int pa_, pb_;
+                if (u == 0) {
+                    pa_ = step;
+                    pb_ = P - 1;
+                } else {
+                    pa_ = (step + u) % (P - 1);
+                    pb_ = (step - u + P - 1) % (P - 1);
+                }
+                const int p = min(pa_, pb_), q = max(pa_, pb_);
+                double c = 1.0, sn = 0.0;
+                if (q < n) {
+                    const double apq = Cm[p * ldn + q];
+                    if (fabs(apq) > rot[5]) {
+                        const double app = Cm[p * ldn + p], aqq = Cm[q * ldn + q];
+                        const double th = (aqq - app) / (2.0 * apq);
+                        const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        c = 1.0 / sqrt(tt * tt + 1.0);
+                        sn = tt * c;
+                        any_rot[h] = 1;
+                    }
+                }
+                pp[h][u] = p;
+                pq[h][u] = q;
+                pc[u] = c;
+                ps[u] = sn;
+            }
+            __syncthreads();
+            int P_[kMaxPairs], Q_[kMaxPairs];
+            double C_[kMaxPairs], S_[kMaxPairs], X_[kMaxPairs], Y_[kMaxPairs];
+#pragma unroll
+            for (int r = 0; r < kMaxPairs; ++r) {
+                const bool on = r < npair;
+                P_[r] = on ? pp[h][r] : 0;
+                Q_[r] = on ? pq[h][r] : 0;
+                C_[r] = on ? pc[r] : 1.0;
+                S_[r] = on ? ps[r] : 0.0;
+            }
+            if (u < n) {
+#pragma unroll
+                for (int r = 0; r < kMaxPairs; ++r)
+                    if (S_[r] != 0.0) {
+                        X_[r] = Cm[P_[r] * ldn + u];
+                        Y_[r] = Cm[Q_[r] * ldn + u];
+                    }
+#pragma unroll
+                for (int r = 0; r < kMaxPairs; ++r)
+                    if (S_[r] != 0.0) {
+                        Cm[P_[r] * ldn + u] = C_[r] * X_[r] - S_[r] * Y_[r];
+                        Cm[Q_[r] * ldn + u] = S_[r] * X_[r] + C_[r] * Y_[r];
+                    }
+            }
+            __syncthreads();
+            if (u < n) {
+#pragma unroll
+                for (int r = 0; r < kMaxPairs; ++r)
+                    if (S_[r] != 0.0) {
+                        X_[r] = Cm[u * ldn + P_[r]];
+                        Y_[r] = Cm[u * ldn + Q_[r]];
+                    }
+#pragma unroll
+                for (int r = 0; r < kMaxPairs; ++r)
+                    if (S_[r] != 0.0) {
+                        Cm[u * ldn + P_[r]] = C_[r] * X_[r] - S_[r] * Y_[r];
+                        Cm[u * ldn + Q_[r]] = S_[r] * X_[r] + C_[r] * Y_[r];
+                    }
+#pragma unroll
+                for (int r = 0; r < kMaxPairs; ++r)
+                    if (S_[r] != 0.0) {
+                        X_[r] = Zm[u * ldn + P_[r]];
+                        Y_[r] = Zm[u * ldn + Q_[r]];
+                    }
+#pragma unroll
+                for (int r = 0; r < kMaxPairs; ++r)
+                    if (S_[r] != 0.0) {
+                        Zm[u * ldn + P_[r]] = C_[r] * X_[r] - S_[r] * Y_[r];
+                        Zm[u * ldn + Q_[r]] = S_[r] * X_[r] + C_[r] * Y_[r];
+                    }
+            }
+            __syncthreads();
+        }
+        if (any_rot[0] == 0 && any_rot[1] == 0) break;
+        __syncthreads();
+    }
+    // Y = L^{-T} Z
+    if (u < n)
+        for (int i = n - 1; i >= 0; --i) {
+            double v = Zm[i * ldn + u];
+            for (int k = i + 1; k < n; ++k) v -= Lm[k * ldn + i] * Zm[k * ldn + u];
+            Zm[i * ldn + u] = v / Lm[i * ldn + i];
+        }
+    if (u < n) {
+        const double e = Cm[u * ldn + u];
+        int rank = 0;
+        for (int k = 0; k < n; ++k) {
+            const double f = Cm[k * ldn + k];
+            rank += (f < e || (f == e && k < u)) ? 1 : 0;
+        }
+        perm[h][rank] = u;
+    }
+    __syncthreads();
+    double trB = 0.0, trA = 0.0;
+    if (valid && u < nu) {
+        const size_t o = (size_t)col * nu;
+        if (u < n) {
+            const int m = perm[h][u];
+            const double e = Cm[m * ldn + m];
+            double am = 0.0, bm = 0.0, cm = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const double y = Zm[i * ldn + m];
+                am = fma(av[i], y, am);
+                bm = fma(bv[i], y, bm);
+                cm = fma(cv[i], y, cm);
+            }
+            a.eps[o + u] = e;
+            a.wI[o + u] = am * am;
+            a.wB[o + u] = am * bm;
+            a.wA[o + u] = am * cm;
+            const double fw = ma_fermi(e, a.mu, a.kT);
+            trB = fw * am * bm;
+            trA = fw * am * cm;
+            fa[u] = fw * am;
+        } else {
+            a.eps[o + u] = 0.0;
+            a.wI[o + u] = 0.0;
+            a.wB[o + u] = 0.0;
+            a.wA[o + u] = 0.0;
+        }
+        if (u == 0) a.dim[col] = n;
+    }
+    __syncthreads();
+    if (valid && a.g && u < nu) {
+        double v = 0.0;
+        int ci = -1;
+        for (int i = 0; i < n; ++i)
+            if (idx[h][i] == u) ci = i;
+        if (ci >= 0)
+            for (int k = 0; k < n; ++k) v = fma(Zm[ci * ldn + perm[h][k]], fa[k], v);
+        a.g[(size_t)s * nu + u] = v;
+    }
+    if (a.ctr) {
+        for (int off = 16; off > 0; off >>= 1) {
+            trB += __shfl_down(trB, off, 32);
+            trA += __shfl_down(trA, off, 32);
+        }
+        if (valid && u == 0) {
+            a.ctr[2 * (size_t)col] = trB;
+            a.ctr[2 * (size_t)col + 1] = trA;
+        }
+    }
+}
+
 // rho on the column patterns: rho[p] = sum_i g[slot][i] W_i[row_p][lane]
 // (pattern rows -1, outside a region, give 0).
 __global__ void ma_rho_kernel(int n_cols, const int64_t* __restrict__ pat_off, const int* __restrict__ rows,
@@ -685,10 +947,12 @@ void launch_ma_eig(int n_slots, int nu, const double* H, const double* Br, const
                    hipStream_t st) {
     MaEig a{nu, H, Br, dead, slot_row, slot_col, W, wstride, Lw, mu, kT, eps, wI, wB, wA, dim, g, ctr};
     const size_t lds = sizeof(double) * (3 * (size_t)nu * (nu | 1) + 3 * nu + 72 + 64);
-    if (nu <= 32)
-        hipLaunchKernelGGL(ma_eig_kernel<16>, dim3(n_slots), dim3(kWave), lds, st, a);
-    else
+    if (nu <= 32) {
+        const size_t lds2 = sizeof(double) * 2 * (3 * (size_t)nu * (nu | 1) + 3 * nu + 104);
+        hipLaunchKernelGGL(ma_eig2_kernel, dim3((n_slots + 1) / 2), dim3(kWave), lds2, st, a, n_slots);
+    } else {
         hipLaunchKernelGGL(ma_eig_kernel<24>, dim3(n_slots), dim3(kWave), lds, st, a);
+    }
 }
 
 void launch_ma_rho(int n_cols, const int64_t* pat_off, const int* rows, const int* col_slot, const double* g, int nu,
