@@ -1457,7 +1457,7 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
                     vout = xcur;
                     F2 = xoth;
                 } else {
-                    // round 1: FP32 solve of B x = s (s kept in FP64 and FP32)
+                    // first FP32 solve: B x = s (s kept in FP64 and FP32)
                     launch_overlap_start(M, vw, Tp, Tn, alpha, inv_beta, row_tile, rich.g0, F1, nullptr, S32, Xa32,
                                          st);
                     float* xcur = Xa32;
@@ -1476,7 +1476,7 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
                     pa.R32o = R32;
                     pa.Xio32 = Da32;
                     launch_pass(PASS_REFINE, pa, st);
-                    // round 2: FP32 solve of B d = r; the last step forms v = x + d
+                    // second FP32 solve, the correction: B d = r; the last step forms v = x + d
                     float* dcur = Da32;
                     float* doth = Db32;
                     pa.R32 = R32;
