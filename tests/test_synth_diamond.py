@@ -92,3 +92,34 @@ def test_amorphous_columns_are_not_equivalent():
     r = oracle.shifted_solve(A, B, cols, synth.shift_grid(8), tol=1e-8, full=False, true_residual=False)
     it = np.asarray(r.iters)
     assert it.max() - it.min() > 5
+
+
+@pytest.mark.parametrize("kappa", [20, 100])
+def test_kappa_radii_hold_kappa_atoms(kappa):
+    """Amorphous box: the sphere of each radius holds exactly kappa atoms (the
+    centre included), checked by brute-force minimum-image distances."""
+    s = synth.make_system(1024, synth.config_seed(2))
+    centres = np.arange(0, 1024, 37)
+    radii = synth.kappa_radii(s, centres, kappa)
+    for c, r in zip(centres, radii):
+        d = s.pos - s.pos[c]
+        d -= s.L * np.rint(d / s.L)
+        dist = np.sqrt((d * d).sum(1))
+        assert np.sum(dist <= r) == kappa
+        assert np.sort(dist)[kappa - 1] < r < np.sort(dist)[kappa]
+
+
+def test_kappa_radii_take_whole_shells_in_the_crystal(d2):
+    """Crystal: tied distances put whole shells inside, identically for every atom."""
+    s = synth.make_diamond(3, 2001)
+    radii = synth.kappa_radii(s, np.arange(s.n_atoms), 20)
+    assert np.ptp(radii) < 1e-9
+    counts = [oracle.region_atoms(s, i, float(radii[i])).size for i in range(0, s.n_atoms, 17)]
+    assert len(set(counts)) == 1 and counts[0] >= 20
+    d = s.pos - s.pos[0]
+    d -= s.L * np.rint(d / s.L)
+    dist = np.sort(np.sqrt((d * d).sum(1)))
+    # membership is robust: no atom lies just outside the cut (the tied shell is
+    # inside, the next shell far beyond)
+    r = radii[0]
+    assert np.sum(dist <= r) == np.sum(dist <= r + 1e-6) == counts[0]
