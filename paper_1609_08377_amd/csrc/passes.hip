@@ -677,7 +677,13 @@ __device__ __forceinline__ void group_partial(int u0, int u4, int u1, int sub, c
 // Two waves per group (KS = 2): each wave keeps the rows it finishes in
 // registers and hands the other wave's rows over through LDS, half of the
 // group's partial rows (rows of parity p go to wave p, at slot row / 2).
-// Exactly one workgroup barrier.
+// Exactly one workgroup barrier.  Taken at two or more columns per lane, where
+// the halved LDS lets more waves run, and for FP64 values at one column per
+// lane.  FP32-valued passes over 64-wide region tiles ran faster with the
+// generic hand-over below (measured on one device, tiles of the 50000-atom
+// box: step pass 316 against 357 us, mixed A pass 1134 against 1405 us),
+// while FP64-valued ones ran slower (multiple-Arnoldi B pass 123 against
+// 115 us).
 constexpr int kHalfRows = kMaxGroupRows / 2;
 
 template <int KIND, int R, int CPL, typename TA, typename TV, typename Src>
@@ -718,7 +724,8 @@ __global__ __launch_bounds__(kBlock) void pass_group_kernel(PassArgs a, const in
     using TA = typename KindTypes<KIND>::TA;
     using TX = typename KindTypes<KIND>::TX;
     constexpr int GPW = kWavesPerBlock / KS;  // groups per workgroup
-    constexpr size_t kPartBytes = sizeof(TA) * kWavesPerBlock * (KS == 2 ? kHalfRows : kMaxGroupRows) * kWave * CPL;
+    constexpr bool kHand = KS == 2 && (CPL >= 2 || sizeof(typename KindTypes<KIND>::TV) == 8);
+    constexpr size_t kPartBytes = sizeof(TA) * kWavesPerBlock * (kHand ? kHalfRows : kMaxGroupRows) * kWave * CPL;
     constexpr size_t kRedBytes = sizeof(double) * 2 * kWavesPerBlock * kWave * CPL;
     __shared__ __align__(16) unsigned char smem[kPartBytes > kRedBytes ? kPartBytes : kRedBytes];
     TA* part = reinterpret_cast<TA*>(smem);
@@ -746,7 +753,7 @@ __global__ __launch_bounds__(kBlock) void pass_group_kernel(PassArgs a, const in
     const bool tile_done = a.tile_live && a.tile_live[a.slab_tile[slab]] == 0;
     const bool live = (a.slab_group ? g >= 0 : g < a.n_grp) && !tile_done;
     int R = 0;
-    if constexpr (KS == 2) {
+    if constexpr (kHand) {
         if (live) {
             R = gR[g];
             const int u0 = guoff[g], u4 = gu4[g], u1 = guoff[g + 1];
