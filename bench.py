@@ -47,6 +47,7 @@ METRIC = "column×shift solves/sec at 1e-8 rel. residual; SpMV HBM GB/s vs peak"
 
 PASS_SOURCE = os.path.join(ROOT, "paper_1609_08377_amd", "csrc", "passes.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pass_group_step_c2_traffic.md")
+C3_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pass_group_step32_c3_traffic.md")
 MA_SOURCE = os.path.join(ROOT, "paper_1609_08377_amd", "csrc", "arnoldi.hip")
 MA_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ma_update_regions4096_traffic.md")
 
@@ -497,7 +498,10 @@ def main():
     iters = torch.cat(iters_all).cpu().numpy()
     achieved = nbytes.value / (avg_us.value * 1e-6) / 1e9 if avg_us.value > 0 else 0.0
     tag = ("step32" if mixed else "step64") + f"_{args.config}_{args.tile if region_mode else slots.value}"
-    traffic = committed_traffic(tag) if args.variant == "auto" else None
+    if region_mode and (args.regions != N_REGIONS or args.region_order != "index"):
+        tag += f"_{args.regions}_{args.region_order}"  # counters were taken on the default region set
+    summary = C3_TRAFFIC_SUMMARY if region_mode else TRAFFIC_SUMMARY
+    traffic = committed_traffic(tag, summary) if args.variant == "auto" else None
     kernel = ("pass_group_kernel<PASS_STEP32> (FP32 B SpMM + Richardson step)" if mixed else
               "pass_group_kernel<PASS_STEP> (FP64 B SpMM + Richardson step)")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
