@@ -113,14 +113,19 @@ typedef struct {
     double tol;          /* relative residual ||e_j - (z B - A) x|| per (j,k); default 1e-8 */
     int32_t max_outer;   /* outer (Lanczos) iterations per column; default 20000            */
     double inner_tol;    /* relative residual of each overlap solve; default 1e-13          */
-    int32_t out_mode;    /* ELSES_OUT_PATTERN or ELSES_OUT_FULL (global mode only)          */
+    int32_t out_mode;    /* ELSES_OUT_PATTERN or ELSES_OUT_FULL (not on region tiles)       */
     int32_t slots;       /* columns advanced together (multiple of 64); 0 = autotune        */
     int32_t use_mixed;   /* 1: FP32 overlap solve + FP64 refinement (needs ELSES_MIXED)     */
     int32_t audit;       /* 1: recompute FP64 true residuals (ELSES_OUT_FULL only)          */
     int32_t variant;     /* sparse passes: 0 auto, 1 direct gathers, 2 / 3 LDS-staged       */
                          /* gathers (8- / 4-atom clusters), 4 row groups sharing gathers   */
     int32_t graph;       /* 1: capture the outer iterations in a HIP graph and replay it    */
-                         /* on a private stream (pass timing is not sampled); default 0     */
+                         /* on a private stream (pass timing is not sampled); default 0.    */
+                         /* No effect on compact region sets (already one launch).          */
+    int32_t audit_every; /* compact region sets, pattern mode: the columns c with           */
+                         /* c % audit_every == 0 are also carried on every row of their     */
+                         /* region and their resid_out entries receive the recomputed FP64  */
+                         /* true residual instead of the estimate; 0 (default) = none       */
 } elses_opts;
 
 /* Fill *o with the defaults listed above. */
@@ -277,31 +282,60 @@ elses_status elses_spmm(elses_ctx ctx, elses_mat mat, int which, int32_t variant
  * distinct atoms) with radius radii[r] (HOST, Angstrom, > 0); it holds the atoms
  * whose minimum-image distance to the centre is <= radius (the matrix needs
  * pos, and box for periodic images).  Its columns are the orbitals of the
- * centre atom, region by region in the order given, so consecutive regions
- * should be spatial neighbours.  Regions are packed into tiles of
- * tile_width column slots (64 or 128; 0 = 64) that advance through one
- * persistent launch sequence; the set keeps its data on the device until
- * destroyed, and depends on `mat`, which must outlive it.
+ * centre atom, region by region in the order given.
+ *
+ * Layouts (tile_width):
+ *  0        compact (default): every region keeps its own sub-pencil (at most
+ *           4096 orbitals per region); one persistent launch solves them,
+ *           one workgroup per region at a time, taking regions from a device
+ *           queue largest first, with every step of a region's solve (outer
+ *           Lanczos steps, overlap solves, shift updates, density assembly)
+ *           inside the launch;
+ *  64, 128  tiles: consecutive regions (which should be spatial neighbours)
+ *           are packed into tiles of tile_width column slots of one
+ *           block-diagonal matrix that advance through one launch sequence
+ *           per outer step (the layout multiple Arnoldi needs).
+ * The set keeps its data on the device until destroyed, and depends on
+ * `mat`, which must outlive it.
  */
 typedef struct elses_regions_s *elses_regions;
 elses_status elses_regions_create(elses_ctx ctx, elses_mat mat, int32_t n_regions, const int32_t *centres,
                                   const double *radii, int32_t tile_width, elses_regions *out);
+/* As elses_regions_create in the compact layout, with orb_mask (HOST uint8
+ * [n_regions], may be NULL) selecting the centre's orbitals that are solved
+ * as columns: bit q set = orbital q of the centre atom (0 = all orbitals).
+ * Columns sampled on the same atom thus share one region (one solve). */
+elses_status elses_regions_create_ex(elses_ctx ctx, elses_mat mat, int32_t n_regions, const int32_t *centres,
+                                     const double *radii, const uint8_t *orb_mask, elses_regions *out);
 void elses_regions_destroy(elses_regions reg);
 /* Sizes and layout of a region set (HOST outputs, each may be NULL):
- * n_cols columns; n_tiles tiles; rows_total rows of all tiles' atom unions;
- * useful_rows = sum over columns of their region's orbital count;
+ * n_cols columns; n_tiles tiles (0 for the compact layout); rows_total rows of
+ * all tiles' atom unions (compact: sum over regions of the padded row count
+ * times the region's vector width, so that useful_rows / rows_total is the
+ * share of useful lane-rows, as useful_rows / (rows_total x tile_width) is in
+ * the tile layout); useful_rows = sum over columns of their region's orbital
+ * count;
  * cols [n_cols] global orbital of each column; pat_off [n_cols+1] offsets of
  * each column's pattern P_j in the caller's matrix (as elses_pattern);
  * region_orbitals [n_regions] orbitals of each region. */
 elses_status elses_regions_info(elses_regions reg, int32_t *n_cols, int32_t *n_tiles, int64_t *rows_total,
                                 int64_t *useful_rows, int32_t *cols, int64_t *pat_off, int32_t *region_orbitals);
+/* Region of each column (HOST int32 [n_cols], in the column order of
+ * elses_regions_info). */
+elses_status elses_regions_columns(elses_regions reg, int32_t *col_region);
 /* Solve (z_k B_r - A_r) x = e_j for every column of every region and every
  * shift (HOST, Im z > 0), in pattern mode: x_out, rho_out, col_traces_out,
  * iters_out and resid_out are laid out as in elses_density_matrix for the
  * column list of elses_regions_info (pattern rows outside the region hold 0).
  * c (HOST complex weights) may be NULL when no density output is requested.
- * opts: as elses_opts (out_mode must be ELSES_OUT_PATTERN, variant 0 or a
- * grouped variant; use_mixed needs a matrix created with ELSES_MIXED). */
+ * opts: as elses_opts; use_mixed needs a matrix created with ELSES_MIXED.
+ * Tile layout: out_mode must be ELSES_OUT_PATTERN, variant 0 or a grouped
+ * variant.  Compact layout: variant and slots are ignored; ELSES_OUT_FULL
+ * writes, per column in order, a [K][m_r] block of its region's vectors in
+ * the region's orbital order (atoms ascending; m_r = region_orbitals), and
+ * with opts->audit resid_out receives the FP64 true residuals
+ * ||e_j - (z_k B_r - A_r) x||_2 of the pencil solved (the FP32-rounded one
+ * for use_mixed); opts->audit_every audits a subset in pattern mode. */
 elses_status elses_regions_solve(elses_ctx ctx, elses_regions reg, int32_t n_shifts, const double *shifts,
                                  const double *c, const elses_opts *opts, double *x_out, double *rho_out,
                                  double *traces_out, double *col_traces_out, int32_t *iters_out,

@@ -58,7 +58,8 @@ class _System(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("out_mode", ctypes.c_int32), ("slots", ctypes.c_int32), ("use_mixed", ctypes.c_int32),
-                ("audit", ctypes.c_int32), ("variant", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("audit", ctypes.c_int32), ("variant", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("audit_every", ctypes.c_int32)]
 
 
 class ArnoldiOpts(ctypes.Structure):
@@ -122,6 +123,10 @@ def lib():
         L.elses_autotune.restype = ctypes.c_int
         L.elses_regions_create.argtypes = [P, P, I32, P, P, I32, ctypes.POINTER(P)]
         L.elses_regions_create.restype = ctypes.c_int
+        L.elses_regions_create_ex.argtypes = [P, P, I32, P, P, P, ctypes.POINTER(P)]
+        L.elses_regions_create_ex.restype = ctypes.c_int
+        L.elses_regions_columns.argtypes = [P, P]
+        L.elses_regions_columns.restype = ctypes.c_int
         L.elses_regions_destroy.argtypes = [P]
         L.elses_regions_destroy.restype = None
         L.elses_regions_info.argtypes = [P, P, P, P, P, P, P, P]
@@ -366,9 +371,11 @@ def spmm32(ctx: Context, mat: Matrix, which: str, x, variant: str = "auto"):
 
 
 class Regions:
-    """Region problems (principal sub-pencils around centre atoms) packed into tiles on the device."""
+    """Region problems (principal sub-pencils around centre atoms) on the device: the compact layout
+    (tile_width 0, one persistent launch) or tiles of 64 / 128 column slots.  orb_mask (one uint8 per
+    region, compact layout only) selects the centre's orbitals solved as columns (0 = all)."""
 
-    def __init__(self, ctx: Context, mat: Matrix, centres, radii, tile_width: int = 0):
+    def __init__(self, ctx: Context, mat: Matrix, centres, radii, tile_width: int = 0, orb_mask=None):
         self.ctx = ctx
         self.mat = mat
         centres = np.ascontiguousarray(centres, dtype=np.int32)
@@ -376,10 +383,20 @@ class Regions:
         if centres.shape != radii.shape:
             raise ValueError("one radius per centre")
         h = ctypes.c_void_p()
-        st = lib().elses_regions_create(ctx._h, mat._h, int(centres.shape[0]), _np_ptr(centres), _np_ptr(radii),
-                                        int(tile_width), ctypes.byref(h))
+        if orb_mask is not None:
+            if tile_width != 0:
+                raise ValueError("orbital masks need the compact layout (tile_width 0)")
+            mask = np.ascontiguousarray(orb_mask, dtype=np.uint8)
+            if mask.shape != centres.shape:
+                raise ValueError("one orbital mask per centre")
+            st = lib().elses_regions_create_ex(ctx._h, mat._h, int(centres.shape[0]), _np_ptr(centres),
+                                               _np_ptr(radii), _np_ptr(mask), ctypes.byref(h))
+        else:
+            st = lib().elses_regions_create(ctx._h, mat._h, int(centres.shape[0]), _np_ptr(centres),
+                                            _np_ptr(radii), int(tile_width), ctypes.byref(h))
         ctx.check(st)
         self._h = h
+        self.compact = (tile_width == 0)
         nc, nt = ctypes.c_int32(), ctypes.c_int32()
         rows, useful = ctypes.c_int64(), ctypes.c_int64()
         lib().elses_regions_info(h, ctypes.byref(nc), ctypes.byref(nt), ctypes.byref(rows), ctypes.byref(useful),
@@ -393,6 +410,10 @@ class Regions:
         self.region_orbitals = np.zeros(centres.shape[0], dtype=np.int32)
         lib().elses_regions_info(h, None, None, None, None, _np_ptr(self.cols), _np_ptr(self.pat_off),
                                  _np_ptr(self.region_orbitals))
+        self.col_region = np.zeros(self.n_cols, dtype=np.int32)
+        ctx.check(lib().elses_regions_columns(h, _np_ptr(self.col_region)))
+        # first entry of each column's block of full region vectors ([K][m_r] per column)
+        self.full_off = np.concatenate([[0], np.cumsum(self.region_orbitals[self.col_region].astype(np.int64))])
 
     def close(self):
         if getattr(self, "_h", None):
@@ -407,8 +428,13 @@ class Regions:
 
 
 def region_solve(ctx: Context, reg: Regions, shifts, c=None, *, tol=1e-8, max_outer=20000, inner_tol=1e-13,
-                 mixed=False, want_x=True, allow_not_converged=False, variant="auto", graph=False):
-    """Solve every region's columns for every shift; density outputs when weights c are given."""
+                 mixed=False, want_x=True, allow_not_converged=False, variant="auto", graph=False, full=False,
+                 audit=False, audit_every=0):
+    """Solve every region's columns for every shift; density outputs when weights c are given.
+
+    Compact region sets also take full=True (x holds, per column, the [K][m_r] vectors of its region in
+    the region's orbital order, offsets reg.full_off), audit=True (with full: resid = FP64 true residuals)
+    and audit_every=n (pattern mode: the columns c % n == 0 get their true residual in resid)."""
     torch = _torch()
     z = _shifts_ri(shifts)
     K = z.shape[0] // 2
@@ -418,13 +444,15 @@ def region_solve(ctx: Context, reg: Regions, shifts, c=None, *, tol=1e-8, max_ou
     nc = reg.n_cols
     npat = int(reg.pat_off[-1])
     dev = torch.device("cuda", ctx.device)
-    x = torch.empty(2 * npat * K, dtype=torch.float64, device=dev) if want_x else None
+    nx = int(reg.full_off[-1]) * K if full else npat * K
+    x = torch.empty(2 * nx, dtype=torch.float64, device=dev) if want_x else None
     rho = torch.empty(npat, dtype=torch.float64, device=dev) if cw is not None else None
     col_tr = torch.empty(2 * nc, dtype=torch.float64, device=dev) if cw is not None else None
     iters = torch.empty(nc, dtype=torch.int32, device=dev)
     resid = torch.empty(nc * K, dtype=torch.float64, device=dev)
     traces = np.zeros(2)
-    opts = make_opts(tol, max_outer, inner_tol, False, 0, mixed, False, variant, graph)
+    opts = make_opts(tol, max_outer, inner_tol, full, 0, mixed, audit, variant, graph)
+    opts.audit_every = int(audit_every)
     st = lib().elses_regions_solve(ctx._h, reg._h, K, _np_ptr(z), None if cw is None else _np_ptr(cw),
                                    ctypes.byref(opts), _dev_ptr(x), _dev_ptr(rho),
                                    None if cw is None else _np_ptr(traces), _dev_ptr(col_tr), _dev_ptr(iters),

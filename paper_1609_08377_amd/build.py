@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "libelses.so")
-SOURCES = ["capi.hip", "passes.hip", "shift.hip", "setup.hip", "spai.hip", "arnoldi.hip"]
+SOURCES = ["capi.hip", "passes.hip", "shift.hip", "setup.hip", "spai.hip", "arnoldi.hip", "region.hip",
+           "region_host.hip"]
 ARCH = os.environ.get("ELSES_OFFLOAD_ARCH", "gfx950")
 
 

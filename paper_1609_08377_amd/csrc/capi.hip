@@ -829,8 +829,29 @@ int choose_slots(int n_cols, int M, const elses_opts& o) {
 struct elses_regions_s {
     elses_ctx ctx = nullptr;
     elses_mat gm = nullptr;  // the caller's matrix (not owned)
-    elses_mat bm = nullptr;  // block-diagonal tile matrix (owned)
+    elses_mat bm = nullptr;  // block-diagonal tile matrix (owned; tile layout only)
     int L = 64, n_tiles = 0, n_cols = 0, n_regions = 0;
+    // compact layout (tile_width 0): every region on its own, one persistent launch
+    bool compact = false;
+    struct Compact {
+        std::vector<RegionDesc> reg;
+        std::vector<int> col_region, region_nnz, order;
+        std::vector<int64_t> region_ent;
+        // regions grouped by vector width (4, 2, 1): group g is order[goff[g] .. goff[g+1]);
+        // one launch per group
+        int goff[4] = {0, 0, 0, 0};
+        int gcw[3] = {4, 2, 1};
+        int gmaxP[3] = {0, 0, 0};
+        int64_t lane_rows = 0;  // sum over regions of positions x column width
+        bool has32 = false;
+        RegionDesc* d_reg = nullptr;
+        int *d_order = nullptr, *d_slice_len = nullptr, *d_slice_ent = nullptr, *d_col_pos = nullptr,
+            *d_pat_pos = nullptr;
+        uint16_t *d_idx = nullptr, *d_pos_row = nullptr;
+        double *d_A64 = nullptr, *d_B64 = nullptr, *d_pat_B = nullptr, *d_pat_A = nullptr;
+        float *d_A32 = nullptr, *d_B32 = nullptr;
+        int64_t* d_pat_off = nullptr;
+    } cp;
     std::vector<int> cols;         // global orbital of each column, region by region
     std::vector<int> col_row;      // row of each column's unit vector in bm
     std::vector<int> slot_map;     // [n_tiles * L] column of each slot or -1
@@ -839,6 +860,7 @@ struct elses_regions_s {
     std::vector<int64_t> vidx;     // internal value index of X_ji in gm per pattern entry
     std::vector<int> group_tile;   // tile of each row group of bm (non-decreasing)
     std::vector<int> region_orbs;  // orbitals of each region
+    std::vector<int> centres;      // centre atom of each region
     std::vector<int> region_tile;
     std::vector<int> tile_row0;    // [n_tiles + 1] first row of each tile in bm
     int64_t useful = 0;            // sum over columns of their region's orbitals
@@ -853,32 +875,132 @@ struct elses_regions_s {
         void* p[] = {d_mask, d_col_row, d_rows, d_vidx, d_pat_off, d_slot_map, d_row_tile};
         for (void* q : p)
             if (q) (void)hipFree(q);
+        void* c[] = {cp.d_reg, cp.d_order, cp.d_slice_len, cp.d_slice_ent, cp.d_col_pos, cp.d_pat_pos, cp.d_idx,
+                     cp.d_pos_row, cp.d_A64, cp.d_B64, cp.d_pat_B, cp.d_pat_A, cp.d_A32, cp.d_B32, cp.d_pat_off};
+        for (void* q : c)
+            if (q) (void)hipFree(q);
         if (bm) elses_mat_destroy(bm);
     }
 };
 
 namespace {
 
-elses_status regions_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, const int32_t* centres,
-                                 const double* radii, int tile_width, elses_regions* out) {
+template <typename T>
+T* upload(const std::vector<T>& v) {
+    T* p = dalloc<T>(v.size());
+    if (!v.empty()) HCHECK(hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return p;
+}
+
+// Compact layout: each region's principal sub-pencil laid out on its own
+// (region.hip), solved by one persistent launch with a largest-first queue.
+elses_status compact_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, const int32_t* centres,
+                                 const double* radii, const uint8_t* orb_mask, elses_regions* out) {
+    const HostMatrix& h = gm->h;
+    CompactHost H;
+    const char* err = build_compact(h, n_regions, centres, radii, orb_mask, gm->precision == ELSES_MIXED, H);
+    if (err) return set_err(ctx, ELSES_ERR_INVALID_ARG, err);
+    if (H.max_slices * 64 > 8192)
+        return set_err(ctx, ELSES_ERR_INVALID_ARG,
+                       "a region exceeds 8192 orbitals, the compact layout's limit; use tile_width 64 or 128");
+    auto* P = new elses_regions_s();
+    P->centres.assign(centres, centres + n_regions);
+    P->ctx = ctx;
+    P->gm = gm;
+    P->L = 0;
+    P->compact = true;
+    P->n_regions = n_regions;
+    P->n_tiles = 0;
+    P->cols = H.cols;
+    P->pat_off = H.pat_off;
+    P->region_orbs = H.region_orbs;
+    P->n_cols = (int)H.cols.size();
+    P->useful = H.useful;
+    auto& C = P->cp;
+    C.reg = H.reg;
+    C.col_region = H.col_region;
+    C.has32 = gm->precision == ELSES_MIXED;
+    // per region: nonzeros (algorithmic bytes) and padded entries; lane-rows
+    C.region_nnz.assign(n_regions, 0);
+    C.region_ent.assign(n_regions, 0);
+    for (int r = 0; r < n_regions; ++r) {
+        const RegionDesc& D = H.reg[r];
+        C.region_nnz[r] = (int)H.region_nnz[r];
+        C.region_ent[r] = (r + 1 < n_regions ? H.reg[r + 1].ent0 : (int64_t)H.idx.size()) - D.ent0;
+        C.lane_rows += (int64_t)D.nslice * 64 * D.cw;
+    }
+    // queue order per vector width: largest region first
+    C.order.clear();
+    for (int g = 0; g < 3; ++g) {
+        C.goff[g] = (int)C.order.size();
+        std::vector<int> grp;
+        for (int r = 0; r < n_regions; ++r)
+            if (H.reg[r].cw == C.gcw[g]) {
+                grp.push_back(r);
+                C.gmaxP[g] = std::max(C.gmaxP[g], H.reg[r].nslice * 64);
+            }
+        std::stable_sort(grp.begin(), grp.end(),
+                         [&](int a, int b) { return H.reg[a].nslice > H.reg[b].nslice; });
+        C.order.insert(C.order.end(), grp.begin(), grp.end());
+    }
+    C.goff[3] = (int)C.order.size();
+    try {
+        C.d_reg = upload(H.reg);
+        C.d_order = upload(C.order);
+        C.d_slice_len = upload(H.slice_len);
+        C.d_slice_ent = upload(H.slice_ent);
+        C.d_col_pos = upload(H.col_pos);
+        C.d_pat_pos = upload(H.pat_pos);
+        C.d_idx = upload(H.idx);
+        C.d_pos_row = upload(H.pos_row);
+        C.d_A64 = upload(H.A64);
+        C.d_B64 = upload(H.B64);
+        C.d_pat_B = upload(H.pat_B);
+        C.d_pat_A = upload(H.pat_A);
+        C.d_pat_off = upload(H.pat_off);
+        if (C.has32) {
+            C.d_A32 = upload(H.A32);
+            C.d_B32 = upload(H.B32);
+        }
+    } catch (const HipFail& f) {
+        delete P;
+        const elses_status s = (f.e == hipErrorOutOfMemory) ? ELSES_ERR_OOM : ELSES_ERR_HIP;
+        return set_err(ctx, s, std::string(f.what) + ": " + hipGetErrorString(f.e));
+    }
+    *out = P;
+    return ELSES_OK;
+}
+
+elses_status regions_check(elses_ctx ctx, elses_mat gm, int n_regions, const int32_t* centres, const double* radii) {
     const HostMatrix& h = gm->h;
     const int N = h.n_atoms;
     if (h.n_orb.empty()) return set_err(ctx, ELSES_ERR_INVALID_ARG, "regions need a caller-created matrix");
     if (h.pos.empty()) return set_err(ctx, ELSES_ERR_INVALID_ARG, "regions need atom positions (pos)");
     if (n_regions < 1 || !centres || !radii) return set_err(ctx, ELSES_ERR_INVALID_ARG, "no regions");
-    const int L = tile_width == 0 ? 64 : tile_width;
-    if (L != 64 && L != 128) return set_err(ctx, ELSES_ERR_INVALID_ARG, "tile_width must be 0, 64 or 128");
-    {
-        std::vector<char> seen(N, 0);
-        for (int r = 0; r < n_regions; ++r) {
-            if (centres[r] < 0 || centres[r] >= N) return set_err(ctx, ELSES_ERR_INVALID_ARG, "centre out of range");
-            if (seen[centres[r]]) return set_err(ctx, ELSES_ERR_INVALID_ARG, "duplicate centre");
-            seen[centres[r]] = 1;
-            if (!(radii[r] > 0.0) || !std::isfinite(radii[r]))
-                return set_err(ctx, ELSES_ERR_INVALID_ARG, "radii must be finite and > 0");
-        }
+    std::vector<char> seen(N, 0);
+    for (int r = 0; r < n_regions; ++r) {
+        if (centres[r] < 0 || centres[r] >= N) return set_err(ctx, ELSES_ERR_INVALID_ARG, "centre out of range");
+        if (seen[centres[r]]) return set_err(ctx, ELSES_ERR_INVALID_ARG, "duplicate centre");
+        seen[centres[r]] = 1;
+        if (!(radii[r] > 0.0) || !std::isfinite(radii[r]))
+            return set_err(ctx, ELSES_ERR_INVALID_ARG, "radii must be finite and > 0");
     }
+    return ELSES_OK;
+}
+
+elses_status regions_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, const int32_t* centres,
+                                 const double* radii, int tile_width, elses_regions* out) {
+    const HostMatrix& h = gm->h;
+    const int N = h.n_atoms;
+    {
+        const elses_status st = regions_check(ctx, gm, n_regions, centres, radii);
+        if (st != ELSES_OK) return st;
+    }
+    if (tile_width == 0) return compact_create_impl(ctx, gm, n_regions, centres, radii, nullptr, out);
+    const int L = tile_width;
+    if (L != 64 && L != 128) return set_err(ctx, ELSES_ERR_INVALID_ARG, "tile_width must be 0, 64 or 128");
     auto* P = new elses_regions_s();
+    P->centres.assign(centres, centres + n_regions);
     P->ctx = ctx;
     P->gm = gm;
     P->L = L;
@@ -1622,6 +1744,236 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
     return ELSES_OK;
 }
 
+// Region solves in the compact layout: argument checks, scratch, one
+// persistent launch (region.hip), then the trace sum.
+elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, const double* shifts, const double* cw,
+                           const elses_opts* opts_in, double* x_out, int32_t* iters_out, double* resid_out,
+                           double* rho_out, double* traces_out, double* col_traces_out) {
+    elses_opts o;
+    elses_opts_default(&o);
+    if (opts_in) o = *opts_in;
+    const elses_mat mat = rp->gm;
+    const auto& C = rp->cp;
+    const bool density = (cw != nullptr);
+    const int n_cols = rp->n_cols;
+    if (K < 1 || K > 256) return set_err(ctx, ELSES_ERR_INVALID_ARG, "n_shifts must be in [1, 256]");
+    if (!shifts) return set_err(ctx, ELSES_ERR_INVALID_ARG, "shifts is null");
+    for (int k = 0; k < K; ++k) {
+        if (!std::isfinite(shifts[2 * k]) || !std::isfinite(shifts[2 * k + 1]) || !(shifts[2 * k + 1] > 0.0))
+            return set_err(ctx, ELSES_ERR_INVALID_ARG, "every shift needs a finite value with Im z > 0");
+        if (density && (!std::isfinite(cw[2 * k]) || !std::isfinite(cw[2 * k + 1])))
+            return set_err(ctx, ELSES_ERR_INVALID_ARG, "non-finite density weight");
+    }
+    if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return set_err(ctx, ELSES_ERR_INVALID_ARG, "tol must be > 0");
+    if (o.max_outer < 1) return set_err(ctx, ELSES_ERR_INVALID_ARG, "max_outer must be >= 1");
+    if (!(o.inner_tol > 0.0 && o.inner_tol < 1.0))
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "inner_tol must be in (0, 1)");
+    if (o.out_mode != ELSES_OUT_PATTERN && o.out_mode != ELSES_OUT_FULL)
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "out_mode must be PATTERN or FULL");
+    if (o.use_mixed && !C.has32)
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "use_mixed needs a matrix created with ELSES_MIXED");
+    const bool full = (o.out_mode == ELSES_OUT_FULL);
+    if (full && density)
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "density matrix output uses the pattern mode");
+    if (o.audit && (!full || !resid_out))
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "audit needs ELSES_OUT_FULL and resid_out");
+    if (o.audit_every < 0) return set_err(ctx, ELSES_ERR_INVALID_ARG, "audit_every must be >= 0");
+    if (o.audit_every > 0 && (full || !resid_out))
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "audit_every needs the pattern mode and resid_out");
+    if (traces_out) traces_out[0] = traces_out[1] = 0.0;
+    const bool mixed = o.use_mixed != 0;
+    const Rich rich = richardson_plan(mat->b_lo, mat->b_hi, mixed ? std::sqrt(o.inner_tol) : o.inner_tol);
+    // one launch per vector-width group: LDS of its largest iterate, resident workgroups
+    size_t glds[3] = {0, 0, 0};
+    int gwg[3] = {0, 0, 0};
+    for (int g = 0; g < 3; ++g) {
+        const int cnt = C.goff[g + 1] - C.goff[g];
+        if (cnt == 0) continue;
+        glds[g] = (size_t)C.gmaxP[g] * C.gcw[g] * (mixed ? 4 : 8);
+        const int occ = compact_occupancy(!mixed, C.gcw[g], glds[g]);
+        if (occ < 1)
+            return set_err(ctx, ELSES_ERR_INVALID_ARG,
+                           "the largest region's overlap iterate does not fit in LDS; use tile_width 64 or 128");
+        gwg[g] = std::max(1, std::min(cnt, occ * ctx->n_cu));
+    }
+    // carried rows per column: the pattern, or every position of the region (full output, audits)
+    std::vector<int> carry_full(n_cols, 0);
+    std::vector<int64_t> carry_off(n_cols + 1, 0), full_off(n_cols + 1, 0);
+    for (int c = 0; c < n_cols; ++c) {
+        const RegionDesc& D = C.reg[C.col_region[c]];
+        carry_full[c] = (full || (o.audit_every > 0 && c % o.audit_every == 0)) ? 1 : 0;
+        const int64_t len = carry_full[c] ? (int64_t)D.nslice * 64 : rp->pat_off[c + 1] - rp->pat_off[c];
+        carry_off[c + 1] = carry_off[c] + len * K;
+        full_off[c + 1] = full_off[c] + D.m;
+    }
+    // per-workgroup scratch: seven [P][cw] FP64 blocks, for the largest group
+    size_t vstride = 0, vtotal = 0;
+    for (int g = 0; g < 3; ++g) {
+        const size_t st_g = (size_t)7 * C.gmaxP[g] * C.gcw[g];
+        vstride = std::max(vstride, st_g);
+        vtotal = std::max(vtotal, st_g * gwg[g]);
+    }
+    int n_notconv = 0;
+    try {
+        HCHECK(hipSetDevice(ctx->device));
+        hipStream_t st = ctx->stream;
+        DevPool pool;
+        CompactArgs a{};
+        a.reg = C.d_reg;
+        a.order = C.d_order;
+        a.n_regions = rp->n_regions;
+        a.slice_len = C.d_slice_len;
+        a.slice_ent = C.d_slice_ent;
+        a.idx = C.d_idx;
+        a.A64 = C.d_A64;
+        a.B64 = C.d_B64;
+        a.A32 = C.d_A32;
+        a.B32 = C.d_B32;
+        a.pos_row = C.d_pos_row;
+        a.col_pos = C.d_col_pos;
+        a.pat_off = C.d_pat_off;
+        a.pat_pos = C.d_pat_pos;
+        a.pat_B = C.d_pat_B;
+        a.pat_A = C.d_pat_A;
+        int64_t* d_carry_off = pool.get<int64_t>(n_cols + 1);
+        int* d_carry_full = pool.get<int>(n_cols);
+        int64_t* d_full_off = pool.get<int64_t>(n_cols + 1);
+        HCHECK(hipMemcpyAsync(d_carry_off, carry_off.data(), sizeof(int64_t) * (n_cols + 1), hipMemcpyHostToDevice,
+                              st));
+        HCHECK(hipMemcpyAsync(d_carry_full, carry_full.data(), sizeof(int) * n_cols, hipMemcpyHostToDevice, st));
+        HCHECK(hipMemcpyAsync(d_full_off, full_off.data(), sizeof(int64_t) * (n_cols + 1), hipMemcpyHostToDevice,
+                              st));
+        a.carry_off = d_carry_off;
+        a.carry_full = d_carry_full;
+        a.full_off = d_full_off;
+        a.full_out = full ? 1 : 0;
+        a.audit = (o.audit || o.audit_every > 0) ? 1 : 0;
+        a.K = K;
+        double* d_z = pool.get<double>(2 * K);
+        HCHECK(hipMemcpyAsync(d_z, shifts, sizeof(double) * 2 * K, hipMemcpyHostToDevice, st));
+        a.z = d_z;
+        double* d_cw = nullptr;
+        if (density) {
+            d_cw = pool.get<double>(2 * K);
+            HCHECK(hipMemcpyAsync(d_cw, cw, sizeof(double) * 2 * K, hipMemcpyHostToDevice, st));
+        }
+        a.cw = d_cw;
+        a.tol = o.tol;
+        a.max_outer = o.max_outer;
+        a.d = rich.d;
+        double* d_tau = pool.get<double>(std::max<size_t>(1, rich.tau.size()));
+        HCHECK(hipMemcpyAsync(d_tau, rich.tau.data(), sizeof(double) * rich.tau.size(), hipMemcpyHostToDevice, st));
+        a.tau = d_tau;
+        a.g0 = rich.g0;
+        a.vec = pool.get<double>(vtotal);
+        a.eta = pool.get<double>((size_t)n_cols * K * 2);
+        a.zeta = pool.get<double>((size_t)n_cols * K * 2);
+        a.res = pool.get<double>((size_t)n_cols * K);
+        a.fac = pool.get<double>((size_t)n_cols * K * 4);
+        a.conv = pool.get<int>((size_t)n_cols * K);
+        HCHECK(hipMemsetAsync(a.conv, 0, sizeof(int) * n_cols * K, st));
+        a.xs = pool.get<double>((size_t)carry_off[n_cols] * 2);
+        a.ps = pool.get<double>((size_t)carry_off[n_cols] * 2);
+        int* counters = pool.get<int>(4);  // three queues, then the not-converged count
+        HCHECK(hipMemsetAsync(counters, 0, sizeof(int) * 4, st));
+        a.n_notconv = counters + 3;
+        a.x_out = x_out;
+        int32_t* iters = iters_out ? iters_out : pool.get<int32_t>(n_cols);
+        a.iters_out = iters;
+        a.resid_out = resid_out;
+        a.rho_out = rho_out;
+        double* ctr = col_traces_out;
+        if (density && !ctr && traces_out) ctr = pool.get<double>(2 * (size_t)n_cols);
+        a.ctr_out = density ? ctr : nullptr;
+        // per group: HIP events around its launch (profiling enabled)
+        hipEvent_t ev[3][2] = {};
+        const bool timed = ctx->prof_stride > 0;
+        for (int g = 0; g < 3; ++g) {
+            const int cnt = C.goff[g + 1] - C.goff[g];
+            if (cnt == 0) continue;
+            a.order = C.d_order + C.goff[g];
+            a.n_regions = cnt;
+            a.queue = counters + g;
+            a.vec_stride = (size_t)7 * C.gmaxP[g] * C.gcw[g];
+            if (timed) {
+                HCHECK(hipEventCreate(&ev[g][0]));
+                HCHECK(hipEventCreate(&ev[g][1]));
+                HCHECK(hipEventRecord(ev[g][0], st));
+            }
+            launch_compact(a, !mixed, C.gcw[g], gwg[g], glds[g], st);
+            HCHECK(hipGetLastError());
+            if (timed) HCHECK(hipEventRecord(ev[g][1], st));
+        }
+        double* tr2 = nullptr;
+        if (density && traces_out && ctr) {
+            tr2 = pool.get<double>(2);
+            launch_sum_pairs(ctr, n_cols, tr2, st);
+            HCHECK(hipMemcpyAsync(traces_out, tr2, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+        }
+        int h_cnt[4] = {0, 0, 0, 0};
+        HCHECK(hipMemcpyAsync(h_cnt, counters, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+        HCHECK(hipStreamSynchronize(st));
+        n_notconv = h_cnt[3];
+        // algorithmic bytes of the launch: per outer step of a region, its
+        // sparse products (index + value per nonzero), the carried x and p
+        // (read and written), and the Lanczos vectors in scratch
+        std::vector<int32_t> it_h(n_cols);
+        HCHECK(hipMemcpy(it_h.data(), iters, sizeof(int32_t) * n_cols, hipMemcpyDeviceToHost));
+        const double vb = mixed ? 4.0 : 8.0;
+        const double products = mixed ? (2.0 * (rich.d - 1) + 1.0) : (double)(rich.d - 1);
+        double gbytes[3] = {0, 0, 0}, gflops[3] = {0, 0, 0};
+        int64_t outer = 0;
+        for (int r = 0; r < rp->n_regions; ++r) {
+            const RegionDesc& D = C.reg[r];
+            const int g = D.cw == 4 ? 0 : (D.cw == 2 ? 1 : 2);
+            int n_it = 0;
+            double carried = 0.0;
+            for (int c = D.col0; c < D.col0 + D.ncol; ++c) {
+                n_it = std::max(n_it, (int)it_h[c]);
+                carried += (double)(carry_off[c + 1] - carry_off[c]);
+            }
+            const double nnz = (double)C.region_nnz[r];
+            const double per_it = nnz * (2.0 + vb) * products + nnz * (2.0 + vb) + 64.0 * carried +
+                                  18.0 * 8.0 * (double)D.m * D.cw;
+            gbytes[g] += (n_it + 1) * per_it;
+            gflops[g] += (n_it + 1) * (2.0 * nnz * D.cw * (products + 1.0));
+            outer += n_it;
+        }
+        if (timed) {
+            // the statistics describe the group launch that took longest
+            int gbest = -1;
+            float best = -1.f;
+            for (int g = 0; g < 3; ++g) {
+                if (!ev[g][0]) continue;
+                float ms = 0.f;
+                HCHECK(hipEventElapsedTime(&ms, ev[g][0], ev[g][1]));
+                if (ms > best) {
+                    best = ms;
+                    gbest = g;
+                }
+            }
+            if (gbest >= 0) {
+                ctx->prof_ms += best;
+                ctx->prof_launches += 1;
+                ctx->prof_bytes = gbytes[gbest];
+                ctx->prof_flops = gflops[gbest];
+                ctx->prof_slots = C.gcw[gbest];
+            }
+            for (auto& e : ev)
+                for (hipEvent_t x : e)
+                    if (x) (void)hipEventDestroy(x);
+        }
+        ctx->total_passes += outer;
+    } catch (const HipFail& f) {
+        const elses_status s = (f.e == hipErrorOutOfMemory) ? ELSES_ERR_OOM : ELSES_ERR_HIP;
+        return set_err(ctx, s, std::string(f.what) + ": " + hipGetErrorString(f.e));
+    }
+    if (n_notconv > 0)
+        return set_err(ctx, ELSES_WARN_NOT_CONVERGED,
+                       std::to_string(n_notconv) + " column(s) reached max_outer before every shift converged");
+    return ELSES_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1754,6 +2106,20 @@ elses_status elses_regions_create(elses_ctx ctx, elses_mat mat, int32_t n_region
     return regions_create_impl(ctx, mat, n_regions, centres, radii, tile_width, out);
 }
 
+elses_status elses_regions_create_ex(elses_ctx ctx, elses_mat mat, int32_t n_regions, const int32_t* centres,
+                                     const double* radii, const uint8_t* orb_mask, elses_regions* out) {
+    if (!ctx || !mat || !out) return ELSES_ERR_INVALID_ARG;
+    *out = nullptr;
+    try {
+        HCHECK(hipSetDevice(ctx->device));
+    } catch (const HipFail& f) {
+        return set_err(ctx, ELSES_ERR_HIP, std::string(f.what) + ": " + hipGetErrorString(f.e));
+    }
+    const elses_status st = regions_check(ctx, mat, n_regions, centres, radii);
+    if (st != ELSES_OK) return st;
+    return compact_create_impl(ctx, mat, n_regions, centres, radii, orb_mask, out);
+}
+
 void elses_regions_destroy(elses_regions reg) { delete reg; }
 
 elses_status elses_regions_info(elses_regions reg, int32_t* n_cols, int32_t* n_tiles, int64_t* rows_total,
@@ -1761,11 +2127,25 @@ elses_status elses_regions_info(elses_regions reg, int32_t* n_cols, int32_t* n_t
     if (!reg) return ELSES_ERR_INVALID_ARG;
     if (n_cols) *n_cols = reg->n_cols;
     if (n_tiles) *n_tiles = reg->n_tiles;
-    if (rows_total) *rows_total = reg->bm->d.M;
+    if (rows_total) *rows_total = reg->compact ? reg->cp.lane_rows : reg->bm->d.M;
     if (useful_rows) *useful_rows = reg->useful;
     if (cols) std::copy(reg->cols.begin(), reg->cols.end(), cols);
     if (pat_off) std::copy(reg->pat_off.begin(), reg->pat_off.end(), pat_off);
     if (region_orbitals) std::copy(reg->region_orbs.begin(), reg->region_orbs.end(), region_orbitals);
+    return ELSES_OK;
+}
+
+elses_status elses_regions_columns(elses_regions reg, int32_t* col_region) {
+    if (!reg || !col_region) return ELSES_ERR_INVALID_ARG;
+    if (reg->compact) {
+        std::copy(reg->cp.col_region.begin(), reg->cp.col_region.end(), col_region);
+    } else {
+        int c = 0;
+        for (int r = 0; r < reg->n_regions; ++r) {
+            const int nI = reg->gm->h.n_orb[reg->centres[r]];
+            for (int q = 0; q < nI; ++q) col_region[c++] = r;
+        }
+    }
     return ELSES_OK;
 }
 
@@ -1776,6 +2156,9 @@ elses_status elses_regions_solve(elses_ctx ctx, elses_regions reg, int32_t n_shi
     if (!ctx || !reg) return ELSES_ERR_INVALID_ARG;
     if (!c && (rho_out || traces_out || col_traces_out))
         return set_err(ctx, ELSES_ERR_INVALID_ARG, "density outputs need the weights c");
+    if (reg->compact)
+        return compact_solve(ctx, reg, n_shifts, shifts, c, opts, x_out, iters_out, resid_out, rho_out, traces_out,
+                             col_traces_out);
     return solve_core(ctx, reg->gm, reg->n_cols, reg->cols.data(), n_shifts, shifts, c, opts, x_out, iters_out,
                       resid_out, rho_out, traces_out, col_traces_out, reg);
 }
@@ -2847,6 +3230,8 @@ elses_status elses_regions_arnoldi(elses_ctx ctx, elses_regions reg, const elses
                                    double* w_I, double* w_B, double* w_A, int32_t* dim, double* rho_out,
                                    double* col_traces_out) {
     if (!ctx || !reg) return ELSES_ERR_INVALID_ARG;
+    if (reg->compact)
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "multiple Arnoldi runs on region tiles (tile_width 64 or 128)");
     return arnoldi_core(ctx, reg->gm, reg, reg->n_cols, reg->cols.data(), o, eps, w_I, w_B, w_A, dim, rho_out,
                         col_traces_out);
 }

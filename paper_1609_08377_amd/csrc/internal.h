@@ -310,6 +310,93 @@ void launch_infer_bf16(int64_t n, const uint16_t *Wbf, const float *params, cons
 void launch_spai_assemble(int64_t n, const int *pI, const int *pJ, const int *pb, const int *pbt,
                           const DevMatrix &d, const float *out, double *Mv, hipStream_t st);
 
+// Region problems in the compact per-region layout (region.hip): one
+// workgroup of kRegThreads threads solves one region at a time; the regions
+// come from a device queue.  See region.hip for the layout.
+constexpr int kRegThreads = 512;
+
+struct RegionDesc {
+    int m;         // orbitals of the region
+    int nslice;    // slices of 64 positions (P = 64 nslice)
+    int slice0;    // first slice in the slice tables
+    int col0;      // first column of the region in the column list
+    int ncol;      // columns solved (1..4)
+    int cw;        // column width of the region's vectors: 1, 2 or 4 (>= ncol)
+    int64_t ent0;  // first entry of the region's slices
+    int64_t pos0;  // first position in the position tables
+};
+
+struct CompactArgs {
+    const RegionDesc* reg;
+    const int* order;        // queue order of the regions (largest first)
+    int n_regions;
+    const int* slice_len;    // longest row of each slice
+    const int* slice_ent;    // first entry of each slice, relative to its region
+    const uint16_t* idx;     // entries: column position inside the region
+    const double *A64, *B64; // entries: FP64 values
+    const float *A32, *B32;  // entries: FP32 values (mixed precision)
+    const uint16_t* pos_row; // region orbital of each position (>= m: padding)
+    const int* col_pos;      // [n_cols] position of the column's unit vector
+    const int64_t* pat_off;  // [n_cols+1] pattern offsets (caller's layout)
+    const int* pat_pos;      // position of each pattern entry (-1 outside the region)
+    const double *pat_B, *pat_A;  // B_ji, A_ji of each pattern entry (traces)
+    const int64_t* carry_off;     // [n_cols] first carried entry of each column (x, p: [K][len])
+    const int* carry_full;        // [n_cols] 1: carried on every position of its region
+    const int64_t* full_off;      // [n_cols] first orbital of each column's full output block
+    int full_out;                 // x_out holds [K][m] region vectors per column
+    int audit;                    // resid_out of fully carried columns = FP64 true residual
+    int K;
+    const double* z;
+    const double* cw;
+    double tol;
+    int max_outer;
+    int d;                        // Richardson degree (per round)
+    const double* tau;            // [d-1] inverse Chebyshev roots (Leja order)
+    double g0;
+    double* vec;                  // per workgroup: six [Pmax][Cmax] FP64 blocks
+    size_t vec_stride;
+    double *eta, *zeta, *res, *fac;  // [n_cols][K] (x2, x2, x1, x4)
+    int* conv;                       // [n_cols][K] iteration of convergence, 0 running
+    double *xs, *ps;                 // carried x and p (complex)
+    int* queue;
+    int* n_notconv;
+    double* x_out;
+    int* iters_out;
+    double* resid_out;
+    double* rho_out;
+    double* ctr_out;
+};
+// resident workgroups per CU of the kernel for (precision, column width, LDS bytes)
+int compact_occupancy(bool fp64, int cw, size_t lds);
+// one persistent launch over the regions a.order[0 .. a.n_regions) (all of column width cw)
+void launch_compact(const CompactArgs& a, bool fp64, int cw, int n_wg, size_t lds, hipStream_t st);
+
+// Host-side construction of the compact layout (region_host.hip).
+struct CompactHost {
+    std::vector<RegionDesc> reg;
+    std::vector<int> slice_len, slice_ent;
+    std::vector<uint16_t> idx, pos_row;
+    std::vector<double> A64, B64;
+    std::vector<float> A32, B32;
+    std::vector<int> cols;      // global orbital of each column, region by region
+    std::vector<int> col_pos;   // position of each column's unit vector in its region
+    std::vector<int> col_region;
+    std::vector<int64_t> pat_off;
+    std::vector<int> pat_pos;
+    std::vector<double> pat_B, pat_A;
+    std::vector<int> region_orbs;
+    std::vector<int64_t> region_nnz;   // nonzeros of each region's matrices
+    int max_slices = 0;
+    int64_t useful = 0;
+    size_t lds_fp64 = 0, lds_fp32 = 0;  // LDS of the largest region (P x cw values)
+};
+// Carve the regions (atoms within radii[r] of centres[r], minimum image) and
+// build their compact layout.  orb_mask (may be null) selects the centre's
+// orbitals solved as columns (bit q: orbital q; 0 or null: all).  Returns an
+// error message or null.
+const char* build_compact(const HostMatrix& h, int n_regions, const int* centres, const double* radii,
+                          const uint8_t* orb_mask, bool want32, CompactHost& out);
+
 // Multiple Arnoldi method (arnoldi.hip).  Vector blocks are [rows][Lw]; row
 // chunks (ch_r0, ch_r1, ch_seg) lie inside one segment each, seg_ch0 lists
 // each segment's chunks; partials are [chunk][K][Lw], per-slot results

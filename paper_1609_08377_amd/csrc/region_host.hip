@@ -1,0 +1,314 @@
+// Host-side construction of the compact per-region layout (see region.hip).
+//
+// Region r is the set of atoms whose minimum-image distance to the centre
+// atom is <= radius (the paper's real-space projection, Sec. III-B, with a
+// radius in place of an atom count), in ascending atom order; its matrices
+// are the principal sub-blocks of A and B on those atoms.  The build runs on
+// all host threads: a cell list finds each region's atoms, then every region
+// is laid out independently into pre-computed offsets.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <functional>
+#include <thread>
+
+#include "internal.h"
+
+namespace elses {
+
+namespace {
+
+// Cell list of a periodic cube (or none: every query scans all atoms).
+struct Cells {
+    int nc = 0;
+    double side = 0;
+    std::vector<int> start, atoms;
+};
+
+Cells make_cells(const HostMatrix& h) {
+    Cells c;
+    if (!(h.box > 0.0)) return c;
+    int nc = (int)std::floor(h.box / 4.0);
+    nc = std::max(1, std::min(nc, 128));
+    c.nc = nc;
+    c.side = h.box / nc;
+    const int N = h.n_atoms;
+    std::vector<int> key(N);
+    for (int I = 0; I < N; ++I) {
+        int k[3];
+        for (int d = 0; d < 3; ++d) {
+            double p = std::fmod(h.pos[3 * I + d], h.box);
+            if (p < 0) p += h.box;
+            k[d] = std::min(nc - 1, (int)(p / c.side));
+        }
+        key[I] = (k[0] * nc + k[1]) * nc + k[2];
+    }
+    c.start.assign((size_t)nc * nc * nc + 1, 0);
+    for (int I = 0; I < N; ++I) c.start[key[I] + 1]++;
+    for (size_t q = 1; q < c.start.size(); ++q) c.start[q] += c.start[q - 1];
+    c.atoms.resize(N);
+    std::vector<int> fill(c.start.begin(), c.start.end() - 1);
+    for (int I = 0; I < N; ++I) c.atoms[fill[key[I]]++] = I;
+    return c;
+}
+
+// Atoms within radius R of atom `centre` (minimum image), ascending.
+void region_atoms(const HostMatrix& h, const Cells& cl, int centre, double R, std::vector<int>& out) {
+    out.clear();
+    const double cx = h.pos[3 * centre], cy = h.pos[3 * centre + 1], cz = h.pos[3 * centre + 2];
+    const double R2 = R * R, box = h.box;
+    auto test = [&](int I) {
+        double dx = h.pos[3 * I] - cx, dy = h.pos[3 * I + 1] - cy, dz = h.pos[3 * I + 2] - cz;
+        if (box > 0.0) {
+            dx -= box * std::nearbyint(dx / box);
+            dy -= box * std::nearbyint(dy / box);
+            dz -= box * std::nearbyint(dz / box);
+        }
+        if (dx * dx + dy * dy + dz * dz <= R2) out.push_back(I);
+    };
+    const int reach = cl.nc > 0 ? (int)std::ceil(R / cl.side) : 0;
+    if (cl.nc == 0 || 2 * reach + 1 >= cl.nc) {
+        for (int I = 0; I < h.n_atoms; ++I) test(I);
+        return;
+    }
+    const int nc = cl.nc;
+    int k[3];
+    for (int d = 0; d < 3; ++d) {
+        double p = std::fmod(h.pos[3 * centre + d], box);
+        if (p < 0) p += box;
+        k[d] = std::min(nc - 1, (int)(p / cl.side));
+    }
+    for (int dx = -reach; dx <= reach; ++dx)
+        for (int dy = -reach; dy <= reach; ++dy)
+            for (int dz = -reach; dz <= reach; ++dz) {
+                const int a = ((k[0] + dx) % nc + nc) % nc, b = ((k[1] + dy) % nc + nc) % nc,
+                          c = ((k[2] + dz) % nc + nc) % nc;
+                const int q = (a * nc + b) * nc + c;
+                for (int t = cl.start[q]; t < cl.start[q + 1]; ++t) test(cl.atoms[t]);
+            }
+    std::sort(out.begin(), out.end());
+}
+
+void parallel_for(int n, const std::function<void(int, int)>& body) {
+    int nt = (int)std::thread::hardware_concurrency();
+    nt = std::max(1, std::min(nt, 32));
+    nt = std::min(nt, std::max(1, n));
+    std::atomic<int> next{0};
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            for (;;) {
+                const int i = next.fetch_add(1);
+                if (i >= n) break;
+                body(i, t);
+            }
+        });
+    for (auto& x : th) x.join();
+}
+
+struct RegionPlan {
+    std::vector<int> atoms;   // ascending
+    std::vector<int> row_len; // per local atom: nonzeros of each of its rows
+    int m = 0, ncol = 0, cw = 1, nslice = 0;
+    int64_t n_ent = 0, nnz = 0;
+};
+
+}  // namespace
+
+const char* build_compact(const HostMatrix& h, int n_regions, const int* centres, const double* radii,
+                          const uint8_t* orb_mask, bool want32, CompactHost& out) {
+    const int N = h.n_atoms;
+    out = CompactHost();
+    const Cells cl = make_cells(h);
+    std::vector<RegionPlan> plan(n_regions);
+    int nthreads = std::max(1, std::min<int>((int)std::thread::hardware_concurrency(), 32));
+    std::vector<std::vector<int>> loc_t(nthreads, std::vector<int>());
+    std::atomic<int> too_big{0};
+    // pass 1: members, row lengths, sizes
+    parallel_for(n_regions, [&](int r, int t) {
+        std::vector<int>& loc = loc_t[t];
+        if (loc.empty()) loc.assign(N, -1);
+        RegionPlan& P = plan[r];
+        region_atoms(h, cl, centres[r], radii[r], P.atoms);
+        for (size_t a = 0; a < P.atoms.size(); ++a) loc[P.atoms[a]] = (int)a;
+        P.row_len.resize(P.atoms.size());
+        int m = 0;
+        int64_t ent = 0;
+        for (size_t a = 0; a < P.atoms.size(); ++a) {
+            const int I = P.atoms[a];
+            int len = 0;
+            for (int b = h.brow[I]; b < h.brow[I + 1]; ++b)
+                if (loc[h.bcol[b]] >= 0) len += h.n_orb[h.bcol[b]];
+            P.row_len[a] = len;
+            m += h.n_orb[I];
+            P.nnz += (int64_t)len * h.n_orb[I];
+        }
+        P.m = m;
+        P.nslice = (m + 63) / 64;
+        if (P.nslice * 64 > 65535) too_big.store(1);
+        // rows sorted by length, longest first: slice lengths from the sorted rows
+        std::vector<int> lens;
+        lens.reserve(m);
+        for (size_t a = 0; a < P.atoms.size(); ++a)
+            for (int q = 0; q < h.n_orb[P.atoms[a]]; ++q) lens.push_back(P.row_len[a]);
+        std::stable_sort(lens.begin(), lens.end(), std::greater<int>());
+        for (int s = 0; s < P.nslice; ++s) ent += (int64_t)lens[64 * s] * 64;
+        P.n_ent = ent;
+        const int nI = h.n_orb[centres[r]];
+        const int mask = (orb_mask && orb_mask[r]) ? (orb_mask[r] & ((1 << nI) - 1)) : ((1 << nI) - 1);
+        P.ncol = __builtin_popcount(mask);
+        P.cw = P.ncol <= 1 ? 1 : (P.ncol == 2 ? 2 : 4);
+        for (int a : P.atoms) loc[a] = -1;
+    });
+    if (too_big.load()) return "a region holds more than 65535 orbitals";
+    for (int r = 0; r < n_regions; ++r)
+        if (plan[r].ncol == 0) return "a region has no columns (orbital mask selects nothing)";
+    // offsets
+    out.reg.resize(n_regions);
+    int64_t ent = 0, pos = 0;
+    int slice = 0, col = 0;
+    std::vector<int64_t> pat0(n_regions);
+    int64_t pat = 0;
+    for (int r = 0; r < n_regions; ++r) {
+        RegionDesc& D = out.reg[r];
+        const RegionPlan& P = plan[r];
+        D.m = P.m;
+        D.nslice = P.nslice;
+        D.slice0 = slice;
+        D.col0 = col;
+        D.ncol = P.ncol;
+        D.cw = P.cw;
+        D.ent0 = ent;
+        D.pos0 = pos;
+        pat0[r] = pat;
+        ent += P.n_ent;
+        pos += (int64_t)P.nslice * 64;
+        slice += P.nslice;
+        col += P.ncol;
+        pat += (int64_t)P.ncol * h.atom_plen[centres[r]];
+        out.max_slices = std::max(out.max_slices, P.nslice);
+        out.lds_fp64 = std::max(out.lds_fp64, (size_t)P.nslice * 64 * P.cw * 8);
+        out.lds_fp32 = std::max(out.lds_fp32, (size_t)P.nslice * 64 * P.cw * 4);
+        out.region_orbs.push_back(P.m);
+        out.region_nnz.push_back(P.nnz);
+    }
+    if (ent >= ((int64_t)1 << 40)) return "region layout too large";
+    out.slice_len.assign(slice, 0);
+    out.slice_ent.assign(slice, 0);
+    out.idx.assign(ent, 0);
+    out.A64.assign(ent, 0.0);
+    out.B64.assign(ent, 0.0);
+    if (want32) {
+        out.A32.assign(ent, 0.0f);
+        out.B32.assign(ent, 0.0f);
+    }
+    out.pos_row.assign(pos, 0xFFFF);
+    out.cols.assign(col, 0);
+    out.col_pos.assign(col, 0);
+    out.col_region.assign(col, 0);
+    out.pat_off.assign(col + 1, 0);
+    out.pat_pos.assign(pat, -1);
+    out.pat_B.assign(pat, 0.0);
+    out.pat_A.assign(pat, 0.0);
+    {
+        int c = 0;
+        for (int r = 0; r < n_regions; ++r)
+            for (int q = 0; q < plan[r].ncol; ++q, ++c)
+                out.pat_off[c + 1] = out.pat_off[c] + h.atom_plen[centres[r]];
+    }
+    std::atomic<int> bad{0};
+    // pass 2: layout of every region
+    parallel_for(n_regions, [&](int r, int t) {
+        std::vector<int>& loc = loc_t[t];
+        if (loc.empty()) loc.assign(N, -1);
+        const RegionPlan& P = plan[r];
+        const RegionDesc& D = out.reg[r];
+        const int na = (int)P.atoms.size();
+        std::vector<int> aoff(na + 1, 0);
+        for (int a = 0; a < na; ++a) {
+            loc[P.atoms[a]] = a;
+            aoff[a + 1] = aoff[a] + h.n_orb[P.atoms[a]];
+        }
+        // rows in order of decreasing length (stable): position -> row
+        std::vector<int> row_atom(P.m), row_len(P.m), perm(P.m), row_pos(P.m);
+        for (int a = 0; a < na; ++a)
+            for (int q = aoff[a]; q < aoff[a + 1]; ++q) {
+                row_atom[q] = a;
+                row_len[q] = P.row_len[a];
+            }
+        for (int q = 0; q < P.m; ++q) perm[q] = q;
+        std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return row_len[x] > row_len[y]; });
+        for (int p = 0; p < P.m; ++p) row_pos[perm[p]] = p;
+        for (int p = 0; p < P.m; ++p) out.pos_row[D.pos0 + p] = (uint16_t)perm[p];
+        int64_t e_rel = 0;
+        for (int s = 0; s < P.nslice; ++s) {
+            const int len = row_len[perm[64 * s]];
+            out.slice_len[D.slice0 + s] = len;
+            out.slice_ent[D.slice0 + s] = (int)e_rel;
+            for (int l = 0; l < 64; ++l) {
+                const int p = 64 * s + l;
+                int k = 0;
+                const int64_t base = D.ent0 + e_rel + l;
+                if (p < P.m) {
+                    const int row = perm[p];
+                    const int a = row_atom[row];
+                    const int I = P.atoms[a];
+                    const int al = row - aoff[a];
+                    const int nI = h.n_orb[I];
+                    for (int b = h.brow[I]; b < h.brow[I + 1]; ++b) {
+                        const int J = h.bcol[b];
+                        const int lj = loc[J];
+                        if (lj < 0) continue;
+                        const int nJ = h.n_orb[J];
+                        const int64_t vo = h.in_voff[b] + (int64_t)al * nJ;
+                        for (int be = 0; be < nJ; ++be, ++k) {
+                            const int64_t e = base + (int64_t)k * 64;
+                            out.idx[e] = (uint16_t)row_pos[aoff[lj] + be];
+                            out.A64[e] = h.A_in[vo + be];
+                            out.B64[e] = h.B_in[vo + be];
+                            if (want32) {
+                                out.A32[e] = (float)h.A_in[vo + be];
+                                out.B32[e] = (float)h.B_in[vo + be];
+                            }
+                        }
+                    }
+                    (void)nI;
+                }
+                if (k > len) bad.store(1);
+                for (; k < len; ++k) out.idx[base + (int64_t)k * 64] = (uint16_t)p;  // zero padding
+            }
+            e_rel += (int64_t)len * 64;
+        }
+        if (e_rel != P.n_ent) bad.store(1);
+        // columns and their patterns (the caller's pattern of column j: the
+        // orbitals of the atoms coupled to j's atom, ascending)
+        const int C = centres[r];
+        const int nC = h.n_orb[C];
+        const int mask = (orb_mask && orb_mask[r]) ? (orb_mask[r] & ((1 << nC) - 1)) : ((1 << nC) - 1);
+        int c = D.col0;
+        int64_t po = pat0[r];
+        for (int q = 0; q < nC; ++q) {
+            if (!((mask >> q) & 1)) continue;
+            out.cols[c] = h.atom_off[C] + q;
+            out.col_pos[c] = row_pos[aoff[loc[C]] + q];
+            out.col_region[c] = r;
+            for (int b = h.brow[C]; b < h.brow[C + 1]; ++b) {
+                const int J = h.bcol[b];
+                const int nJ = h.n_orb[J];
+                const int lj = loc[J];
+                for (int be = 0; be < nJ; ++be, ++po) {
+                    out.pat_pos[po] = lj >= 0 ? row_pos[aoff[lj] + be] : -1;
+                    out.pat_B[po] = h.B_in[h.in_voff[b] + (int64_t)q * nJ + be];
+                    out.pat_A[po] = h.A_in[h.in_voff[b] + (int64_t)q * nJ + be];
+                }
+            }
+            ++c;
+        }
+        for (int a : P.atoms) loc[a] = -1;
+    });
+    if (bad.load()) return "internal: region layout sizes disagree";
+    for (int r = 0; r < n_regions; ++r) out.useful += (int64_t)plan[r].m * plan[r].ncol;
+    return nullptr;
+}
+
+}  // namespace elses

@@ -135,7 +135,7 @@ def test_regions_smaller_than_subspace_are_exact(ctx):
     mat = pk.Matrix.from_system(ctx, s)
     centres = np.arange(0, 40, dtype=np.int32)
     radii = np.full(centres.size, 2.3)
-    reg = pk.Regions(ctx, mat, centres, radii)
+    reg = pk.Regions(ctx, mat, centres, radii, tile_width=64)
     out = pk.region_arnoldi(ctx, reg, nu=30, mu=MU, kT=KT, want_rho=True)
     c = 0
     for cen in centres:

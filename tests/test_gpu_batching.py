@@ -57,7 +57,7 @@ def test_graph_replay_region_mode(el, ctx):
     mat = el.Matrix.from_system(ctx, s)
     rng = np.random.default_rng(3)
     centres = np.sort(rng.choice(s.n_atoms, size=30, replace=False)).astype(np.int32)
-    reg = el.Regions(ctx, mat, centres, rng.uniform(4.0, 7.0, size=30))
+    reg = el.Regions(ctx, mat, centres, rng.uniform(4.0, 7.0, size=30), 64)
     z = synth.shift_grid(16)
     a = el.region_solve(ctx, reg, z, tol=1e-9)
     b = el.region_solve(ctx, reg, z, tol=1e-9, graph=True)

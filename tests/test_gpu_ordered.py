@@ -57,7 +57,7 @@ def test_diamond_regions_are_equivalent(ctx):
     centres = np.arange(0, 48, dtype=np.int32)
     radii = synth.kappa_radii(s, centres, 40)
     assert np.ptp(radii) < 1e-9
-    reg = pk.Regions(ctx, mat, centres, radii)
+    reg = pk.Regions(ctx, mat, centres, radii, tile_width=64)
     z = synth.shift_grid(16)
     out = pk.region_solve(ctx, reg, z, tol=1e-8)
     it = out["iters"].cpu().numpy().reshape(-1, 4)

@@ -147,7 +147,7 @@ def test_region_density_and_traces(el, ctx, box):
             break
 
 
-@pytest.mark.parametrize("tile_width", [64, 128])
+@pytest.mark.parametrize("tile_width", [0, 64, 128])
 def test_region_mixed_and_tile_width(el, ctx, box, tile_width):
     s, mat, mat32 = box
     rng = np.random.default_rng(11)
