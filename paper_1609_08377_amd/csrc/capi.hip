@@ -1806,13 +1806,9 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         carry_off[c + 1] = carry_off[c] + len * K;
         full_off[c + 1] = full_off[c] + D.m;
     }
-    // per-workgroup scratch: seven [P][cw] FP64 blocks, for the largest group
-    size_t vstride = 0, vtotal = 0;
-    for (int g = 0; g < 3; ++g) {
-        const size_t st_g = (size_t)7 * C.gmaxP[g] * C.gcw[g];
-        vstride = std::max(vstride, st_g);
-        vtotal = std::max(vtotal, st_g * gwg[g]);
-    }
+    // per-workgroup scratch of each group: seven [P][cw] FP64 blocks
+    size_t gvec[3] = {0, 0, 0};
+    for (int g = 0; g < 3; ++g) gvec[g] = (size_t)7 * C.gmaxP[g] * C.gcw[g] * gwg[g];
     int n_notconv = 0;
     try {
         HCHECK(hipSetDevice(ctx->device));
@@ -1865,7 +1861,9 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         HCHECK(hipMemcpyAsync(d_tau, rich.tau.data(), sizeof(double) * rich.tau.size(), hipMemcpyHostToDevice, st));
         a.tau = d_tau;
         a.g0 = rich.g0;
-        a.vec = pool.get<double>(vtotal);
+        double* vec_g[3] = {nullptr, nullptr, nullptr};
+        for (int g = 0; g < 3; ++g)
+            if (gvec[g] > 0) vec_g[g] = pool.get<double>(gvec[g]);
         a.eta = pool.get<double>((size_t)n_cols * K * 2);
         a.zeta = pool.get<double>((size_t)n_cols * K * 2);
         a.res = pool.get<double>((size_t)n_cols * K);
@@ -1885,24 +1883,53 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         double* ctr = col_traces_out;
         if (density && !ctr && traces_out) ctr = pool.get<double>(2 * (size_t)n_cols);
         a.ctr_out = density ? ctr : nullptr;
-        // per group: HIP events around its launch (profiling enabled)
+        // One launch per group, on streams of their own (default priority) so
+        // that a group's last regions overlap the next group's work: the
+        // widest regions (longest per region) start first.  HIP events around
+        // each launch when profiling is enabled.
         hipEvent_t ev[3][2] = {};
         const bool timed = ctx->prof_stride > 0;
+        hipStream_t gst[3] = {st, nullptr, nullptr};
+        hipEvent_t ready = nullptr, gdone[3] = {};
+        struct StreamGuard {
+            hipStream_t* s;
+            hipEvent_t* e;
+            hipEvent_t* r;
+            ~StreamGuard() {
+                for (int g = 1; g < 3; ++g)
+                    if (s[g]) (void)hipStreamDestroy(s[g]);
+                for (int g = 0; g < 3; ++g)
+                    if (e[g]) (void)hipEventDestroy(e[g]);
+                if (*r) (void)hipEventDestroy(*r);
+            }
+        } guard{gst, gdone, &ready};
+        HCHECK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        HCHECK(hipEventRecord(ready, st));
         for (int g = 0; g < 3; ++g) {
             const int cnt = C.goff[g + 1] - C.goff[g];
             if (cnt == 0) continue;
+            if (g > 0) {
+                HCHECK(hipStreamCreateWithFlags(&gst[g], hipStreamNonBlocking));
+                HCHECK(hipStreamWaitEvent(gst[g], ready, 0));
+            }
             a.order = C.d_order + C.goff[g];
             a.n_regions = cnt;
             a.queue = counters + g;
+            a.vec = vec_g[g];
             a.vec_stride = (size_t)7 * C.gmaxP[g] * C.gcw[g];
             if (timed) {
                 HCHECK(hipEventCreate(&ev[g][0]));
                 HCHECK(hipEventCreate(&ev[g][1]));
-                HCHECK(hipEventRecord(ev[g][0], st));
+                HCHECK(hipEventRecord(ev[g][0], gst[g]));
             }
-            launch_compact(a, !mixed, C.gcw[g], gwg[g], glds[g], st);
+            launch_compact(a, !mixed, C.gcw[g], gwg[g], glds[g], gst[g]);
             HCHECK(hipGetLastError());
-            if (timed) HCHECK(hipEventRecord(ev[g][1], st));
+            if (timed) HCHECK(hipEventRecord(ev[g][1], gst[g]));
+            if (g > 0) {
+                HCHECK(hipEventCreateWithFlags(&gdone[g], hipEventDisableTiming));
+                HCHECK(hipEventRecord(gdone[g], gst[g]));
+                HCHECK(hipStreamWaitEvent(st, gdone[g], 0));
+            }
         }
         double* tr2 = nullptr;
         if (density && traces_out && ctr) {

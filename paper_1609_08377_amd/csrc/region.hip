@@ -116,7 +116,7 @@ __device__ __forceinline__ void row_product(const uint16_t* __restrict__ ib, con
                                             int len, const TX* src, TA (&acc)[C]) {
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = TA(0);
-#pragma unroll 4
+#pragma unroll 16
     for (int k = 0; k < len; ++k) {
         const uint32_t e = e0 + 64u * (uint32_t)k;
         const uint32_t j = ib[e];
