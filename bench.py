@@ -58,14 +58,24 @@ WORKLOADS = {
     "c2": (4096, 64, "4096-atom amorphous hydrocarbon box (C:H=1:2, 1.0 g/cm^3), M=8191 (4x4/4x1/1x1 atom "
                      "blocks, ~71 nnz/row), all 8191 columns x 64 shifts z=eps_k+0.01i on [-1,1] Ha, FP64, "
                      "tol 1e-8, global"),
-    "c5": (1000000, 128, "one-GPU share of a 10^6-atom amorphous hydrocarbon box (M=2.0e6, FP32-stored A and "
-                         "B), the FP32 Richardson pass of the overlap solve on a block of right-hand sides"),
+    "c5": (1000000, 128, "one-GPU share of a 10^6-atom amorphous hydrocarbon box (C:H=1:2, 1.0 g/cm^3, "
+                         "M=2.0e6, FP32-stored A and B): 65536 columns sampled uniformly, solved as region "
+                         "problems (atoms within a radius U[6,14] A of the column's atom; columns on one atom "
+                         "share its region) x 128 shifts z=eps_k+0.01i on [-1,1] Ha, tol 1e-8, compact "
+                         "per-region layout in one persistent launch per column-width group, FP32 overlap "
+                         "solves with FP64 refinement; rho on the patterns and tr(rho B) per column"),
+    "c4": (100000, 64, "100000-atom amorphous hydrocarbon box (M=2.0e5): 16384 columns sampled uniformly, "
+                       "solved as region problems (radius U[6,14] A) x 64 shifts, tol 1e-8, compact layout"),
     "c3": (50000, 64, "2048 local regions (centre atoms sampled without replacement, radius U[6,14] A, "
                       "187-3079 orbitals) carved from a 50000-atom amorphous hydrocarbon box (M=100001), all "
                       "orbitals of each centre x 64 shifts, packed into tiles and advanced by one launch "
                       "sequence, tol 1e-8"),
 }
 N_REGIONS = 2048
+# sampled-column workloads: columns sampled from the whole box, solved as region problems
+N_SAMPLED = {"c4": 16384, "c5": 65536}
+REGION_SOURCE = os.path.join(ROOT, "paper_1609_08377_amd", "csrc", "region.hip")
+C5_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "compact_kernel_c5_traffic.md")
 
 
 def cpu_baseline(sysm, shifts, gpu_iters_mean: float, budget_s: float = 20.0):
@@ -317,6 +327,274 @@ def run_balance(args):
     print(json.dumps(res), flush=True)
 
 
+def popcount8(m):
+    m = np.asarray(m, dtype=np.uint8)
+    return np.unpackbits(m[:, None], axis=1).sum(1)
+
+
+def cpu_baseline_regions(sysm, centres, masks, radii, z, gpu_iters_mean: float, budget_s: float = 20.0):
+    """The CPU oracle on a bounded sample of the benchmark's region columns: each
+    thread carves one column's region and runs the oracle's shifted COCG on it."""
+    import concurrent.futures as cf
+
+    import oracle
+    nthreads = oracle.max_threads()
+    rng = np.random.default_rng(13)
+    pick = rng.choice(centres.size, size=nthreads, replace=False)
+    jobs = []
+    for r in pick:
+        atoms = oracle.region_atoms(sysm, int(centres[r]), float(radii[r]))
+        Ar, Br, omap = oracle.carve_region(sysm, atoms)
+        q = int(np.nonzero([(int(masks[r]) >> b) & 1 for b in range(8)])[0][0])
+        j = int(sysm.orb_off[centres[r]]) + q
+        jobs.append((Ar, Br, int(np.nonzero(omap == j)[0][0])))
+
+    def run(job, n_it):
+        Ar, Br, jl = job
+        r = oracle.shifted_solve(Ar, Br, np.array([jl], np.int32), z, tol=1e-8, max_it=n_it, full=False,
+                                 true_residual=False, nthreads=1)
+        return float(r.iters[0])
+
+    with cf.ThreadPoolExecutor(max_workers=nthreads) as ex:
+        t0 = time.perf_counter()
+        list(ex.map(lambda jb: run(jb, 20), jobs))
+        per_it = (time.perf_counter() - t0) / 20
+        n_it = int(max(20, min(gpu_iters_mean, budget_s / max(per_it, 1e-9))))
+        t0 = time.perf_counter()
+        done = list(ex.map(lambda jb: run(jb, n_it), jobs))
+        t = time.perf_counter() - t0
+    done_it = float(np.mean(done))
+    t_full = t / done_it * gpu_iters_mean
+    value = len(jobs) * len(z) / t_full
+    sample = (f"{len(jobs)} region columns (one per thread, regions carved by the oracle) x {len(z)} shifts, "
+              f"oracle shifted COCG (CSR, CG overlap solves) run for {done_it:.0f} iterations in {t:.1f} s and "
+              f"scaled to the {gpu_iters_mean:.0f} outer iterations the GPU needed; COCG needs about 6 % more "
+              f"iterations than the GPU's Lanczos recurrences, so the scaled rate slightly flatters the oracle")
+    return {"value": value, "unit": "column-shift solves/s", "cores": nthreads, "kind": "oracle", "sample": sample}
+
+
+def train_spai(ctx, el, seed: int):
+    """The learned preconditioner's network, trained by the library's kernels on the exact
+    inverses of three 500-atom boxes of the same generator (FP32, Adam)."""
+    import torch
+
+    feats, targs, masks = [], [], []
+    for s_ in (11, 12, 13):
+        m = el.Matrix.from_system(ctx, __import__("synth").make_system(500, s_))
+        feats.append(el.spai_features(ctx, m))
+        T, W = el.spai_targets(ctx, m)
+        targs.append(T)
+        masks.append(W)
+    theta = torch.as_tensor(el.mlp_init(seed + 5), dtype=torch.float32).cuda()
+    el.spai_train(ctx, theta, torch.cat(feats), torch.cat(targs), torch.cat(masks), steps=1500, batch=4096,
+                  lr=2e-3, seed=1)
+    return theta
+
+
+def region_iters(sets, iters_all, args, n_sets):
+    """Sum over the timed steps of each region's outer iterations (its slowest column)."""
+    tot = 0
+    for st, it in enumerate(iters_all):
+        reg = sets[(args.warmup + st) % n_sets]
+        it = it.cpu().numpy()
+        per = np.zeros(int(reg.col_region.max()) + 1, dtype=np.int64)
+        np.maximum.at(per, reg.col_region, it)
+        tot += int(per.sum())
+    return tot
+
+
+def run_sampled(args):
+    """One step = one compact region-set solve (elses_regions_solve) over a batch of
+    consecutive sampled-column regions of the box: every region's shifted solve to
+    tol 1e-8 (Lanczos outer steps, FP32 Richardson overlap solves with FP64
+    refinement, fused multi-shift update), rho on the column patterns and
+    e_j^T rho B e_j, e_j^T rho A e_j per column.  The region sets are built before
+    the timed region; steps cycle through them."""
+    import ctypes
+
+    import torch
+
+    import synth
+    import paper_1609_08377_amd as el
+
+    cfg = args.config
+    n_atoms, K, desc = WORKLOADS[cfg]
+    seed = synth.config_seed(int(cfg[1:]))
+    t0 = time.perf_counter()
+    sysm = synth.make_system(n_atoms, seed)
+    t_gen = time.perf_counter() - t0
+    print(f"{cfg}: system generated in {t_gen:.1f} s (M={sysm.M})", file=sys.stderr, flush=True)
+    z = synth.shift_grid(K)
+    cw = (-(1.0 / np.pi) * (2.0 / K) * 0.5 * (1.0 - np.tanh(0.5 * (z.real - 0.0) / 0.01))).astype(np.complex128)
+    mixed = (args.precision or "mixed") == "mixed"
+    ctx = el.Context(0)
+    t0 = time.perf_counter()
+    mat = el.Matrix.from_system(ctx, sysm, precision="mixed")
+    t_mat = time.perf_counter() - t0
+    print(f"{cfg}: matrix uploaded in {t_mat:.1f} s", file=sys.stderr, flush=True)
+    precond = cfg == "c4" and not args.no_precond
+    t_train = 0.0
+    if precond:
+        t0 = time.perf_counter()
+        theta = train_spai(ctx, el, seed)
+        el.set_preconditioner(ctx, mat, theta, bf16=True)
+        t_train = time.perf_counter() - t0
+        print(f"{cfg}: network trained on 500-atom boxes and M assembled in {t_train:.1f} s", file=sys.stderr,
+              flush=True)
+    cols = synth.sample_columns(sysm, N_SAMPLED[cfg], seed)
+    centres, masks, radii = synth.column_regions(sysm, cols, seed)
+    ncol = popcount8(masks)
+    # batches of consecutive regions holding about args.batch columns each
+    cut = np.searchsorted(np.cumsum(ncol), np.arange(args.batch, ncol.sum(), args.batch), side="left") + 1
+    bounds = np.concatenate([[0], cut, [centres.size]])
+    batches = [(int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+    n_sets = max(1, min(len(batches), args.steps + args.warmup, args.max_sets))
+    t0 = time.perf_counter()
+    sets = []
+    for a, b in batches[:n_sets]:
+        sets.append(el.Regions(ctx, mat, centres[a:b], radii[a:b], orb_mask=masks[a:b]))
+    t_sets = time.perf_counter() - t0
+    print(f"{cfg}: {n_sets} region sets of ~{args.batch} columns built in {t_sets:.1f} s", file=sys.stderr,
+          flush=True)
+    lib = el.lib()
+    lib.elses_ctx_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.elses_ctx_pass_stats.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 6
+
+    def step(reg, **kw):
+        kw.setdefault("precond", precond)
+        return el.region_solve(ctx, reg, z, cw, want_x=True, mixed=mixed, **kw)
+
+    # load the kernels outside the timed region
+    small = el.Regions(ctx, mat, centres[:4], radii[:4], orb_mask=masks[:4])
+    step(small, max_outer=16, allow_not_converged=True)
+    for w in range(args.warmup):
+        step(sets[w % n_sets])
+        print(f"warmup {w + 1}/{args.warmup}", file=sys.stderr, flush=True)
+    lib.elses_ctx_set_profiling(ctx._h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_solves = 0
+    iters_all, resid_max, trace_b = [], 0.0, 0.0
+    products = fallbacks = 0
+    for st in range(args.steps):
+        reg = sets[(args.warmup + st) % n_sets]
+        out = step(reg)
+        n_solves += reg.n_cols * K
+        pr, fb = el.solve_counts(ctx)
+        products += pr
+        fallbacks += fb
+        iters_all.append(out["iters"])
+        resid_max = max(resid_max, float(out["resid"].max()))
+        trace_b += float(out["traces"][0])
+        print(f"step {st + 1}/{args.steps} done ({reg.n_cols} columns)", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launches, avg_us, nbytes, flops = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    total, width = ctypes.c_int64(), ctypes.c_int32()
+    lib.elses_ctx_pass_stats(ctx._h, ctypes.byref(launches), ctypes.byref(avg_us), ctypes.byref(nbytes),
+                             ctypes.byref(flops), ctypes.byref(total), ctypes.byref(width))
+    lib.elses_ctx_set_profiling(ctx._h, 0)
+    iters = torch.cat(iters_all).cpu().numpy()
+    value = n_solves / dt
+    achieved = nbytes.value / (avg_us.value * 1e-6) / 1e9 if avg_us.value > 0 else 0.0
+    tag = f"compact_{cfg}_{'mixed' if mixed else 'fp64'}_w{width.value}_b{args.batch}"
+    traffic = committed_traffic(tag, C5_TRAFFIC_SUMMARY, REGION_SOURCE)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": f"compact_kernel<{'float' if mixed else 'double'}, {width.value}> (persistent: every outer step "
+                      f"of every region, regions from a device queue; the launches of the other column widths "
+                      f"overlap it and are counted with it)",
+            "traffic_tag": tag, "bytes_per_launch": nbytes.value, "avg_launch_us": round(avg_us.value, 1),
+            "timed_launches": launches.value}
+    # audit subsample (untimed): the first regions of the first set, every column carried
+    # on its whole region and its FP64 true residual recomputed in the kernel
+    n_aud = min(48, centres.size)
+    areg = el.Regions(ctx, mat, centres[:n_aud], radii[:n_aud], orb_mask=masks[:n_aud])
+    aout = el.region_solve(ctx, areg, z, cw, want_x=False, mixed=mixed, audit_every=1, precond=precond)
+    audit_max = float(aout["resid"].max())
+    reg_orbs = np.concatenate([s_.region_orbitals for s_ in sets])
+    res = {
+        "metric": METRIC, "value": round(value, 2), "unit": "column-shift solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1000.0 * dt / args.steps, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32/f64 mixed" if mixed else "f64", "data": "synthetic",
+        "config": {"workload": cfg + ": " + desc, "n_atoms": n_atoms, "M": int(sysm.M), "nnz": int(sysm.nnz),
+                   "sampled_columns": int(cols.size), "regions": int(centres.size),
+                   "columns_per_step_target": args.batch, "batches_in_job": len(batches),
+                   "region_sets_built": n_sets, "columns_timed": int(n_solves // K), "shifts": K, "tol": 1e-8,
+                   "region_orbitals_min_mean_max": [int(reg_orbs.min()), round(float(reg_orbs.mean()), 1),
+                                                    int(reg_orbs.max())],
+                   "outer_iters_mean": round(float(iters.mean()), 1), "outer_iters_max": int(iters.max()),
+                   "max_resid_estimate": resid_max,
+                   "max_true_resid_audited": audit_max,
+                   "audited_columns": int(areg.n_cols),
+                   "trace_rhoB_timed_columns": trace_b,
+                   "sparse_products_per_region_iteration": round(products / max(1, region_iters(sets, iters_all, args,
+                                                                                                  n_sets)), 2),
+                   "learned_preconditioner": precond, "preconditioner_fallbacks": fallbacks,
+                   "system_generation_s": round(t_gen, 1), "matrix_upload_s": round(t_mat, 1),
+                   "network_training_s": round(t_train, 1), "region_set_build_s": round(t_sets, 1)},
+        "roofline": roof,
+    }
+    if precond:
+        # the same region sets with the plain overlap iteration (Chebyshev-Richardson), for the
+        # comparison the learned preconditioner is built for: outer iterations, products, time
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        its_p, prods_p, nc_p = [], 0, 0
+        for st in range(min(args.steps, n_sets)):
+            reg = sets[(args.warmup + st) % n_sets]
+            o2 = step(reg, precond=False)
+            prods_p += el.solve_counts(ctx)[0]
+            its_p.append(o2["iters"])
+            nc_p += reg.n_cols
+        torch.cuda.synchronize()
+        t_p = time.perf_counter() - t1
+        its_p = torch.cat(its_p).cpu().numpy()
+        its_q = torch.cat(iters_all[:min(args.steps, n_sets)]).cpu().numpy()
+        res["precond_comparison"] = {
+            "columns": int(nc_p),
+            "with_M": {"col_shift_per_s": round(value, 1), "outer_iters_mean": round(float(iters.mean()), 1),
+                       "sparse_products": int(products)},
+            "plain": {"col_shift_per_s": round(nc_p * K / t_p, 1), "outer_iters_mean": round(float(its_p.mean()), 1),
+                      "sparse_products": int(prods_p)},
+            "note": "with_M: overlap solves by CG preconditioned with the learned M (BF16 inference, FP32/FP64 "
+                    "values); plain: the Chebyshev-Richardson polynomial; products count A, B and M products "
+                    "per region (one product serves the region's columns)"}
+    if args.plain_sample > 0:
+        # the plain FP64 GPU method (tile layout, one launch sequence per outer step) against the
+        # compact mixed solve on the same columns
+        nb = int(np.searchsorted(np.cumsum(ncol), args.plain_sample)) + 1
+        print(f"timing the plain FP64 method on {int(ncol[:nb].sum())} columns", file=sys.stderr, flush=True)
+        preg = el.Regions(ctx, mat, centres[:nb], radii[:nb], 64, orb_mask=masks[:nb])
+        creg = el.Regions(ctx, mat, centres[:nb], radii[:nb], orb_mask=masks[:nb])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        el.region_solve(ctx, preg, z, cw, want_x=True, mixed=False)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        el.region_solve(ctx, creg, z, cw, want_x=True, mixed=mixed)
+        torch.cuda.synchronize()
+        t_comp = time.perf_counter() - t1
+        nsel = int(creg.n_cols)
+        plain_rate = nsel * K / t_plain
+        res["plain_fp64_comparison"] = {
+            "columns": nsel, "regions": nb,
+            "plain_fp64_tiles_col_shift_per_s": round(plain_rate, 1),
+            "this_path_same_sample_col_shift_per_s": round(nsel * K / t_comp, 1),
+            "value_over_plain": round(value / plain_rate, 2),
+            "note": "plain FP64 GPU method = the same shifted solves in FP64 with region tiles of 64 column "
+                    "slots advanced by one launch sequence per outer step (no persistent queue), timed on the "
+                    "first sampled regions; value_over_plain compares the timed steps' rate with it (the "
+                    "compact launch needs many more regions than this sample to fill the GPU)"}
+    if not args.no_cpu:
+        print("timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline_regions(sysm, centres, masks, radii, z, float(iters.mean()),
+                                                   args.cpu_budget)
+    print(json.dumps(res), flush=True)
+
+
 def run_pass(args):
     """The sparse pass alone at a workload's full matrix size: the Richardson step
     of the overlap solve (FP32-stored B with FP32 vectors for c5, FP64
@@ -365,19 +643,25 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--batch", type=int, default=1024, help="columns per step")
+    ap.add_argument("--config", default="c5", choices=sorted(WORKLOADS))
+    ap.add_argument("--batch", type=int, default=0, help="columns per step (0: 1024 for c2, 640 for c4/c5)")
+    ap.add_argument("--max-sets", type=int, default=8, help="c4/c5: region sets built (steps cycle through them)")
+    ap.add_argument("--plain-sample", type=int, default=192,
+                    help="c4/c5: columns on which the plain FP64 tile method is timed against this path (0: skip)")
     ap.add_argument("--cols", type=int, default=0, help="limit the column count (0 = all)")
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default: fp64 for c1/c2, mixed (FP32-stored A, B) for c3")
-    ap.add_argument("--tile", type=int, default=64, help="column slots per region tile (c3)")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="region layout: 0 compact, 64 / 128 tile width (default: compact for c3 solves, 64 for "
+                         "the arnoldi and balance methods, which need tiles)")
     ap.add_argument("--regions", type=int, default=N_REGIONS, help="c3: number of regions")
     ap.add_argument("--region-order", default="index", choices=["index", "size"],
                     help="c3: pack regions in atom order, or largest radius first")
     ap.add_argument("--copy-calib", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--variant", default="auto", choices=["auto", "direct", "staged8", "staged4", "grouped", "grouped2", "grouped1"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-precond", action="store_true", help="c4: skip the learned preconditioner")
     ap.add_argument("--max-outer", type=int, default=20000,
                     help="cap on outer iterations (profiling runs only: capped runs do not converge)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -402,13 +686,16 @@ def main():
     if args.method == "balance":
         run_balance(args)
         return
+    if args.batch == 0:
+        args.batch = 640 if args.config in N_SAMPLED else 1024
+    if args.tile < 0:
+        args.tile = 0 if args.method == "shifted" else 64
     if args.method == "pass":
         run_pass(args)
         return
-    if args.config == "c5":
-        print(json.dumps({"error": "c5 is measured with --method pass (the sparse pass at full matrix size); "
-                                   "its columns are solved in the full-size tests"}), flush=True)
-        sys.exit(2)
+    if args.config in N_SAMPLED:
+        run_sampled(args)
+        return
 
     import torch
 
@@ -443,9 +730,10 @@ def main():
             centres, radii = centres[o], radii[o]
         t_plan = time.perf_counter()
         reg = el.Regions(ctx, mat, centres, radii, args.tile)
-        extra = {"regions": int(centres.size), "region_tiles": reg.n_tiles, "tile_width": args.tile,
-                 "tile_rows_total": reg.rows_total,
-                 "useful_lane_fraction": round(reg.useful_rows / (reg.rows_total * args.tile), 4),
+        extra = {"regions": int(centres.size), "region_tiles": reg.n_tiles,
+                 "layout": "compact" if args.tile == 0 else f"tiles of {args.tile}",
+                 "lane_rows_total": reg.rows_total,
+                 "useful_lane_fraction": round(reg.useful_rows / (reg.rows_total * max(args.tile, 1)), 4),
                  "region_orbitals_min_mean_max": [int(reg.region_orbitals.min()),
                                                   round(float(reg.region_orbitals.mean()), 1),
                                                   int(reg.region_orbitals.max())],
@@ -528,7 +816,12 @@ def main():
     if region_mode:
         res["config"].pop("columns_per_step", None)
         res["config"]["batches_in_job"] = 1
-        res["config"]["idle_lane_fraction"] = round(tile_idle(sysm, centres, iters, args.tile), 4)
+        if args.tile > 0:
+            res["config"]["idle_lane_fraction"] = round(tile_idle(sysm, centres, iters, args.tile), 4)
+        else:
+            res["roofline"]["kernel"] = (f"compact_kernel<{'float' if mixed else 'double'}, {slots.value}> (one "
+                                         f"persistent launch per column-width group)")
+            res["roofline"]["traffic"] = None
     if not args.no_cpu and not region_mode:
         print("timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(sysm, z, float(iters.mean()), args.cpu_budget)

@@ -126,6 +126,12 @@ typedef struct {
                          /* c % audit_every == 0 are also carried on every row of their     */
                          /* region and their resid_out entries receive the recomputed FP64  */
                          /* true residual instead of the estimate; 0 (default) = none       */
+    int32_t precond;     /* compact region sets: 1 = overlap solves by conjugate gradients  */
+                         /* preconditioned with the learned M of elses_mat_set_preconditioner */
+                         /* (the set must be created after it); a region whose M fails      */
+                         /* (a non-positive curvature, or inner_max steps without reaching  */
+                         /* inner_tol) falls back to the plain iteration; default 0         */
+    int32_t inner_max;   /* preconditioned CG steps per solve before the fallback; 200      */
 } elses_opts;
 
 /* Fill *o with the defaults listed above. */
@@ -183,6 +189,15 @@ elses_status elses_density_matrix(elses_ctx ctx, elses_mat mat, int32_t n_cols, 
  *                  iterate; 8 or 4 bytes per entry)
  *   flops          2 * nnz * slots + 3 * M * slots
  *   total_passes   all passes (A and B products) launched by solves
+ * Region solves in the compact layout time their launches instead: the
+ * launches of the width groups (4, 2 or 1 columns per region) overlap, and
+ * one solve counts as one launch from the first group's start to the last
+ * group's end; bytes and flops are the means over the timed solves of the
+ * algorithmic traffic of all groups: per outer step of each region its sparse
+ * products (a 2-byte index plus the value, 4 or 8 bytes, per nonzero), the
+ * carried x and p (read and written, 64 bytes per shift and row) and its
+ * Lanczos vectors in scratch (18 x 8 bytes per row and column); slots = the
+ * column width of the group that moved most bytes.
  * Multiple Arnoldi calls (elses_arnoldi, elses_regions_arnoldi) sample their
  * Gram-Schmidt update passes instead (every stride-th launch, one launch per
  * sample; block b subtracts the projections of two candidates on the 2b basis
@@ -301,12 +316,13 @@ elses_status elses_spmm(elses_ctx ctx, elses_mat mat, int which, int32_t variant
 typedef struct elses_regions_s *elses_regions;
 elses_status elses_regions_create(elses_ctx ctx, elses_mat mat, int32_t n_regions, const int32_t *centres,
                                   const double *radii, int32_t tile_width, elses_regions *out);
-/* As elses_regions_create in the compact layout, with orb_mask (HOST uint8
- * [n_regions], may be NULL) selecting the centre's orbitals that are solved
- * as columns: bit q set = orbital q of the centre atom (0 = all orbitals).
- * Columns sampled on the same atom thus share one region (one solve). */
+/* As elses_regions_create, with orb_mask (HOST uint8 [n_regions], may be
+ * NULL) selecting the centre's orbitals that are solved as columns: bit q set
+ * = orbital q of the centre atom (0 = all orbitals).  Columns sampled on the
+ * same atom thus share one region (one solve). */
 elses_status elses_regions_create_ex(elses_ctx ctx, elses_mat mat, int32_t n_regions, const int32_t *centres,
-                                     const double *radii, const uint8_t *orb_mask, elses_regions *out);
+                                     const double *radii, const uint8_t *orb_mask, int32_t tile_width,
+                                     elses_regions *out);
 void elses_regions_destroy(elses_regions reg);
 /* Sizes and layout of a region set (HOST outputs, each may be NULL):
  * n_cols columns; n_tiles tiles (0 for the compact layout); rows_total rows of
@@ -390,6 +406,21 @@ elses_status elses_spai_predict(elses_ctx ctx, const float *params, int64_t n, c
  * symmetrised).  M_vals (DEVICE double, as many values as B) is in the
  * library's internal block order: an opaque buffer for elses_overlap_solve. */
 elses_status elses_spai_apply(elses_ctx ctx, elses_mat mat, const float *params, int32_t bf16, double *M_vals);
+/* Learned preconditioner of the overlap solves (Sec. III-B: B^{-1} enters
+ * every step of the generalized problem).  Runs the features, the network
+ * (params: DEVICE FP32 [ELSES_MLP_PARAMS], BF16 inference if bf16 != 0) and
+ * the assembly of M ~ B^{-1} on B's pattern (diagonal blocks symmetrised),
+ * and keeps M with the matrix.  Region sets created afterwards carry M's
+ * values with A and B (FP64, and FP32 for ELSES_MIXED), and their solves
+ * with opts->precond use it.  params = NULL removes M.  Needs atom positions.
+ * Errors: ELSES_ERR_INVALID_ARG for a non-finite network output. */
+elses_status elses_mat_set_preconditioner(elses_ctx ctx, elses_mat mat, const float *params, int32_t bf16);
+/* Work of the last compact region solve on this context: sparse products
+ * launched (A, B and M products, summed over the regions; per region one
+ * product serves all of its columns) and the number of regions whose
+ * preconditioned overlap solve fell back to the plain iteration (HOST
+ * outputs, each may be NULL). */
+elses_status elses_ctx_solve_counts(elses_ctx ctx, int64_t *products, int64_t *fallbacks);
 /* Overlap solve x = p(B) s for nvec right-hand sides (DEVICE double
  * [M][nvec], nvec a multiple of 64) to relative residual tol by Richardson
  * steps with Chebyshev roots.  With M_vals (from elses_spai_apply) the steps

@@ -59,7 +59,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("out_mode", ctypes.c_int32), ("slots", ctypes.c_int32), ("use_mixed", ctypes.c_int32),
                 ("audit", ctypes.c_int32), ("variant", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("audit_every", ctypes.c_int32)]
+                ("audit_every", ctypes.c_int32), ("precond", ctypes.c_int32), ("inner_max", ctypes.c_int32)]
 
 
 class ArnoldiOpts(ctypes.Structure):
@@ -123,10 +123,14 @@ def lib():
         L.elses_autotune.restype = ctypes.c_int
         L.elses_regions_create.argtypes = [P, P, I32, P, P, I32, ctypes.POINTER(P)]
         L.elses_regions_create.restype = ctypes.c_int
-        L.elses_regions_create_ex.argtypes = [P, P, I32, P, P, P, ctypes.POINTER(P)]
+        L.elses_regions_create_ex.argtypes = [P, P, I32, P, P, P, I32, ctypes.POINTER(P)]
         L.elses_regions_create_ex.restype = ctypes.c_int
         L.elses_regions_columns.argtypes = [P, P]
         L.elses_regions_columns.restype = ctypes.c_int
+        L.elses_mat_set_preconditioner.argtypes = [P, P, P, I32]
+        L.elses_mat_set_preconditioner.restype = ctypes.c_int
+        L.elses_ctx_solve_counts.argtypes = [P, P, P]
+        L.elses_ctx_solve_counts.restype = ctypes.c_int
         L.elses_regions_destroy.argtypes = [P]
         L.elses_regions_destroy.restype = None
         L.elses_regions_info.argtypes = [P, P, P, P, P, P, P, P]
@@ -373,7 +377,7 @@ def spmm32(ctx: Context, mat: Matrix, which: str, x, variant: str = "auto"):
 class Regions:
     """Region problems (principal sub-pencils around centre atoms) on the device: the compact layout
     (tile_width 0, one persistent launch) or tiles of 64 / 128 column slots.  orb_mask (one uint8 per
-    region, compact layout only) selects the centre's orbitals solved as columns (0 = all)."""
+    region) selects the centre's orbitals solved as columns (0 = all)."""
 
     def __init__(self, ctx: Context, mat: Matrix, centres, radii, tile_width: int = 0, orb_mask=None):
         self.ctx = ctx
@@ -384,13 +388,11 @@ class Regions:
             raise ValueError("one radius per centre")
         h = ctypes.c_void_p()
         if orb_mask is not None:
-            if tile_width != 0:
-                raise ValueError("orbital masks need the compact layout (tile_width 0)")
             mask = np.ascontiguousarray(orb_mask, dtype=np.uint8)
             if mask.shape != centres.shape:
                 raise ValueError("one orbital mask per centre")
             st = lib().elses_regions_create_ex(ctx._h, mat._h, int(centres.shape[0]), _np_ptr(centres),
-                                               _np_ptr(radii), _np_ptr(mask), ctypes.byref(h))
+                                               _np_ptr(radii), _np_ptr(mask), int(tile_width), ctypes.byref(h))
         else:
             st = lib().elses_regions_create(ctx._h, mat._h, int(centres.shape[0]), _np_ptr(centres),
                                             _np_ptr(radii), int(tile_width), ctypes.byref(h))
@@ -427,9 +429,21 @@ class Regions:
             pass
 
 
+def set_preconditioner(ctx: Context, mat: Matrix, params=None, bf16: bool = True):
+    """Keep the learned M (network params: FP32 device tensor, or None to remove it) with the matrix."""
+    ctx.check(lib().elses_mat_set_preconditioner(ctx._h, mat._h, _dev_ptr(params), 1 if bf16 else 0))
+
+
+def solve_counts(ctx: Context) -> tuple[int, int]:
+    """(sparse products, preconditioner fallbacks) of the last compact region solve."""
+    p, f = ctypes.c_int64(), ctypes.c_int64()
+    ctx.check(lib().elses_ctx_solve_counts(ctx._h, ctypes.byref(p), ctypes.byref(f)))
+    return int(p.value), int(f.value)
+
+
 def region_solve(ctx: Context, reg: Regions, shifts, c=None, *, tol=1e-8, max_outer=20000, inner_tol=1e-13,
                  mixed=False, want_x=True, allow_not_converged=False, variant="auto", graph=False, full=False,
-                 audit=False, audit_every=0):
+                 audit=False, audit_every=0, precond=False, inner_max=200):
     """Solve every region's columns for every shift; density outputs when weights c are given.
 
     Compact region sets also take full=True (x holds, per column, the [K][m_r] vectors of its region in
@@ -453,6 +467,8 @@ def region_solve(ctx: Context, reg: Regions, shifts, c=None, *, tol=1e-8, max_ou
     traces = np.zeros(2)
     opts = make_opts(tol, max_outer, inner_tol, full, 0, mixed, audit, variant, graph)
     opts.audit_every = int(audit_every)
+    opts.precond = 1 if precond else 0
+    opts.inner_max = int(inner_max)
     st = lib().elses_regions_solve(ctx._h, reg._h, K, _np_ptr(z), None if cw is None else _np_ptr(cw),
                                    ctypes.byref(opts), _dev_ptr(x), _dev_ptr(rho),
                                    None if cw is None else _np_ptr(traces), _dev_ptr(col_tr), _dev_ptr(iters),
@@ -468,6 +484,21 @@ def region_solve(ctx: Context, reg: Regions, shifts, c=None, *, tol=1e-8, max_ou
 # Learned SPAI of the overlap
 # ---------------------------------------------------------------------------
 MLP_PARAMS = 40336
+MLP_SHAPES = [(128, 40), (128,), (128, 128), (128,), (128, 128), (128,), (16, 128), (16,)]
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """Seeded initial parameters of the network (FP64 host array in the library's parameter
+    order): weights uniform in +-sqrt(6 / (fan_in + fan_out)), biases zero."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for sh in MLP_SHAPES:
+        if len(sh) == 2:
+            lim = np.sqrt(6.0 / (sh[0] + sh[1]))
+            parts.append(rng.uniform(-lim, lim, size=sh).ravel())
+        else:
+            parts.append(np.zeros(sh))
+    return np.concatenate(parts)
 
 
 def spai_pairs(mat: Matrix) -> np.ndarray:

@@ -341,6 +341,7 @@ void elses_opts_default(elses_opts* o) {
     o->slots = 0;
     o->use_mixed = 0;
     o->audit = 0;
+    o->inner_max = 200;
 }
 
 elses_status elses_ctx_create(int device, void* hip_stream, elses_ctx* out) {
@@ -848,9 +849,10 @@ struct elses_regions_s {
         int *d_order = nullptr, *d_slice_len = nullptr, *d_slice_ent = nullptr, *d_col_pos = nullptr,
             *d_pat_pos = nullptr;
         uint16_t *d_idx = nullptr, *d_pos_row = nullptr;
-        double *d_A64 = nullptr, *d_B64 = nullptr, *d_pat_B = nullptr, *d_pat_A = nullptr;
-        float *d_A32 = nullptr, *d_B32 = nullptr;
+        double *d_A64 = nullptr, *d_B64 = nullptr, *d_pat_B = nullptr, *d_pat_A = nullptr, *d_M64 = nullptr;
+        float *d_A32 = nullptr, *d_B32 = nullptr, *d_M32 = nullptr;
         int64_t* d_pat_off = nullptr;
+        bool hasM = false;  // the learned preconditioner was carved with the regions
     } cp;
     std::vector<int> cols;         // global orbital of each column, region by region
     std::vector<int> col_row;      // row of each column's unit vector in bm
@@ -875,8 +877,9 @@ struct elses_regions_s {
         void* p[] = {d_mask, d_col_row, d_rows, d_vidx, d_pat_off, d_slot_map, d_row_tile};
         for (void* q : p)
             if (q) (void)hipFree(q);
-        void* c[] = {cp.d_reg, cp.d_order, cp.d_slice_len, cp.d_slice_ent, cp.d_col_pos, cp.d_pat_pos, cp.d_idx,
-                     cp.d_pos_row, cp.d_A64, cp.d_B64, cp.d_pat_B, cp.d_pat_A, cp.d_A32, cp.d_B32, cp.d_pat_off};
+        void* c[] = {cp.d_reg,   cp.d_order, cp.d_slice_len, cp.d_slice_ent, cp.d_col_pos, cp.d_pat_pos,
+                     cp.d_idx,   cp.d_pos_row, cp.d_A64,     cp.d_B64,       cp.d_pat_B,   cp.d_pat_A,
+                     cp.d_A32,   cp.d_B32,   cp.d_pat_off,   cp.d_M64,       cp.d_M32};
         for (void* q : c)
             if (q) (void)hipFree(q);
         if (bm) elses_mat_destroy(bm);
@@ -962,6 +965,11 @@ elses_status compact_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, con
             C.d_A32 = upload(H.A32);
             C.d_B32 = upload(H.B32);
         }
+        if (!H.M64.empty()) {
+            C.hasM = true;
+            C.d_M64 = upload(H.M64);
+            if (C.has32) C.d_M32 = upload(H.M32);
+        }
     } catch (const HipFail& f) {
         delete P;
         const elses_status s = (f.e == hipErrorOutOfMemory) ? ELSES_ERR_OOM : ELSES_ERR_HIP;
@@ -989,14 +997,21 @@ elses_status regions_check(elses_ctx ctx, elses_mat gm, int n_regions, const int
 }
 
 elses_status regions_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, const int32_t* centres,
-                                 const double* radii, int tile_width, elses_regions* out) {
+                                 const double* radii, const uint8_t* orb_mask, int tile_width, elses_regions* out) {
     const HostMatrix& h = gm->h;
     const int N = h.n_atoms;
     {
         const elses_status st = regions_check(ctx, gm, n_regions, centres, radii);
         if (st != ELSES_OK) return st;
     }
-    if (tile_width == 0) return compact_create_impl(ctx, gm, n_regions, centres, radii, nullptr, out);
+    if (tile_width == 0) return compact_create_impl(ctx, gm, n_regions, centres, radii, orb_mask, out);
+    // orbitals of each centre solved as columns
+    std::vector<int> cmask(n_regions);
+    for (int r = 0; r < n_regions; ++r) {
+        const int all = (1 << h.n_orb[centres[r]]) - 1;
+        cmask[r] = (orb_mask && orb_mask[r]) ? (orb_mask[r] & all) : all;
+        if (cmask[r] == 0) return set_err(ctx, ELSES_ERR_INVALID_ARG, "a region has no columns (orbital mask selects nothing)");
+    }
     const int L = tile_width;
     if (L != 64 && L != 128) return set_err(ctx, ELSES_ERR_INVALID_ARG, "tile_width must be 0, 64 or 128");
     auto* P = new elses_regions_s();
@@ -1032,7 +1047,7 @@ elses_status regions_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, con
     {
         int used = 0;
         for (int r = 0; r < n_regions; ++r) {
-            const int nc = h.n_orb[centres[r]];
+            const int nc = __builtin_popcount(cmask[r]);
             if (used + nc > L) {
                 tile_r0.push_back(r);
                 used = 0;
@@ -1124,7 +1139,9 @@ elses_status regions_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, con
             for (int I : reg[r]) inreg[loc[I] - tile_atom0[t]] = 1;
             const int c_first = (int)P->cols.size();
             for (int q = 0; q < h.n_orb[C]; ++q) {
+                if (!((cmask[r] >> q) & 1)) continue;
                 const int cidx = (int)P->cols.size();
+                P->cp.col_region.push_back(r);
                 P->cols.push_back(h.atom_off[C] + q);
                 P->col_row.push_back(brow_off[loc[C]] + q);
                 P->slot_map[(size_t)t * L + slot] = cidx;
@@ -1778,6 +1795,11 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
     if (o.audit && (!full || !resid_out))
         return set_err(ctx, ELSES_ERR_INVALID_ARG, "audit needs ELSES_OUT_FULL and resid_out");
     if (o.audit_every < 0) return set_err(ctx, ELSES_ERR_INVALID_ARG, "audit_every must be >= 0");
+    const bool precond = o.precond != 0;
+    if (precond && !C.hasM)
+        return set_err(ctx, ELSES_ERR_INVALID_ARG,
+                       "precond needs a region set created after elses_mat_set_preconditioner");
+    if (precond && o.inner_max < 1) return set_err(ctx, ELSES_ERR_INVALID_ARG, "inner_max must be >= 1");
     if (o.audit_every > 0 && (full || !resid_out))
         return set_err(ctx, ELSES_ERR_INVALID_ARG, "audit_every needs the pattern mode and resid_out");
     if (traces_out) traces_out[0] = traces_out[1] = 0.0;
@@ -1790,7 +1812,7 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         const int cnt = C.goff[g + 1] - C.goff[g];
         if (cnt == 0) continue;
         glds[g] = (size_t)C.gmaxP[g] * C.gcw[g] * (mixed ? 4 : 8);
-        const int occ = compact_occupancy(!mixed, C.gcw[g], glds[g]);
+        const int occ = compact_occupancy(!mixed, C.gcw[g], precond, glds[g]);
         if (occ < 1)
             return set_err(ctx, ELSES_ERR_INVALID_ARG,
                            "the largest region's overlap iterate does not fit in LDS; use tile_width 64 or 128");
@@ -1806,9 +1828,11 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         carry_off[c + 1] = carry_off[c] + len * K;
         full_off[c + 1] = full_off[c] + D.m;
     }
-    // per-workgroup scratch of each group: seven [P][cw] FP64 blocks
+    // per-workgroup scratch of each group: seven [P][cw] FP64 blocks (twelve with the
+    // preconditioned solve's own vectors)
+    const size_t nblk = precond ? 12 : 7;
     size_t gvec[3] = {0, 0, 0};
-    for (int g = 0; g < 3; ++g) gvec[g] = (size_t)7 * C.gmaxP[g] * C.gcw[g] * gwg[g];
+    for (int g = 0; g < 3; ++g) gvec[g] = nblk * C.gmaxP[g] * C.gcw[g] * gwg[g];
     int n_notconv = 0;
     try {
         HCHECK(hipSetDevice(ctx->device));
@@ -1825,6 +1849,10 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         a.B64 = C.d_B64;
         a.A32 = C.d_A32;
         a.B32 = C.d_B32;
+        a.M64 = C.d_M64;
+        a.M32 = C.d_M32;
+        a.inner_tol = o.inner_tol;
+        a.inner_max = o.inner_max;
         a.pos_row = C.d_pos_row;
         a.col_pos = C.d_col_pos;
         a.pat_off = C.d_pat_off;
@@ -1872,9 +1900,11 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         HCHECK(hipMemsetAsync(a.conv, 0, sizeof(int) * n_cols * K, st));
         a.xs = pool.get<double>((size_t)carry_off[n_cols] * 2);
         a.ps = pool.get<double>((size_t)carry_off[n_cols] * 2);
-        int* counters = pool.get<int>(4);  // three queues, then the not-converged count
-        HCHECK(hipMemsetAsync(counters, 0, sizeof(int) * 4, st));
+        int* counters = pool.get<int>(8);  // three queues, not-converged, fallbacks, pad, product count
+        HCHECK(hipMemsetAsync(counters, 0, sizeof(int) * 8, st));
         a.n_notconv = counters + 3;
+        a.n_fallback = counters + 4;
+        a.products = reinterpret_cast<unsigned long long*>(counters + 6);
         a.x_out = x_out;
         int32_t* iters = iters_out ? iters_out : pool.get<int32_t>(n_cols);
         a.iters_out = iters;
@@ -1916,13 +1946,13 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
             a.n_regions = cnt;
             a.queue = counters + g;
             a.vec = vec_g[g];
-            a.vec_stride = (size_t)7 * C.gmaxP[g] * C.gcw[g];
+            a.vec_stride = nblk * C.gmaxP[g] * C.gcw[g];
             if (timed) {
                 HCHECK(hipEventCreate(&ev[g][0]));
                 HCHECK(hipEventCreate(&ev[g][1]));
                 HCHECK(hipEventRecord(ev[g][0], gst[g]));
             }
-            launch_compact(a, !mixed, C.gcw[g], gwg[g], glds[g], gst[g]);
+            launch_compact(a, !mixed, C.gcw[g], precond, gwg[g], glds[g], gst[g]);
             HCHECK(hipGetLastError());
             if (timed) HCHECK(hipEventRecord(ev[g][1], gst[g]));
             if (g > 0) {
@@ -1937,10 +1967,14 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
             launch_sum_pairs(ctr, n_cols, tr2, st);
             HCHECK(hipMemcpyAsync(traces_out, tr2, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
         }
-        int h_cnt[4] = {0, 0, 0, 0};
-        HCHECK(hipMemcpyAsync(h_cnt, counters, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+        int h_cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        HCHECK(hipMemcpyAsync(h_cnt, counters, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
         HCHECK(hipStreamSynchronize(st));
         n_notconv = h_cnt[3];
+        unsigned long long prods = 0;
+        memcpy(&prods, h_cnt + 6, sizeof(prods));
+        ctx->last_products = (int64_t)prods;
+        ctx->last_fallbacks = h_cnt[4];
         // algorithmic bytes of the launch: per outer step of a region, its
         // sparse products (index + value per nonzero), the carried x and p
         // (read and written), and the Lanczos vectors in scratch
@@ -1967,24 +2001,34 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
             outer += n_it;
         }
         if (timed) {
-            // the statistics describe the group launch that took longest
-            int gbest = -1;
-            float best = -1.f;
+            // The group launches overlap on their streams: one solve counts as one
+            // launch spanning the first launch's start to the last one's end, with
+            // the algorithmic bytes of all groups; slots = the width of the group
+            // that moved most bytes.
+            int gfirst = -1, glast = -1, gmost = -1;
+            float span = 0.f;
+            for (int g = 0; g < 3; ++g) {
+                if (!ev[g][0]) continue;
+                if (gfirst < 0) gfirst = g;
+                if (gmost < 0 || gbytes[g] > gbytes[gmost]) gmost = g;
+            }
             for (int g = 0; g < 3; ++g) {
                 if (!ev[g][0]) continue;
                 float ms = 0.f;
-                HCHECK(hipEventElapsedTime(&ms, ev[g][0], ev[g][1]));
-                if (ms > best) {
-                    best = ms;
-                    gbest = g;
+                HCHECK(hipEventElapsedTime(&ms, ev[gfirst][0], ev[g][1]));
+                if (ms > span) {
+                    span = ms;
+                    glast = g;
                 }
             }
-            if (gbest >= 0) {
-                ctx->prof_ms += best;
+            if (gfirst >= 0 && glast >= 0) {
+                ctx->prof_ms += span;
                 ctx->prof_launches += 1;
-                ctx->prof_bytes = gbytes[gbest];
-                ctx->prof_flops = gflops[gbest];
-                ctx->prof_slots = C.gcw[gbest];
+                ctx->prof_bytes_acc += gbytes[0] + gbytes[1] + gbytes[2];
+                ctx->prof_flops_acc += gflops[0] + gflops[1] + gflops[2];
+                ctx->prof_bytes = ctx->prof_bytes_acc / (double)ctx->prof_launches;
+                ctx->prof_flops = ctx->prof_flops_acc / (double)ctx->prof_launches;
+                ctx->prof_slots = C.gcw[gmost];
             }
             for (auto& e : ev)
                 for (hipEvent_t x : e)
@@ -2026,6 +2070,8 @@ elses_status elses_ctx_set_profiling(elses_ctx ctx, int32_t stride) {
     ctx->prof_stride = stride;
     ctx->prof_launches = 0;
     ctx->prof_ms = 0.0;
+    ctx->prof_bytes_acc = 0.0;
+    ctx->prof_flops_acc = 0.0;
     ctx->total_passes = 0;
     return ELSES_OK;
 }
@@ -2130,11 +2176,12 @@ elses_status elses_regions_create(elses_ctx ctx, elses_mat mat, int32_t n_region
     } catch (const HipFail& f) {
         return set_err(ctx, ELSES_ERR_HIP, std::string(f.what) + ": " + hipGetErrorString(f.e));
     }
-    return regions_create_impl(ctx, mat, n_regions, centres, radii, tile_width, out);
+    return regions_create_impl(ctx, mat, n_regions, centres, radii, nullptr, tile_width, out);
 }
 
 elses_status elses_regions_create_ex(elses_ctx ctx, elses_mat mat, int32_t n_regions, const int32_t* centres,
-                                     const double* radii, const uint8_t* orb_mask, elses_regions* out) {
+                                     const double* radii, const uint8_t* orb_mask, int32_t tile_width,
+                                     elses_regions* out) {
     if (!ctx || !mat || !out) return ELSES_ERR_INVALID_ARG;
     *out = nullptr;
     try {
@@ -2142,9 +2189,7 @@ elses_status elses_regions_create_ex(elses_ctx ctx, elses_mat mat, int32_t n_reg
     } catch (const HipFail& f) {
         return set_err(ctx, ELSES_ERR_HIP, std::string(f.what) + ": " + hipGetErrorString(f.e));
     }
-    const elses_status st = regions_check(ctx, mat, n_regions, centres, radii);
-    if (st != ELSES_OK) return st;
-    return compact_create_impl(ctx, mat, n_regions, centres, radii, orb_mask, out);
+    return regions_create_impl(ctx, mat, n_regions, centres, radii, orb_mask, tile_width, out);
 }
 
 void elses_regions_destroy(elses_regions reg) { delete reg; }
@@ -2164,15 +2209,7 @@ elses_status elses_regions_info(elses_regions reg, int32_t* n_cols, int32_t* n_t
 
 elses_status elses_regions_columns(elses_regions reg, int32_t* col_region) {
     if (!reg || !col_region) return ELSES_ERR_INVALID_ARG;
-    if (reg->compact) {
-        std::copy(reg->cp.col_region.begin(), reg->cp.col_region.end(), col_region);
-    } else {
-        int c = 0;
-        for (int r = 0; r < reg->n_regions; ++r) {
-            const int nI = reg->gm->h.n_orb[reg->centres[r]];
-            for (int q = 0; q < nI; ++q) col_region[c++] = r;
-        }
-    }
+    std::copy(reg->cp.col_region.begin(), reg->cp.col_region.end(), col_region);
     return ELSES_OK;
 }
 
@@ -2603,6 +2640,49 @@ elses_status elses_spai_apply(elses_ctx ctx, elses_mat mat, const float* params,
     } catch (const HipFail& f) {
         return hip_err(ctx, f);
     }
+    return ELSES_OK;
+}
+
+elses_status elses_mat_set_preconditioner(elses_ctx ctx, elses_mat mat, const float* params, int32_t bf16) {
+    if (!ctx || !mat) return ELSES_ERR_INVALID_ARG;
+    HostMatrix& h = mat->h;
+    if (!params) {
+        h.M_in.clear();
+        return ELSES_OK;
+    }
+    if (h.n_orb.empty()) return set_err(ctx, ELSES_ERR_INVALID_ARG, "the preconditioner needs a caller-created matrix");
+    const int64_t nnz = mat->d.nnz;
+    const int nnzb = (int)h.bcol.size();
+    std::vector<double> Mi(nnz);
+    std::vector<int64_t> asc_voff(nnzb);
+    try {
+        HCHECK(hipSetDevice(ctx->device));
+        DevPool pool;
+        double* Mv = pool.get<double>(nnz);
+        const elses_status st = elses_spai_apply(ctx, mat, params, bf16, Mv);
+        if (st != ELSES_OK) return st;
+        HCHECK(hipMemcpy(Mi.data(), Mv, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+        HCHECK(hipMemcpy(asc_voff.data(), mat->d.asc_voff, sizeof(int64_t) * nnzb, hipMemcpyDeviceToHost));
+    } catch (const HipFail& f) {
+        return hip_err(ctx, f);
+    }
+    std::vector<double> Min(nnz);
+    for (int b = 0; b < nnzb; ++b) {
+        const int64_t len = h.in_voff[b + 1] - h.in_voff[b];
+        for (int64_t e = 0; e < len; ++e) {
+            const double v = Mi[asc_voff[b] + e];
+            if (!std::isfinite(v)) return set_err(ctx, ELSES_ERR_INVALID_ARG, "the network produced a non-finite M");
+            Min[h.in_voff[b] + e] = v;
+        }
+    }
+    h.M_in.swap(Min);
+    return ELSES_OK;
+}
+
+elses_status elses_ctx_solve_counts(elses_ctx ctx, int64_t* products, int64_t* fallbacks) {
+    if (!ctx) return ELSES_ERR_INVALID_ARG;
+    if (products) *products = ctx->last_products;
+    if (fallbacks) *fallbacks = ctx->last_fallbacks;
     return ELSES_OK;
 }
 

@@ -84,6 +84,7 @@ struct HostMatrix {
     std::vector<int8_t> n_orb;
     std::vector<int64_t> in_voff;     // value offset of each block (ascending order), nnzb + 1
     std::vector<double> A_in, B_in;
+    std::vector<double> M_in;         // learned preconditioner on B's pattern (caller layout), or empty
     std::vector<int> grp_row0;        // first row of each row group
 };
 
@@ -100,8 +101,14 @@ struct elses_ctx_s {
     double prof_ms = 0.0;
     double prof_bytes = 0.0;
     double prof_flops = 0.0;
+    double prof_bytes_acc = 0.0;  // compact region launches: sums over the timed launches
+    double prof_flops_acc = 0.0;
     int64_t total_passes = 0;
     int prof_slots = 0;
+    // last compact region solve: sparse products launched (A, B, M; summed over
+    // regions) and regions whose preconditioned overlap solve fell back
+    int64_t last_products = 0;
+    int64_t last_fallbacks = 0;
 };
 
 struct elses_mat_s {
@@ -335,6 +342,8 @@ struct CompactArgs {
     const uint16_t* idx;     // entries: column position inside the region
     const double *A64, *B64; // entries: FP64 values
     const float *A32, *B32;  // entries: FP32 values (mixed precision)
+    const double* M64;       // entries: learned preconditioner M (precond launches), FP64
+    const float* M32;        //          and its FP32 copy (mixed precision)
     const uint16_t* pos_row; // region orbital of each position (>= m: padding)
     const int* col_pos;      // [n_cols] position of the column's unit vector
     const int64_t* pat_off;  // [n_cols+1] pattern offsets (caller's layout)
@@ -353,6 +362,10 @@ struct CompactArgs {
     int d;                        // Richardson degree (per round)
     const double* tau;            // [d-1] inverse Chebyshev roots (Leja order)
     double g0;
+    double inner_tol;             // overlap solve tolerance (preconditioned CG: per round)
+    int inner_max;                // preconditioned CG steps per round before the fallback
+    unsigned long long* products; // sparse products launched (A, B and M), summed over regions
+    int* n_fallback;              // regions whose preconditioned overlap solve fell back
     double* vec;                  // per workgroup: six [Pmax][Cmax] FP64 blocks
     size_t vec_stride;
     double *eta, *zeta, *res, *fac;  // [n_cols][K] (x2, x2, x1, x4)
@@ -366,18 +379,18 @@ struct CompactArgs {
     double* rho_out;
     double* ctr_out;
 };
-// resident workgroups per CU of the kernel for (precision, column width, LDS bytes)
-int compact_occupancy(bool fp64, int cw, size_t lds);
+// resident workgroups per CU of the kernel for (precision, column width, preconditioned, LDS bytes)
+int compact_occupancy(bool fp64, int cw, bool precond, size_t lds);
 // one persistent launch over the regions a.order[0 .. a.n_regions) (all of column width cw)
-void launch_compact(const CompactArgs& a, bool fp64, int cw, int n_wg, size_t lds, hipStream_t st);
+void launch_compact(const CompactArgs& a, bool fp64, int cw, bool precond, int n_wg, size_t lds, hipStream_t st);
 
 // Host-side construction of the compact layout (region_host.hip).
 struct CompactHost {
     std::vector<RegionDesc> reg;
     std::vector<int> slice_len, slice_ent;
     std::vector<uint16_t> idx, pos_row;
-    std::vector<double> A64, B64;
-    std::vector<float> A32, B32;
+    std::vector<double> A64, B64, M64;
+    std::vector<float> A32, B32, M32;
     std::vector<int> cols;      // global orbital of each column, region by region
     std::vector<int> col_pos;   // position of each column's unit vector in its region
     std::vector<int> col_region;
@@ -392,8 +405,9 @@ struct CompactHost {
 };
 // Carve the regions (atoms within radii[r] of centres[r], minimum image) and
 // build their compact layout.  orb_mask (may be null) selects the centre's
-// orbitals solved as columns (bit q: orbital q; 0 or null: all).  Returns an
-// error message or null.
+// orbitals solved as columns (bit q: orbital q; 0 or null: all).  The
+// learned preconditioner's values (h.M_in, when set) are carved alongside A
+// and B.  Returns an error message or null.
 const char* build_compact(const HostMatrix& h, int n_regions, const int* centres, const double* radii,
                           const uint8_t* orb_mask, bool want32, CompactHost& out);
 

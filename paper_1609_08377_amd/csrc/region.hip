@@ -139,6 +139,15 @@ struct RView {
     const TV* Bv;             // entries: values of B
     const double* A64;        // entries: FP64 values (refinement and audits)
     const double* B64;
+    const TV* Mv;             // entries: values of the learned preconditioner M (or null)
+};
+
+// Per-column scalars of the region being solved, in LDS (uniform values kept
+// out of the register file).
+struct ColState {
+    double alpha[4], bprev[4], beta[4], snorm[4], invb[4];
+    int alive[4], nend[4], jpos[4], col[4], notconv[4];
+    int fallback;  // the region's preconditioned overlap solve failed once: plain iteration from then on
 };
 
 template <typename TV>
@@ -190,16 +199,216 @@ __device__ __forceinline__ void richardson(const CompactArgs& a, const RView<TV>
     }
 }
 
+// Preconditioned conjugate gradients with the learned M for B x = rhs, per
+// column (TV vectors, FP64 dot products), the overlap solve of the
+// preconditioned path: x_0 = 0, r = rhs, z = M r, p = z; q = B p,
+// a = (r.z)/(p.q), x += a p, r -= a q until ||r|| <= tol ||rhs||; then
+// z = M r, b = (r.z)_new/(r.z)_old, p = z + b p.  The vector being gathered
+// (p for B, r for M) is staged in X (LDS); the lane's own x, r, p, q, z live
+// in per-workgroup scratch.  Returns 1 when a curvature p.Bp or r.Mr was not
+// positive (M not positive definite on the Krylov space) or the steps ran
+// out: the caller then takes the plain iteration (CG's judge and fallback);
+// otherwise x is left in X.
+template <int C, typename TV>
+__device__ __forceinline__ int pcg_round(const CompactArgs& a, const RView<TV>& R, const TV* rhs, TV* X, TV* Xo,
+                                         TV* Ro, TV* Po, TV* Qo, TV* Zo, double tol, double* red,
+                                         unsigned long long* products) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double rr0[C], rz[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) rr0[c] = 0.0;
+    for (int sl = w; sl < R.ns; sl += kRW) {
+        const int pos = sl * 64 + lane;
+        TV r[C], zero[C];
+        ldv<C>(rhs + (size_t)pos * C, r);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            zero[c] = TV(0);
+            rr0[c] = fma((double)r[c], (double)r[c], rr0[c]);
+        }
+        stv<C>(Ro + (size_t)pos * C, r);
+        stv<C>(Xo + (size_t)pos * C, zero);
+        stv<C>(X + (size_t)pos * C, r);
+    }
+    wg_sum<C>(rr0, red);
+#pragma unroll
+    for (int c = 0; c < C; ++c) rz[c] = 0.0;
+    for (int sl = w; sl < R.ns; sl += kRW) {
+        const int pos = sl * 64 + lane;
+        TV z[C], r[C];
+        row_product<C>(R.idx, R.Mv, (uint32_t)(R.sent[sl] + lane), R.slen[sl], X, z);
+        ldv<C>(Ro + (size_t)pos * C, r);
+#pragma unroll
+        for (int c = 0; c < C; ++c) rz[c] = fma((double)r[c], (double)z[c], rz[c]);
+        stv<C>(Po + (size_t)pos * C, z);
+    }
+    wg_sum<C>(rz, red);  // its barriers also end every gather of r
+    bool active[C];
+    int fail = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        active[c] = rr0[c] > 0.0;
+        if (active[c] && !(rz[c] > 0.0)) fail = 1;
+    }
+    unsigned long long nprod = 1;
+    if (!fail) {
+        for (int sl = w; sl < R.ns; sl += kRW) {
+            const int pos = sl * 64 + lane;
+            TV pv[C];
+            ldv<C>(Po + (size_t)pos * C, pv);
+            stv<C>(X + (size_t)pos * C, pv);
+        }
+        __syncthreads();
+        int k = 0;
+        for (; k < a.inner_max; ++k) {
+            double pq[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) pq[c] = 0.0;
+            for (int sl = w; sl < R.ns; sl += kRW) {
+                const int pos = sl * 64 + lane;
+                TV q[C], pv[C];
+                row_product<C>(R.idx, R.Bv, (uint32_t)(R.sent[sl] + lane), R.slen[sl], X, q);
+                ldv<C>(X + (size_t)pos * C, pv);
+#pragma unroll
+                for (int c = 0; c < C; ++c) pq[c] = fma((double)pv[c], (double)q[c], pq[c]);
+                stv<C>(Qo + (size_t)pos * C, q);
+            }
+            wg_sum<C>(pq, red);
+            TV al[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (active[c] && !(pq[c] > 0.0)) fail = 1;
+                al[c] = (active[c] && pq[c] > 0.0) ? static_cast<TV>(rz[c] / pq[c]) : TV(0);
+            }
+            ++nprod;
+            if (fail) break;
+            double rr[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) rr[c] = 0.0;
+            for (int sl = w; sl < R.ns; sl += kRW) {
+                const int pos = sl * 64 + lane;
+                TV x[C], pv[C], q[C], r[C];
+                ldv<C>(Xo + (size_t)pos * C, x);
+                ldv<C>(X + (size_t)pos * C, pv);
+                ldv<C>(Qo + (size_t)pos * C, q);
+                ldv<C>(Ro + (size_t)pos * C, r);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    x[c] += al[c] * pv[c];
+                    r[c] -= al[c] * q[c];
+                    rr[c] = fma((double)r[c], (double)r[c], rr[c]);
+                }
+                stv<C>(Xo + (size_t)pos * C, x);
+                stv<C>(Ro + (size_t)pos * C, r);
+            }
+            wg_sum<C>(rr, red);
+            bool all = true;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (active[c] && rr[c] <= tol * tol * rr0[c]) active[c] = false;
+                all = all && !active[c];
+            }
+            if (all) break;
+            // z = M r on r staged in X
+            for (int sl = w; sl < R.ns; sl += kRW) {
+                const int pos = sl * 64 + lane;
+                TV r[C];
+                ldv<C>(Ro + (size_t)pos * C, r);
+                stv<C>(X + (size_t)pos * C, r);
+            }
+            __syncthreads();
+            double rzn[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) rzn[c] = 0.0;
+            for (int sl = w; sl < R.ns; sl += kRW) {
+                const int pos = sl * 64 + lane;
+                TV z[C], r[C];
+                row_product<C>(R.idx, R.Mv, (uint32_t)(R.sent[sl] + lane), R.slen[sl], X, z);
+                ldv<C>(Ro + (size_t)pos * C, r);
+#pragma unroll
+                for (int c = 0; c < C; ++c) rzn[c] = fma((double)r[c], (double)z[c], rzn[c]);
+                stv<C>(Zo + (size_t)pos * C, z);
+            }
+            wg_sum<C>(rzn, red);
+            ++nprod;
+            TV be[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (active[c] && !(rzn[c] > 0.0)) fail = 1;
+                be[c] = (active[c] && rz[c] > 0.0) ? static_cast<TV>(rzn[c] / rz[c]) : TV(0);
+                if (active[c]) rz[c] = rzn[c];
+            }
+            if (fail) break;
+            // p = z + b p (frozen columns keep their p; their step length is 0)
+            for (int sl = w; sl < R.ns; sl += kRW) {
+                const int pos = sl * 64 + lane;
+                TV z[C], pv[C];
+                ldv<C>(Zo + (size_t)pos * C, z);
+                ldv<C>(Po + (size_t)pos * C, pv);
+#pragma unroll
+                for (int c = 0; c < C; ++c) pv[c] = active[c] ? z[c] + be[c] * pv[c] : pv[c];
+                stv<C>(Po + (size_t)pos * C, pv);
+                stv<C>(X + (size_t)pos * C, pv);
+            }
+            __syncthreads();
+        }
+        if (k >= a.inner_max) fail = 1;
+    }
+    if (threadIdx.x == 0) atomicAdd(products, nprod);
+    if (fail) {
+        __syncthreads();
+        return 1;
+    }
+    __syncthreads();  // every gather of X done
+    for (int sl = w; sl < R.ns; sl += kRW) {
+        const int pos = sl * 64 + lane;
+        TV x[C];
+        ldv<C>(Xo + (size_t)pos * C, x);
+        stv<C>(X + (size_t)pos * C, x);
+    }
+    __syncthreads();
+    return 0;
+}
+
+// Scratch blocks of the preconditioned overlap solve ([P][C] of TV each)
+template <typename TV>
+struct PcgScratch {
+    TV *x, *r, *p, *q, *z;
+};
+
+// One round of the overlap solve: X <- (approximately) B^{-1} rhs to tol.
+// Plain: the fixed Chebyshev-Richardson polynomial (degree for the round's
+// tolerance).  Preconditioned (PC): CG with the learned M, falling back to the
+// plain polynomial for the rest of the region once M fails.
+template <int C, typename TV, int PC>
+__device__ __forceinline__ void overlap_round(const CompactArgs& a, const RView<TV>& R, const TV* rhs, TV* X, TV* Xn,
+                                              const PcgScratch<TV>& ps, double tol, double* red, ColState& cs) {
+    if constexpr (PC) {
+        if (!cs.fallback) {
+            const int f = pcg_round<C, TV>(a, R, rhs, X, ps.x, ps.r, ps.p, ps.q, ps.z, tol, red, a.products);
+            if (!f) return;
+            if (threadIdx.x == 0) {
+                cs.fallback = 1;
+                atomicAdd(a.n_fallback, 1);
+            }
+            __syncthreads();
+        }
+    }
+    richardson<C, TV>(a, R, rhs, X, Xn);
+    if (threadIdx.x == 0) atomicAdd(a.products, (unsigned long long)(a.d - 1));
+}
+
 // v = p(B) s for the region's columns: S, V [P][C] FP64 (global); Rw scratch
 // [P][C] of TV (global); X the LDS iterate.  FP64: one round to inner_tol.
 // Mixed: two FP32 rounds (to sqrt(inner_tol)) with the FP64-accumulated
 // residual s - B x between them (iterative refinement).
-template <int C, typename TV>
+template <int C, typename TV, int PC>
 __device__ __forceinline__ void overlap_solve(const CompactArgs& a, const RView<TV>& R, const double* S, double* V,
-                                              TV* Rw, TV* Xn, TV* X) {
+                                              TV* Rw, TV* Xn, TV* X, const PcgScratch<TV>& ps, double* red,
+                                              ColState& cs) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if constexpr (sizeof(TV) == 8) {
-        richardson<C, TV>(a, R, S, X, Xn);
+        overlap_round<C, TV, PC>(a, R, S, X, Xn, ps, a.inner_tol, red, cs);
         for (int sl = w; sl < R.ns; sl += kRW) {
             const int pos = sl * 64 + lane;
             double v[C];
@@ -207,6 +416,7 @@ __device__ __forceinline__ void overlap_solve(const CompactArgs& a, const RView<
             stv<C>(V + (size_t)pos * C, v);
         }
     } else {
+        const double rtol = sqrt(a.inner_tol);
         // round 1 on fl32(s)
         for (int sl = w; sl < R.ns; sl += kRW) {
             const int pos = sl * 64 + lane;
@@ -218,14 +428,13 @@ __device__ __forceinline__ void overlap_solve(const CompactArgs& a, const RView<
             stv<C>(Rw + (size_t)pos * C, f);
         }
         __syncthreads();  // X may still be read by the previous product
-        richardson<C, TV>(a, R, Rw, X, Xn);
+        overlap_round<C, TV, PC>(a, R, Rw, X, Xn, ps, rtol, red, cs);
         // refinement: r = s - B x with FP64 accumulation; V = x
         for (int sl = w; sl < R.ns; sl += kRW) {
             const int pos = sl * 64 + lane;
             double acc[C], s[C], xd[C];
             float xo[C], f[C];
-            const int e0 = R.sent[sl] + lane;
-            row_product<C>(R.idx, R.Bv, (uint32_t)e0, R.slen[sl], X, acc);
+            row_product<C>(R.idx, R.Bv, (uint32_t)(R.sent[sl] + lane), R.slen[sl], X, acc);
             ldv<C>(S + (size_t)pos * C, s);
             ldv<C>(X + (size_t)pos * C, xo);
 #pragma unroll
@@ -236,8 +445,9 @@ __device__ __forceinline__ void overlap_solve(const CompactArgs& a, const RView<
             stv<C>(V + (size_t)pos * C, xd);
             stv<C>(Rw + (size_t)pos * C, f);
         }
+        if (threadIdx.x == 0) atomicAdd(a.products, 1ull);
         __syncthreads();  // every gather of round 1's x done before round 2 overwrites it
-        richardson<C, TV>(a, R, Rw, X, Xn);
+        overlap_round<C, TV, PC>(a, R, Rw, X, Xn, ps, rtol, red, cs);
         for (int sl = w; sl < R.ns; sl += kRW) {
             const int pos = sl * 64 + lane;
             double v[C];
@@ -287,14 +497,8 @@ __device__ __forceinline__ void audit_column(const CompactArgs& a, const RView<T
     (void)c;
 }
 
-// Per-column scalars of the region being solved, in LDS (uniform values kept
-// out of the register file).
-struct ColState {
-    double alpha[4], bprev[4], beta[4], snorm[4], invb[4];
-    int alive[4], nend[4], jpos[4], col[4], notconv[4];
-};
 
-template <int C, typename TV>
+template <int C, typename TV, int PC>
 __device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionDesc& D, double* vbase, TV* X,
                                              double* red, ColState& cs) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -311,6 +515,7 @@ __device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionD
     R.B64 = a.B64 + D.ent0;
     R.Av = pick<TV>(a.A64, a.A32) + D.ent0;
     R.Bv = pick<TV>(a.B64, a.B32) + D.ent0;
+    R.Mv = PC ? pick<TV>(a.M64, a.M32) + D.ent0 : nullptr;
     const int P = R.P;
     const size_t vs = (size_t)P * C;
     double* Q = vbase;
@@ -320,7 +525,14 @@ __device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionD
     double* V = S + vs;
     TV* Rw = reinterpret_cast<TV*>(V + vs);
     TV* Xn = reinterpret_cast<TV*>(V + 2 * vs);
+    PcgScratch<TV> ps;
+    ps.x = reinterpret_cast<TV*>(V + 3 * vs);
+    ps.r = reinterpret_cast<TV*>(V + 4 * vs);
+    ps.p = reinterpret_cast<TV*>(V + 5 * vs);
+    ps.q = reinterpret_cast<TV*>(V + 6 * vs);
+    ps.z = reinterpret_cast<TV*>(V + 7 * vs);
 
+    if (tid == 0) cs.fallback = 0;
     if (tid < C) {
         const int cc = tid < D.ncol ? tid : 0;  // padded columns repeat the first one; no output
         cs.col[tid] = D.col0 + cc;
@@ -340,7 +552,7 @@ __device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionD
         stv<C>(T0 + (size_t)pos * C, zero);
     }
     __syncthreads();
-    overlap_solve<C, TV>(a, R, S, V, Rw, Xn, X);
+    overlap_solve<C, TV, PC>(a, R, S, V, Rw, Xn, X, ps, red, cs);
     __syncthreads();
     // beta_0^2 = e_j^T B^{-1} e_j = v_0[j]
     if (tid < C) {
@@ -384,6 +596,7 @@ __device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionD
             }
             wg_sum<C>(al, red);
             if (tid < C) cs.alpha[tid] = al[tid];
+            if (tid == 0) atomicAdd(a.products, 1ull);
         }
         __syncthreads();
         // s = w - alpha_n t_n - beta_{n-1} t_{n-1}
@@ -398,7 +611,7 @@ __device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionD
             stv<C>(S + (size_t)pos * C, s);
         }
         // v = p(B) s
-        overlap_solve<C, TV>(a, R, S, V, Rw, Xn, X);
+        overlap_solve<C, TV, PC>(a, R, S, V, Rw, Xn, X, ps, red, cs);
         // beta_n^2 = v . s and ||s||^2
         {
             double dots[2 * C];
@@ -621,7 +834,7 @@ __device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionD
     __syncthreads();
 }
 
-template <typename TV, int C>
+template <typename TV, int C, int PC>
 __global__ __launch_bounds__(kRegThreads, 2) void compact_kernel(CompactArgs a) {
     __shared__ double red[kRW * 8];
     __shared__ ColState cs;
@@ -636,32 +849,35 @@ __global__ __launch_bounds__(kRegThreads, 2) void compact_kernel(CompactArgs a) 
         __syncthreads();
         if (r >= a.n_regions) return;
         const RegionDesc D = a.reg[a.order[r]];
-        solve_region<C, TV>(a, D, vbase, X, red, cs);
+        solve_region<C, TV, PC>(a, D, vbase, X, red, cs);
     }
 }
 
-template <typename TV>
+template <typename TV, int PC>
 const void* pick_kernel(int cw) {
-    if (cw == 1) return reinterpret_cast<const void*>(&compact_kernel<TV, 1>);
-    if (cw == 2) return reinterpret_cast<const void*>(&compact_kernel<TV, 2>);
-    return reinterpret_cast<const void*>(&compact_kernel<TV, 4>);
+    if (cw == 1) return reinterpret_cast<const void*>(&compact_kernel<TV, 1, PC>);
+    if (cw == 2) return reinterpret_cast<const void*>(&compact_kernel<TV, 2, PC>);
+    return reinterpret_cast<const void*>(&compact_kernel<TV, 4, PC>);
 }
 
-const void* kernel_for(bool fp64, int cw) { return fp64 ? pick_kernel<double>(cw) : pick_kernel<float>(cw); }
+const void* kernel_for(bool fp64, int cw, bool pc) {
+    if (pc) return fp64 ? pick_kernel<double, 1>(cw) : pick_kernel<float, 1>(cw);
+    return fp64 ? pick_kernel<double, 0>(cw) : pick_kernel<float, 0>(cw);
+}
 
 }  // namespace
 
-int compact_occupancy(bool fp64, int cw, size_t lds) {
-    const void* k = kernel_for(fp64, cw);
+int compact_occupancy(bool fp64, int cw, bool precond, size_t lds) {
+    const void* k = kernel_for(fp64, cw, precond);
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kRegThreads, lds) != hipSuccess) return 0;
     return nb;
 }
 
-void launch_compact(const CompactArgs& a, bool fp64, int cw, int n_wg, size_t lds, hipStream_t st) {
+void launch_compact(const CompactArgs& a, bool fp64, int cw, bool precond, int n_wg, size_t lds, hipStream_t st) {
     void* args[] = {const_cast<CompactArgs*>(&a)};
-    (void)hipLaunchKernel(kernel_for(fp64, cw), dim3(n_wg), dim3(kRegThreads), args, lds, st);
+    (void)hipLaunchKernel(kernel_for(fp64, cw, precond), dim3(n_wg), dim3(kRegThreads), args, lds, st);
 }
 
 }  // namespace elses

@@ -196,11 +196,14 @@ const char* build_compact(const HostMatrix& h, int n_regions, const int* centres
     out.slice_len.assign(slice, 0);
     out.slice_ent.assign(slice, 0);
     out.idx.assign(ent, 0);
+    const bool haveM = !h.M_in.empty();
     out.A64.assign(ent, 0.0);
     out.B64.assign(ent, 0.0);
+    if (haveM) out.M64.assign(ent, 0.0);
     if (want32) {
         out.A32.assign(ent, 0.0f);
         out.B32.assign(ent, 0.0f);
+        if (haveM) out.M32.assign(ent, 0.0f);
     }
     out.pos_row.assign(pos, 0xFFFF);
     out.cols.assign(col, 0);
@@ -266,9 +269,11 @@ const char* build_compact(const HostMatrix& h, int n_regions, const int* centres
                             out.idx[e] = (uint16_t)row_pos[aoff[lj] + be];
                             out.A64[e] = h.A_in[vo + be];
                             out.B64[e] = h.B_in[vo + be];
+                            if (haveM) out.M64[e] = h.M_in[vo + be];
                             if (want32) {
                                 out.A32[e] = (float)h.A_in[vo + be];
                                 out.B32[e] = (float)h.B_in[vo + be];
+                                if (haveM) out.M32[e] = (float)h.M_in[vo + be];
                             }
                         }
                     }

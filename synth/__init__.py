@@ -331,6 +331,23 @@ def sample_regions(sysm: System, n_regions: int, seed: int, r_lo: float = 6.0,
     return centres, radii
 
 
+def column_regions(sysm: System, cols: np.ndarray, seed: int, r_lo: float = 6.0,
+                   r_hi: float = 14.0) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Regions of sampled columns: one region per atom that carries a sampled
+    column, centred on that atom (ascending), with the sampled orbitals of the
+    atom as its columns (bit q of the mask = orbital q) and a radius U[r_lo, r_hi]
+    A drawn per region from the region stream (seed + 3)."""
+    cols = np.asarray(cols, dtype=np.int64)
+    atom = np.searchsorted(sysm.orb_off, cols, side="right") - 1
+    centres = np.unique(atom)
+    mask = np.zeros(centres.size, dtype=np.uint8)
+    where = np.searchsorted(centres, atom)
+    np.bitwise_or.at(mask, where, (1 << (cols - sysm.orb_off[atom])).astype(np.uint8))
+    rng = np.random.Generator(np.random.PCG64(seed + 3))
+    radii = rng.uniform(r_lo, r_hi, size=centres.size)
+    return centres.astype(np.int32), mask, radii
+
+
 def kappa_radii(sysm: System, centres: np.ndarray, kappa: int) -> np.ndarray:
     """Radius of each centre's sphere that holds its kappa nearest atoms (the
     centre included; minimum-image distances): the midpoint between the

@@ -229,8 +229,6 @@ def test_compact_invalid_arguments(el, ctx, box):
         el.region_solve(ctx, reg, z, full=True, audit_every=2)
     with pytest.raises(el.ElsesError):
         el.region_solve(ctx, reg, z, oracle.fermi_weights(z, 0.0, 0.05), full=True)
-    with pytest.raises(ValueError):
-        el.Regions(ctx, mat, [3], [5.0], orb_mask=[1], tile_width=64)
     carbon = int(np.nonzero(s.n_orb == 4)[0][0])
     hydrogen = int(np.nonzero(s.n_orb == 1)[0][0])
     with pytest.raises(el.ElsesError):

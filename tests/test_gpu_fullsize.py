@@ -43,6 +43,19 @@ def pattern_rows(s, j):
     return np.concatenate([np.arange(s.orb_off[I], s.orb_off[I] + s.n_orb[I]) for I in nb])
 
 
+def pattern_values(s, j, which):
+    """X_{j,i} for i in the pattern of column j, from the atom blocks."""
+    vals = s.A_val if which == "A" else s.B_val
+    J = int(np.searchsorted(s.orb_off, j, side="right") - 1)
+    a = int(j - s.orb_off[J])
+    nJ = int(s.n_orb[J])
+    out = []
+    for b in range(int(s.blk_row_ptr[J]), int(s.blk_row_ptr[J + 1])):
+        nI = int(s.n_orb[s.blk_col[b]])
+        out.append(vals[s.val_ptr[b]:s.val_ptr[b + 1]].reshape(nJ, nI)[a])
+    return np.concatenate(out)
+
+
 def rounded(s):
     return dataclasses.replace(s, A_val=s.A_val.astype(np.float32).astype(np.float64),
                                B_val=s.B_val.astype(np.float32).astype(np.float64))
@@ -205,11 +218,12 @@ def _row_products(s, rows, x, which):
 
 
 def test_c5_one_gpu_share(el, ctx):
-    """10^6-atom box (M = 2.0e6, FP32-stored matrices), in the launch configuration
-    of `bench.py --method pass --config c5` (256 right-hand sides, default
-    passes): sampled rows of the FP32 and FP64 products against exact products
-    from the atom blocks, and sampled columns solved as mixed-precision regions
-    against the oracle on the FP32-rounded carved sub-pencil."""
+    """10^6-atom box (M = 2.0e6, FP32-stored matrices): sampled rows of the FP32
+    and FP64 products against exact products from the atom blocks; then the
+    first step of `bench.py` (default c5): 640 sampled columns solved as
+    mixed-precision compact regions (radius U[6,14] A, 128 shifts), with x,
+    rho and the per-column traces of a seeded subsample (the largest and the
+    smallest region included) against the oracle on the carved pencils."""
     s = synth.make_system(1000000, synth.config_seed(5))
     mat = el.Matrix.from_system(ctx, s, precision="mixed")
     assert mat.M == s.M and s.M > 1_990_000
@@ -228,30 +242,73 @@ def test_c5_one_gpu_share(el, ctx):
     got = y64[torch.as_tensor(rows).cuda()].cpu().numpy()
     assert np.all(np.abs(got - ref) <= 1e-14 * mag + 1e-300)
     del x64, y64
-    # sampled columns as regions (radius rule of the region workload), mixed precision
-    cols = synth.sample_columns(s, 65536, synth.config_seed(5))[:16]
-    atom_of = np.repeat(np.arange(s.n_atoms), s.n_orb.astype(int))
-    centres = np.unique(atom_of[cols]).astype(np.int32)
-    radii = np.random.default_rng(synth.config_seed(5) + 3).uniform(6.0, 10.0, size=centres.size)
-    reg = el.Regions(ctx, mat, centres, radii, 64)
+    del mat
+    # the benchmark's first step: its region set (sampled columns, radius U[6,14] A, columns of one
+    # atom sharing its region) in the compact layout, 128 shifts, mixed precision, rho and traces
+    mat = el.Matrix.from_system(ctx, s, precision="mixed")
+    cols = synth.sample_columns(s, 65536, synth.config_seed(5))
+    centres, masks, radii = synth.column_regions(s, cols, synth.config_seed(5))
+    ncol = np.array([bin(int(m)).count("1") for m in masks])
+    nb = int(np.searchsorted(np.cumsum(ncol), 640, side="left")) + 1
+    centres, masks, radii = centres[:nb], masks[:nb], radii[:nb]
+    reg = el.Regions(ctx, mat, centres, radii, orb_mask=masks)
     z = synth.shift_grid(128)
+    K = len(z)
     cw = fermi_cw(z)
     out = el.region_solve(ctx, reg, z, cw, tol=1e-8, mixed=True)
     assert np.all(out["resid"].cpu().numpy() <= 1e-8)
-    r = int(np.argmin(reg.region_orbitals))
-    atoms = oracle.region_atoms(s, int(centres[r]), float(radii[r]))
-    Ar, Br, orb_map = oracle.carve_region(rounded(s), atoms)
-    loc = {int(g): l for l, g in enumerate(orb_map)}
-    col_region = np.repeat(np.arange(centres.size), [int(s.n_orb[c]) for c in centres])
-    c = int(np.nonzero(col_region == r)[0][0])
-    j = int(reg.cols[c])
-    ref = oracle.shifted_solve(Ar, Br, np.array([loc[j]], dtype=np.int32), z, tol=1e-10, full=True,
-                               true_residual=False)
-    rows_j = pattern_rows(s, j)
-    K = len(z)
-    blk = out["x"].cpu().numpy()[reg.pat_off[c] * K:reg.pat_off[c + 1] * K].reshape(K, -1)
-    for k in range(K):
-        rk = np.array([ref.x[0, k, loc[int(i)]] if int(i) in loc else 0.0 for i in rows_j])
-        assert np.abs(blk[k] - rk).max() <= 5e-7 * np.abs(rk).max()
-    print(f"\nC5: {reg.n_cols} sampled columns, regions of {reg.region_orbitals.min()}-{reg.region_orbitals.max()} "
-          f"orbitals, outer iterations max {int(out['iters'].max())}")
+    xg = out["x"].cpu().numpy()
+    rho = out["rho"].cpu().numpy()
+    ctr = out["col_traces"].cpu().numpy()
+    print(f"\nC5: {reg.n_cols} sampled columns in {nb} regions of {reg.region_orbitals.min()}-"
+          f"{reg.region_orbitals.max()} orbitals, outer iterations max {int(out['iters'].max())}", flush=True)
+    # seeded subsample: the largest region, the smallest, a multi-column region and two random ones;
+    # the oracle on the carved FP32-rounded pencil (what mixed precision solves) and, for the
+    # smaller ones, on the FP64 pencil
+    rng = np.random.default_rng(55)
+    big = int(np.argmax(reg.region_orbitals))
+    picks = [big, int(np.argmin(reg.region_orbitals))]
+    multi = np.nonzero(ncol[:nb] > 1)[0]
+    if multi.size:
+        picks.append(int(multi[0]))
+    picks += [int(r) for r in rng.choice(nb, size=2, replace=False)]
+    picks = list(dict.fromkeys(picks))
+    s32 = rounded(s)
+    jobs = []
+    for r in picks:
+        for c in np.nonzero(reg.col_region == r)[0]:
+            jobs.append((int(r), int(c), s32, 5e-7))
+            if r != big:
+                jobs.append((int(r), int(c), s, 1e-5))
+
+    def run(job):
+        r, c, sysm, bound = job
+        atoms = oracle.region_atoms(sysm, int(centres[r]), float(radii[r]))
+        Ar, Br, orb_map = oracle.carve_region(sysm, atoms)
+        loc = {int(g): l for l, g in enumerate(orb_map)}
+        j = int(reg.cols[c])
+        ref = oracle.shifted_solve(Ar, Br, np.array([loc[j]], dtype=np.int32), z, tol=1e-8 if r == big else 1e-9,
+                                   full=False, true_residual=False, nthreads=1)
+        # radius >= 6 A > the 4 A cutoff: the whole pattern of j lies inside the region, in the same order
+        rows_j = pattern_rows(s, j)
+        assert ref.pat_off[1] == rows_j.size
+        return job, ref.x.reshape(K, rows_j.size)
+
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        results = list(ex.map(run, jobs))
+    for (r, c, sysm, bound), xr in results:
+        j = int(reg.cols[c])
+        blk = xg[reg.pat_off[c] * K:reg.pat_off[c + 1] * K].reshape(K, -1)
+        assert np.abs(blk - xr).max() <= bound * np.abs(xr).max(), (r, c, bound)
+        # rho_ij = sum_k Im(c_k x_{j,k,i}) on the pattern (Eq. 12) and e_j^T rho X e_j (Eq. 7) from the
+        # oracle's x and the matrix values of row j
+        rho_r = np.imag(cw[:, None] * xr).sum(axis=0)
+        tb = float(rho_r @ pattern_values(s, j, "B"))
+        ta = float(rho_r @ pattern_values(s, j, "A"))
+        rg = rho[reg.pat_off[c]:reg.pat_off[c + 1]]
+        assert np.abs(rg - rho_r).max() <= 2 * bound * np.abs(rho_r).max(), (r, c)
+        assert abs(ctr[c, 0] - tb) <= 2 * bound * abs(tb) + 1e-14, (r, c)
+        assert abs(ctr[c, 1] - ta) <= 2 * bound * abs(ta) + 1e-14, (r, c)
+    print(f"C5 subsample against the oracle: regions of {sorted(int(reg.region_orbitals[r]) for r in picks)} "
+          f"orbitals", flush=True)

@@ -98,8 +98,9 @@ def test_inference_fp32_and_bf16(el, ctx, small):
     assert np.abs(out16 - ref).max() <= 5e-2 * np.abs(ref).max()
 
 
-def test_training_and_preconditioned_overlap_solve(el, ctx):
-    """Train on exact inverses of 500-atom boxes, apply to an unseen box."""
+@pytest.fixture(scope="module")
+def trained(el, ctx):
+    """The network trained on exact inverses of three 500-atom boxes."""
     feats, targs, masks = [], [], []
     for seed in (11, 12, 13):
         s = synth.make_system(500, seed)
@@ -113,6 +114,12 @@ def test_training_and_preconditioned_overlap_solve(el, ctx):
     loss0, _ = el.mlp_loss_grad(ctx, theta, X, T, W)
     hist = el.spai_train(ctx, theta, X, T, W, steps=1500, batch=4096, lr=2e-3, seed=1)
     loss1, _ = el.mlp_loss_grad(ctx, theta, X, T, W)
+    return theta, loss0, loss1, hist
+
+
+def test_training_and_preconditioned_overlap_solve(el, ctx, trained):
+    """Train on exact inverses of 500-atom boxes, apply to an unseen box."""
+    theta, loss0, loss1, hist = trained
     assert loss1 < 0.1 * loss0, (loss0, loss1)
     assert np.all(np.isfinite(hist))
     # unseen box
@@ -143,3 +150,79 @@ def test_training_and_preconditioned_overlap_solve(el, ctx):
     for x in (x0, x1):
         xx = x.cpu().numpy()
         assert np.abs(xx - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def _carved_ref(s, reg, centres, radii, c, z, tol=1e-11):
+    """Oracle x of region column c on the column's global pattern (zero outside the region)."""
+    r = int(reg.col_region[c])
+    atoms = oracle.region_atoms(s, int(centres[r]), float(radii[r]))
+    Ar, Br, omap = oracle.carve_region(s, atoms)
+    loc = {int(g): l for l, g in enumerate(omap)}
+    j = int(reg.cols[c])
+    ref = oracle.shifted_solve(Ar, Br, np.array([loc[j]], np.int32), z, tol=tol, full=True, true_residual=False)
+    B = oracle.to_csr(s, "B")
+    rows = B.ci[B.rp[j]:B.rp[j + 1]]
+    return np.array([[ref.x[0, k, loc[int(i)]] if int(i) in loc else 0.0 for i in rows] for k in range(len(z))])
+
+
+def test_preconditioned_region_solves(el, ctx, trained):
+    """The learned M on the solve path: region solves whose overlap solves are CG preconditioned by
+    M (elses_mat_set_preconditioner, opts.precond), FP64 and mixed, against the oracle on the carved
+    pencils and against the plain solve; M narrows the overlap solves to fewer steps."""
+    import dataclasses
+    theta = trained[0]
+    s = synth.make_system(600, 4242)
+    z = synth.shift_grid(16)
+    K = len(z)
+    rng = np.random.default_rng(71)
+    centres = np.sort(rng.choice(s.n_atoms, size=40, replace=False)).astype(np.int32)
+    radii = rng.uniform(4.0, 7.0, size=centres.size)
+    for precision in ("fp64", "mixed"):
+        mat = el.Matrix.from_system(ctx, s, precision=precision)
+        plain_reg = el.Regions(ctx, mat, centres, radii)
+        el.set_preconditioner(ctx, mat, theta, bf16=True)
+        reg = el.Regions(ctx, mat, centres, radii)
+        mixed = precision == "mixed"
+        tol = 1e-10 if not mixed else 1e-8
+        plain = el.region_solve(ctx, plain_reg, z, tol=tol, mixed=mixed)
+        prod_plain, fb0 = el.solve_counts(ctx)
+        pre = el.region_solve(ctx, reg, z, tol=tol, mixed=mixed, precond=True)
+        prod_pre, fb = el.solve_counts(ctx)
+        it_plain = plain["iters"].cpu().numpy()
+        it_pre = pre["iters"].cpu().numpy()
+        print(f"\n{precision}: sparse products {prod_plain} plain -> {prod_pre} preconditioned "
+              f"({prod_plain / it_plain.sum():.1f} -> {prod_pre / it_pre.sum():.1f} per column-iteration), "
+              f"fallbacks {fb}")
+        assert fb0 == 0 and fb == 0
+        assert np.all(pre["resid"].cpu().numpy() <= tol)
+        xp, xq = plain["x"].cpu().numpy(), pre["x"].cpu().numpy()
+        assert np.abs(xq - xp).max() <= (1e-8 if not mixed else 1e-6) * np.abs(xp).max()
+        sysm = s if not mixed else dataclasses.replace(
+            s, A_val=s.A_val.astype(np.float32).astype(np.float64), B_val=s.B_val.astype(np.float32).astype(np.float64))
+        for c in range(0, reg.n_cols, 11):
+            xr = _carved_ref(sysm, reg, centres, radii, c, z)
+            blk = xq[reg.pat_off[c] * K:reg.pat_off[c + 1] * K].reshape(K, -1)
+            assert np.abs(blk - xr).max() <= (1e-8 if not mixed else 5e-7) * np.abs(xr).max(), (precision, c)
+
+
+def test_preconditioner_fallback(el, ctx):
+    """An indefinite M (a network whose output is minus the identity blocks on every pair) is judged by
+    CG's curvature test: every region falls back to the plain iteration and the answers are unchanged."""
+    s = synth.make_system(600, 4242)
+    mat = el.Matrix.from_system(ctx, s)
+    theta = np.zeros(mlp.N_PARAM, dtype=np.float32)
+    theta[-16:] = -np.eye(4, dtype=np.float32).reshape(-1)  # b4: output -I for every pair
+    el.set_preconditioner(ctx, mat, dev(theta), bf16=False)
+    rng = np.random.default_rng(72)
+    centres = np.sort(rng.choice(s.n_atoms, size=12, replace=False)).astype(np.int32)
+    radii = rng.uniform(4.0, 6.0, size=centres.size)
+    reg = el.Regions(ctx, mat, centres, radii)
+    z = synth.shift_grid(8)
+    plain = el.region_solve(ctx, reg, z, tol=1e-10)
+    pre = el.region_solve(ctx, reg, z, tol=1e-10, precond=True, inner_max=40)
+    _, fb = el.solve_counts(ctx)
+    assert fb == centres.size
+    assert np.array_equal(plain["x"].cpu().numpy(), pre["x"].cpu().numpy())
+    el.set_preconditioner(ctx, mat, None)
+    with pytest.raises(el.ElsesError):  # a set built without M cannot run the preconditioned path
+        el.region_solve(ctx, el.Regions(ctx, mat, centres, radii), z, precond=True)
