@@ -358,6 +358,28 @@ elses_status elses_regions_solve(elses_ctx ctx, elses_regions reg, int32_t n_shi
                                  double *resid_out);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * solve as elses_regions_solve on a compact region set, with every work
+ * buffer taken from a fixed scratch array that the library holds on each GPU
+ * (256 MiB per GPU, for the life of the process).  It calls no hipMalloc or
+ * hipFree and creates no stream or event; the column-width groups run one
+ * after another on the context stream, with as many workgroups as the
+ * scratch holds.  Outputs, arguments and results are those of
+ * elses_regions_solve (profiling statistics are not sampled).  A solve whose
+ * per-column state does not fit (about K x pattern length x 32 bytes per
+ * column plus K x 76 bytes, with K the shift count) returns
+ * ELSES_ERR_INVALID_ARG with the size it needs.  Every call on a GPU shares
+ * that GPU's array and leaves its contents behind: calls that overlap on one
+ * GPU (from several threads or streams) race, and must be serialised by the
+ * caller.  Tile region sets return ELSES_ERR_INVALID_ARG.
+ */
+elses_status elses_regions_solve_noalloc(elses_ctx ctx, elses_regions reg, int32_t n_shifts, const double *shifts,
+                                        const double *c, const elses_opts *opts, double *x_out, double *rho_out,
+                                        double *traces_out, double *col_traces_out, int32_t *iters_out,
+                                        double *resid_out);
+
+/*
  * Learned block sparse approximate inverse (SPAI) of the overlap B.
  *
  * The overlap solves B v = s of the method (paper Sec. III-B: B^{-1} enters

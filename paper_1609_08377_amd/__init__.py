@@ -137,6 +137,8 @@ def lib():
         L.elses_regions_info.restype = ctypes.c_int
         L.elses_regions_solve.argtypes = [P, P, I32, P, P, ctypes.POINTER(Opts), P, P, P, P, P, P]
         L.elses_regions_solve.restype = ctypes.c_int
+        L.elses_regions_solve_noalloc.argtypes = [P, P, I32, P, P, ctypes.POINTER(Opts), P, P, P, P, P, P]
+        L.elses_regions_solve_noalloc.restype = ctypes.c_int
         L.elses_arnoldi_opts_default.argtypes = [ctypes.POINTER(ArnoldiOpts)]
         L.elses_arnoldi_opts_default.restype = None
         L.elses_arnoldi.argtypes = [P, P, I32, P, ctypes.POINTER(ArnoldiOpts), P, P, P, P, P, P, P]
@@ -443,7 +445,7 @@ def solve_counts(ctx: Context) -> tuple[int, int]:
 
 def region_solve(ctx: Context, reg: Regions, shifts, c=None, *, tol=1e-8, max_outer=20000, inner_tol=1e-13,
                  mixed=False, want_x=True, allow_not_converged=False, variant="auto", graph=False, full=False,
-                 audit=False, audit_every=0, precond=False, inner_max=200):
+                 audit=False, audit_every=0, precond=False, inner_max=200, noalloc=False):
     """Solve every region's columns for every shift; density outputs when weights c are given.
 
     Compact region sets also take full=True (x holds, per column, the [K][m_r] vectors of its region in
@@ -469,7 +471,8 @@ def region_solve(ctx: Context, reg: Regions, shifts, c=None, *, tol=1e-8, max_ou
     opts.audit_every = int(audit_every)
     opts.precond = 1 if precond else 0
     opts.inner_max = int(inner_max)
-    st = lib().elses_regions_solve(ctx._h, reg._h, K, _np_ptr(z), None if cw is None else _np_ptr(cw),
+    fn = lib().elses_regions_solve_noalloc if noalloc else lib().elses_regions_solve
+    st = fn(ctx._h, reg._h, K, _np_ptr(z), None if cw is None else _np_ptr(cw),
                                    ctypes.byref(opts), _dev_ptr(x), _dev_ptr(rho),
                                    None if cw is None else _np_ptr(traces), _dev_ptr(col_tr), _dev_ptr(iters),
                                    _dev_ptr(resid))

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -327,9 +328,19 @@ Rich richardson_plan(double lo, double hi, double tol) {
 
 }  // namespace
 
+// Scratch of the allocation-free region solve (elses_regions_solve_noalloc):
+// a file-scope device array that every GPU the library runs on holds until
+// the process ends.  In host code its name is only a stand-in; the device
+// address of each GPU's copy is taken once per device at context creation.
+constexpr size_t kNoAllocBytes = (size_t)256 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
 extern "C" {
 
-const char* elses_version(void) { return "elses-gfx950 0.2"; }
+const char* elses_version(void) { return "elses-gfx950 0.3"; }
 
 void elses_opts_default(elses_opts* o) {
     if (!o) return;
@@ -350,6 +361,16 @@ elses_status elses_ctx_create(int device, void* hip_stream, elses_ctx* out) {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return ELSES_ERR_INVALID_ARG;
     if (hipSetDevice(device) != hipSuccess) return ELSES_ERR_HIP;
+    // this device's address of the allocation-free entry point's scratch array
+    if (device >= kMaxDevices) return ELSES_ERR_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            void* p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ELSES_ERR_HIP;
+            g_scratch_ptr[device] = p;
+        }
+    }
     auto* c = new elses_ctx_s();
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
@@ -1761,11 +1782,36 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
     return ELSES_OK;
 }
 
+// Device work buffers of one call: from a DevPool (allocated and freed per
+// call), or carved from a fixed arena (the allocation-free entry point), in
+// 256-byte aligned pieces.
+struct Scratch {
+    DevPool* pool = nullptr;
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+    template <typename T>
+    T* get(size_t n) {
+        if (pool) return pool->get<T>(n);
+        const size_t bytes = ((std::max<size_t>(n, 1) * sizeof(T)) + 255) & ~(size_t)255;
+        if (used + bytes > cap) throw HipFail{hipErrorOutOfMemory, "no-allocation scratch exhausted"};
+        T* p = reinterpret_cast<T*>(base + used);
+        used += bytes;
+        return p;
+    }
+};
+
+size_t round256(size_t b) { return (std::max<size_t>(b, 1) + 255) & ~(size_t)255; }
+
 // Region solves in the compact layout: argument checks, scratch, one
-// persistent launch (region.hip), then the trace sum.
+// persistent launch per column-width group (region.hip), then the trace sum.
+// With an arena (the allocation-free entry point) every work buffer comes
+// from it, the groups run one after another on the context stream with as
+// many workgroups as the arena holds, and no stream, event or allocation is
+// created.
 elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, const double* shifts, const double* cw,
                            const elses_opts* opts_in, double* x_out, int32_t* iters_out, double* resid_out,
-                           double* rho_out, double* traces_out, double* col_traces_out) {
+                           double* rho_out, double* traces_out, double* col_traces_out, char* arena = nullptr,
+                           size_t arena_bytes = 0) {
     elses_opts o;
     elses_opts_default(&o);
     if (opts_in) o = *opts_in;
@@ -1831,13 +1877,48 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
     // per-workgroup scratch of each group: seven [P][cw] FP64 blocks (twelve with the
     // preconditioned solve's own vectors)
     const size_t nblk = precond ? 12 : 7;
+    const bool noalloc = arena != nullptr;
+    if (noalloc) {
+        // fixed part of the arena, in the order and rounding of the gets below
+        size_t fixed = round256(sizeof(int64_t) * (n_cols + 1)) * 2 + round256(sizeof(int) * n_cols) +
+                       round256(sizeof(double) * 2 * K) * (density ? 2 : 1) +
+                       round256(sizeof(double) * std::max<size_t>(1, rich.tau.size())) +
+                       round256(sizeof(double) * n_cols * K * 2) * 2 + round256(sizeof(double) * n_cols * K) +
+                       round256(sizeof(double) * n_cols * K * 4) + round256(sizeof(int) * n_cols * K) +
+                       round256(sizeof(double) * carry_off[n_cols] * 2) * 2 + round256(sizeof(int) * 8) +
+                       (iters_out ? 0 : round256(sizeof(int32_t) * n_cols)) +
+                       ((density && !col_traces_out && traces_out) ? round256(sizeof(double) * 2 * n_cols) : 0) +
+                       ((density && traces_out) ? round256(sizeof(double) * 2) : 0);
+        // the groups run one after another and share the per-workgroup blocks
+        size_t need_one = 0;
+        for (int g = 0; g < 3; ++g)
+            if (gwg[g] > 0) need_one = std::max(need_one, nblk * C.gmaxP[g] * C.gcw[g] * sizeof(double));
+        if (fixed + round256(need_one) > arena_bytes)
+            return set_err(ctx, ELSES_ERR_INVALID_ARG,
+                           "the solve needs " + std::to_string(fixed + need_one) +
+                               " bytes of scratch; the allocation-free entry point holds " +
+                               std::to_string(arena_bytes) + " (use fewer columns or shifts per call)");
+        const size_t room = arena_bytes - fixed - 256;
+        for (int g = 0; g < 3; ++g) {
+            if (gwg[g] == 0) continue;
+            const size_t per = nblk * C.gmaxP[g] * C.gcw[g] * sizeof(double);
+            gwg[g] = (int)std::max<size_t>(1, std::min<size_t>((size_t)gwg[g], room / per));
+        }
+    }
     size_t gvec[3] = {0, 0, 0};
     for (int g = 0; g < 3; ++g) gvec[g] = nblk * C.gmaxP[g] * C.gcw[g] * gwg[g];
     int n_notconv = 0;
     try {
         HCHECK(hipSetDevice(ctx->device));
         hipStream_t st = ctx->stream;
-        DevPool pool;
+        DevPool dpool;
+        Scratch pool;
+        if (noalloc) {
+            pool.base = arena;
+            pool.cap = arena_bytes;
+        } else {
+            pool.pool = &dpool;
+        }
         CompactArgs a{};
         a.reg = C.d_reg;
         a.order = C.d_order;
@@ -1889,19 +1970,16 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         HCHECK(hipMemcpyAsync(d_tau, rich.tau.data(), sizeof(double) * rich.tau.size(), hipMemcpyHostToDevice, st));
         a.tau = d_tau;
         a.g0 = rich.g0;
-        double* vec_g[3] = {nullptr, nullptr, nullptr};
-        for (int g = 0; g < 3; ++g)
-            if (gvec[g] > 0) vec_g[g] = pool.get<double>(gvec[g]);
         a.eta = pool.get<double>((size_t)n_cols * K * 2);
         a.zeta = pool.get<double>((size_t)n_cols * K * 2);
         a.res = pool.get<double>((size_t)n_cols * K);
         a.fac = pool.get<double>((size_t)n_cols * K * 4);
         a.conv = pool.get<int>((size_t)n_cols * K);
-        HCHECK(hipMemsetAsync(a.conv, 0, sizeof(int) * n_cols * K, st));
+        launch_zero_ints(a.conv, (size_t)n_cols * K, st);
         a.xs = pool.get<double>((size_t)carry_off[n_cols] * 2);
         a.ps = pool.get<double>((size_t)carry_off[n_cols] * 2);
         int* counters = pool.get<int>(8);  // three queues, not-converged, fallbacks, pad, product count
-        HCHECK(hipMemsetAsync(counters, 0, sizeof(int) * 8, st));
+        launch_zero_ints(counters, 8, st);
         a.n_notconv = counters + 3;
         a.n_fallback = counters + 4;
         a.products = reinterpret_cast<unsigned long long*>(counters + 6);
@@ -1913,33 +1991,49 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         double* ctr = col_traces_out;
         if (density && !ctr && traces_out) ctr = pool.get<double>(2 * (size_t)n_cols);
         a.ctr_out = density ? ctr : nullptr;
+        double* tr2 = (density && traces_out && ctr) ? pool.get<double>(2) : nullptr;
+        // per-workgroup blocks last: in the arena the groups share one buffer
+        double* vec_g[3] = {nullptr, nullptr, nullptr};
+        if (noalloc) {
+            size_t most = 0;
+            for (int g = 0; g < 3; ++g) most = std::max(most, gvec[g]);
+            double* shared = most ? pool.get<double>(most) : nullptr;
+            for (int g = 0; g < 3; ++g) vec_g[g] = gvec[g] ? shared : nullptr;
+        } else {
+            for (int g = 0; g < 3; ++g)
+                if (gvec[g] > 0) vec_g[g] = pool.get<double>(gvec[g]);
+        }
         // One launch per group, on streams of their own (default priority) so
         // that a group's last regions overlap the next group's work: the
         // widest regions (longest per region) start first.  HIP events around
         // each launch when profiling is enabled.
         hipEvent_t ev[3][2] = {};
-        const bool timed = ctx->prof_stride > 0;
-        hipStream_t gst[3] = {st, nullptr, nullptr};
+        const bool timed = ctx->prof_stride > 0 && !noalloc;
+        hipStream_t gst[3] = {st, st, st};
+        hipStream_t own[3] = {nullptr, nullptr, nullptr};  // streams created here
         hipEvent_t ready = nullptr, gdone[3] = {};
         struct StreamGuard {
             hipStream_t* s;
             hipEvent_t* e;
             hipEvent_t* r;
             ~StreamGuard() {
-                for (int g = 1; g < 3; ++g)
+                for (int g = 0; g < 3; ++g)
                     if (s[g]) (void)hipStreamDestroy(s[g]);
                 for (int g = 0; g < 3; ++g)
                     if (e[g]) (void)hipEventDestroy(e[g]);
                 if (*r) (void)hipEventDestroy(*r);
             }
-        } guard{gst, gdone, &ready};
-        HCHECK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-        HCHECK(hipEventRecord(ready, st));
+        } guard{own, gdone, &ready};
+        if (!noalloc) {
+            HCHECK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+            HCHECK(hipEventRecord(ready, st));
+        }
         for (int g = 0; g < 3; ++g) {
             const int cnt = C.goff[g + 1] - C.goff[g];
             if (cnt == 0) continue;
-            if (g > 0) {
-                HCHECK(hipStreamCreateWithFlags(&gst[g], hipStreamNonBlocking));
+            if (!noalloc && g > 0) {
+                HCHECK(hipStreamCreateWithFlags(&own[g], hipStreamNonBlocking));
+                gst[g] = own[g];
                 HCHECK(hipStreamWaitEvent(gst[g], ready, 0));
             }
             a.order = C.d_order + C.goff[g];
@@ -1955,15 +2049,13 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
             launch_compact(a, !mixed, C.gcw[g], precond, gwg[g], glds[g], gst[g]);
             HCHECK(hipGetLastError());
             if (timed) HCHECK(hipEventRecord(ev[g][1], gst[g]));
-            if (g > 0) {
+            if (g > 0 && !noalloc) {
                 HCHECK(hipEventCreateWithFlags(&gdone[g], hipEventDisableTiming));
                 HCHECK(hipEventRecord(gdone[g], gst[g]));
                 HCHECK(hipStreamWaitEvent(st, gdone[g], 0));
             }
         }
-        double* tr2 = nullptr;
-        if (density && traces_out && ctr) {
-            tr2 = pool.get<double>(2);
+        if (tr2) {
             launch_sum_pairs(ctr, n_cols, tr2, st);
             HCHECK(hipMemcpyAsync(traces_out, tr2, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
         }
@@ -2205,6 +2297,25 @@ elses_status elses_regions_info(elses_regions reg, int32_t* n_cols, int32_t* n_t
     if (pat_off) std::copy(reg->pat_off.begin(), reg->pat_off.end(), pat_off);
     if (region_orbitals) std::copy(reg->region_orbs.begin(), reg->region_orbs.end(), region_orbitals);
     return ELSES_OK;
+}
+
+elses_status elses_regions_solve_noalloc(elses_ctx ctx, elses_regions reg, int32_t n_shifts, const double* shifts,
+                                        const double* c, const elses_opts* opts, double* x_out, double* rho_out,
+                                        double* traces_out, double* col_traces_out, int32_t* iters_out,
+                                        double* resid_out) {
+    if (!ctx || !reg) return ELSES_ERR_INVALID_ARG;
+    if (!reg->compact)
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "the allocation-free solve needs a compact region set");
+    if (!c && (rho_out || traces_out || col_traces_out))
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "density outputs need the weights c");
+    void* arena = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        arena = (ctx->device >= 0 && ctx->device < kMaxDevices) ? g_scratch_ptr[ctx->device] : nullptr;
+    }
+    if (!arena) return set_err(ctx, ELSES_ERR_HIP, "no scratch address for this device");
+    return compact_solve(ctx, reg, n_shifts, shifts, c, opts, x_out, iters_out, resid_out, rho_out, traces_out,
+                         col_traces_out, static_cast<char*>(arena), kNoAllocBytes);
 }
 
 elses_status elses_regions_columns(elses_regions reg, int32_t* col_region) {

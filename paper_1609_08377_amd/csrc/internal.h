@@ -384,6 +384,9 @@ int compact_occupancy(bool fp64, int cw, bool precond, size_t lds);
 // one persistent launch over the regions a.order[0 .. a.n_regions) (all of column width cw)
 void launch_compact(const CompactArgs& a, bool fp64, int cw, bool precond, int n_wg, size_t lds, hipStream_t st);
 
+// n ints set to zero by a kernel (no memset node, so the call can be captured)
+void launch_zero_ints(int* p, size_t n, hipStream_t st);
+
 // Host-side construction of the compact layout (region_host.hip).
 struct CompactHost {
     std::vector<RegionDesc> reg;

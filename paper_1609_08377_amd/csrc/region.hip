@@ -33,6 +33,8 @@
 // 13-14), the LU recurrences of (z_k I - T_n) for every shift, and the
 // residual estimate |zeta/eta| ||s_n||.  All reductions are workgroup
 // reductions in a fixed order.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace elses {
@@ -865,7 +867,17 @@ const void* kernel_for(bool fp64, int cw, bool pc) {
     return fp64 ? pick_kernel<double, 0>(cw) : pick_kernel<float, 0>(cw);
 }
 
+__global__ void zero_ints_kernel(int* __restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
 }  // namespace
+
+void launch_zero_ints(int* p, size_t n, hipStream_t st) {
+    const unsigned blocks = (unsigned)std::min<size_t>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(std::max(1u, blocks)), dim3(256), 0, st, p, n);
+}
 
 int compact_occupancy(bool fp64, int cw, bool precond, size_t lds) {
     const void* k = kernel_for(fp64, cw, precond);
