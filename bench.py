@@ -1,25 +1,37 @@
 """Throughput of the generalized shifted Krylov solver on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--config c2] [--batch 1024]
+    python bench.py [--steps K] [--warmup W] [--config c5] [--batch 1280]
 
-Workload (default c2): every column j of the 4096-atom box (M = 8191) and 64
-shifts z_k.  The columns are processed in batches of `--batch` consecutive
-columns; one step = one elses_density_matrix call over one batch: for every
-column of the batch and every shift it solves (z_k B - A) x = e_j to a
-relative residual of 1e-8 (Lanczos outer process, Richardson overlap solves,
-fused multi-shift update, slot refill) and assembles the density-matrix
-elements rho_ij = sum_k Im(c_k x_{j,k,i}) on the pattern plus the traces
-Tr[rho B] and Tr[rho A].  Step s takes batch s mod n_batches, so
---steps n_batches (8 for c2) covers the whole job once.  Inputs are resident
-in HBM before the timed region; a short untimed solve loads the kernels first.
+Default workload (c5): the one-GPU share of a 10^6-atom amorphous hydrocarbon
+box (M = 2.0e6, FP32-stored A and B beside the FP64 values).  65536 columns
+are sampled uniformly; each is solved as a region problem on the atoms within
+a radius drawn from U[6, 14] A of the column's atom (Sec. III-B, III-C), for
+128 shifts z_k = eps_k + 0.01i on [-1, 1] Ha, to a relative residual of 1e-8.
+The regions are cut into batches of about `--batch` columns (consecutive
+regions); one step = one elses_regions_solve over one batch: the compact
+per-region layout in one persistent launch per column-width group (Lanczos
+outer process in the B inner product, FP32 Chebyshev-Richardson overlap
+solves with FP64-accumulated refinement, fused multi-shift update), with the
+density-matrix elements on the column patterns and e_j^T rho B e_j,
+e_j^T rho A e_j per column.  The region sets are built before the timed
+region; steps cycle through them.  Inputs are resident in HBM before the
+timed region; a short untimed solve loads the kernels first.
 
 Prints one JSON line with the metric (column x shift solves per second), the
-roofline of the dominant kernel (the Richardson step of the overlap solve:
-the grouped B pass, HBM-bound; algorithmic bytes per launch / mean launch time
-measured with HIP events on the solver's stream), the HBM traffic of that
-kernel from the committed rocprofv3 counter summary when it was taken on the
-current kernel source, and the CPU oracle timed on a bounded sample on the
-host's cores.
+roofline of the dominant kernel (the persistent compact solve: algorithmic
+bytes per solve over the span from its first group launch's start to its last
+group launch's end, measured with HIP events on the launch streams), the HBM
+traffic of that solve from the committed rocprofv3 counter summary when it
+was taken on the current kernel source at this batch size, an FP64 true
+residual recomputed in the kernel for a subsample of columns, the plain FP64
+tile method timed on a small sample for comparison, and the CPU oracle timed
+on a bounded sample on the host's cores.
+
+Other configurations: c1/c2 (global solves of every column of a 128/4096-atom
+box), c3 (2048 regions of a 50000-atom box), c4 (16384 sampled columns of a
+100000-atom box with the learned preconditioner and the plain overlap
+iteration compared); --method arnoldi / balance / pass for the multiple
+Arnoldi method, idle-lane measurements and the global pass alone.
 
     python bench.py --copy-calib 1073741824
 
@@ -644,7 +656,7 @@ def main():
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--config", default="c5", choices=sorted(WORKLOADS))
-    ap.add_argument("--batch", type=int, default=0, help="columns per step (0: 1024 for c2, 640 for c4/c5)")
+    ap.add_argument("--batch", type=int, default=0, help="columns per step (0: 1024 for c2, 1280 for c4/c5)")
     ap.add_argument("--max-sets", type=int, default=8, help="c4/c5: region sets built (steps cycle through them)")
     ap.add_argument("--plain-sample", type=int, default=192,
                     help="c4/c5: columns on which the plain FP64 tile method is timed against this path (0: skip)")
@@ -687,7 +699,7 @@ def main():
         run_balance(args)
         return
     if args.batch == 0:
-        args.batch = 640 if args.config in N_SAMPLED else 1024
+        args.batch = 1280 if args.config in N_SAMPLED else 1024
     if args.tile < 0:
         args.tile = 0 if args.method == "shifted" else 64
     if args.method == "pass":
