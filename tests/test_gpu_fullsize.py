@@ -142,8 +142,82 @@ def test_c3_region_tiles(el, ctx):
                 assert np.abs(blk[k] - r64).max() <= 1e-5 * np.abs(r64).max()
 
 
+def first_step_regions(s, n_sampled, seed, batch=1280):
+    """The region set of the benchmark's first step: sampled columns, radius U[6,14] A,
+    the columns of one atom sharing its region, consecutive regions up to `batch` columns."""
+    cols = synth.sample_columns(s, n_sampled, seed)
+    centres, masks, radii = synth.column_regions(s, cols, seed)
+    ncol = np.array([bin(int(m)).count("1") for m in masks])
+    nb = int(np.searchsorted(np.cumsum(ncol), batch, side="left")) + 1
+    return centres[:nb], masks[:nb], radii[:nb], ncol[:nb]
+
+
+def check_region_subsample(s, reg, centres, radii, ncol, out, z, cw, seed):
+    """x, rho and the per-column traces of a seeded subsample of a mixed-precision region
+    solve (the largest region, the smallest, a multi-column one and two random ones)
+    against the oracle on the carved FP32-rounded pencil (what mixed precision solves,
+    5e-7) and, below the largest, on the FP64 pencil (1e-5)."""
+    K = len(z)
+    nb = centres.size
+    xg = out["x"].cpu().numpy()
+    rho = out["rho"].cpu().numpy()
+    ctr = out["col_traces"].cpu().numpy()
+    rng = np.random.default_rng(seed)
+    big = int(np.argmax(reg.region_orbitals))
+    picks = [big, int(np.argmin(reg.region_orbitals))]
+    multi = np.nonzero(ncol > 1)[0]
+    if multi.size:
+        picks.append(int(multi[0]))
+    picks += [int(r) for r in rng.choice(nb, size=2, replace=False)]
+    picks = list(dict.fromkeys(picks))
+    s32 = rounded(s)
+    jobs = []
+    for r in picks:
+        for c in np.nonzero(reg.col_region == r)[0]:
+            jobs.append((int(r), int(c), s32, 5e-7))
+            if r != big:
+                jobs.append((int(r), int(c), s, 1e-5))
+
+    def run(job):
+        r, c, sysm, bound = job
+        atoms = oracle.region_atoms(sysm, int(centres[r]), float(radii[r]))
+        Ar, Br, orb_map = oracle.carve_region(sysm, atoms)
+        loc = {int(g): l for l, g in enumerate(orb_map)}
+        j = int(reg.cols[c])
+        ref = oracle.shifted_solve(Ar, Br, np.array([loc[j]], dtype=np.int32), z, tol=1e-8 if r == big else 1e-9,
+                                   full=False, true_residual=False, nthreads=1)
+        # radius >= 6 A > the 4 A cutoff: the whole pattern of j lies inside the region, in the same order
+        rows_j = pattern_rows(s, j)
+        assert ref.pat_off[1] == rows_j.size
+        return job, ref.x.reshape(K, rows_j.size)
+
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=min(16, len(jobs))) as ex:
+        results = list(ex.map(run, jobs))
+    for (r, c, sysm, bound), xr in results:
+        j = int(reg.cols[c])
+        blk = xg[reg.pat_off[c] * K:reg.pat_off[c + 1] * K].reshape(K, -1)
+        assert np.abs(blk - xr).max() <= bound * np.abs(xr).max(), (r, c, bound)
+        # rho_ij = sum_k Im(c_k x_{j,k,i}) on the pattern (Eq. 12) and e_j^T rho X e_j (Eq. 7) from the
+        # oracle's x and the matrix values of row j
+        rho_r = np.imag(cw[:, None] * xr).sum(axis=0)
+        tb = float(rho_r @ pattern_values(s, j, "B"))
+        ta = float(rho_r @ pattern_values(s, j, "A"))
+        rg = rho[reg.pat_off[c]:reg.pat_off[c + 1]]
+        assert np.abs(rg - rho_r).max() <= 2 * bound * np.abs(rho_r).max(), (r, c)
+        assert abs(ctr[c, 0] - tb) <= 2 * bound * abs(tb) + 1e-14, (r, c)
+        assert abs(ctr[c, 1] - ta) <= 2 * bound * abs(ta) + 1e-14, (r, c)
+    return sorted(int(reg.region_orbitals[r]) for r in picks)
+
+
 def test_c4_learned_spai_and_regions(el, ctx):
-    """100000-atom box: learned SPAI inference at full size, and sampled-column regions."""
+    """100000-atom box: the learned SPAI assembled into the matrix at full size
+    (elses_mat_set_preconditioner, BF16 inference), the standalone preconditioned
+    overlap solve against the plain one, then the benchmark's first c4 step: 1280
+    sampled columns solved as mixed-precision compact regions (radius U[6,14] A,
+    64 shifts) with the overlap solves preconditioned by M, x, rho and the
+    per-column traces of a seeded subsample (the largest and the smallest region
+    included) against the oracle on the carved pencils."""
     from oracle import mlp
     feats, targs, masks = [], [], []
     for seed in (21, 22, 23):
@@ -156,7 +230,7 @@ def test_c4_learned_spai_and_regions(el, ctx):
     el.spai_train(ctx, theta, torch.cat(feats), torch.cat(targs), torch.cat(masks), steps=1500, batch=4096,
                   lr=2e-3, seed=4)
     s = synth.make_system(100000, synth.config_seed(4))
-    mat = el.Matrix.from_system(ctx, s)
+    mat = el.Matrix.from_system(ctx, s, precision="mixed")
     Mv = el.spai_apply(ctx, mat, theta, bf16=True)
     rhs = torch.as_tensor(np.random.default_rng(4).standard_normal((mat.M, 64))).cuda()
     x0, p0, br0, u0 = el.overlap_solve(ctx, mat, rhs)
@@ -167,30 +241,22 @@ def test_c4_learned_spai_and_regions(el, ctx):
     res = el.spmm(ctx, mat, "B", x1) - rhs
     assert res.abs().max().item() <= 1e-11 * rhs.abs().max().item()
     print(f"\nC4 SPAI: interval ratio {br0[1] / br0[0]:.3f} -> {br1[1] / br1[0]:.3f}, passes {p0} -> {p1}")
-    # region solves of sampled columns (the region radius rule of the region workload)
-    cols = synth.sample_columns(s, 16384, synth.config_seed(4))[:24]
-    atom_of = np.repeat(np.arange(s.n_atoms), s.n_orb.astype(int))
-    centres = np.unique(atom_of[cols]).astype(np.int32)
-    radii = np.random.default_rng(synth.config_seed(4) + 3).uniform(6.0, 14.0, size=centres.size)
-    reg = el.Regions(ctx, mat, centres, radii, 64)
+    del Mv, rhs, x0, x1, res
+    # M on the matrix, then the region set of the benchmark's first step
+    el.set_preconditioner(ctx, mat, theta, bf16=True)
+    centres, masks, radii, ncol = first_step_regions(s, 16384, synth.config_seed(4))
+    reg = el.Regions(ctx, mat, centres, radii, orb_mask=masks)
     z = synth.shift_grid(64)
-    out = el.region_solve(ctx, reg, z, tol=1e-8)
+    cw = fermi_cw(z)
+    el.solve_counts(ctx)
+    out = el.region_solve(ctx, reg, z, cw, tol=1e-8, mixed=True, precond=True)
+    products, fallbacks = el.solve_counts(ctx)
     assert np.all(out["resid"].cpu().numpy() <= 1e-8)
-    r = int(np.argmin(reg.region_orbitals))  # the smallest region against the oracle
-    atoms = oracle.region_atoms(s, int(centres[r]), float(radii[r]))
-    Ar, Br, orb_map = oracle.carve_region(s, atoms)
-    loc = {int(g): l for l, g in enumerate(orb_map)}
-    col_region = np.repeat(np.arange(centres.size), [int(s.n_orb[c]) for c in centres])
-    c = int(np.nonzero(col_region == r)[0][0])
-    j = int(reg.cols[c])
-    ref = oracle.shifted_solve(Ar, Br, np.array([loc[j]], dtype=np.int32), z, tol=1e-10, full=True,
-                               true_residual=False)
-    rows = pattern_rows(s, j)
-    K = len(z)
-    blk = out["x"].cpu().numpy()[reg.pat_off[c] * K:reg.pat_off[c + 1] * K].reshape(K, -1)
-    for k in range(K):
-        rk = np.array([ref.x[0, k, loc[int(i)]] if int(i) in loc else 0.0 for i in rows])
-        assert np.abs(blk[k] - rk).max() <= 5e-7 * np.abs(rk).max()
+    print(f"C4: {reg.n_cols} sampled columns in {centres.size} regions of {reg.region_orbitals.min()}-"
+          f"{reg.region_orbitals.max()} orbitals, outer iterations max {int(out['iters'].max())}, "
+          f"{products} sparse products, {fallbacks} preconditioner fallbacks", flush=True)
+    sizes = check_region_subsample(s, reg, centres, radii, ncol, out, z, cw, 44)
+    print(f"C4 subsample against the oracle: regions of {sizes} orbitals", flush=True)
 
 
 def _row_products(s, rows, x, which):
@@ -220,7 +286,7 @@ def _row_products(s, rows, x, which):
 def test_c5_one_gpu_share(el, ctx):
     """10^6-atom box (M = 2.0e6, FP32-stored matrices): sampled rows of the FP32
     and FP64 products against exact products from the atom blocks; then the
-    first step of `bench.py` (default c5): 640 sampled columns solved as
+    first step of `bench.py` (default c5): 1280 sampled columns solved as
     mixed-precision compact regions (radius U[6,14] A, 128 shifts), with x,
     rho and the per-column traces of a seeded subsample (the largest and the
     smallest region included) against the oracle on the carved pencils."""
@@ -243,72 +309,16 @@ def test_c5_one_gpu_share(el, ctx):
     assert np.all(np.abs(got - ref) <= 1e-14 * mag + 1e-300)
     del x64, y64
     del mat
-    # the benchmark's first step: its region set (sampled columns, radius U[6,14] A, columns of one
-    # atom sharing its region) in the compact layout, 128 shifts, mixed precision, rho and traces
+    # the benchmark's first step: its region set in the compact layout, 128 shifts, mixed precision,
+    # rho and traces
     mat = el.Matrix.from_system(ctx, s, precision="mixed")
-    cols = synth.sample_columns(s, 65536, synth.config_seed(5))
-    centres, masks, radii = synth.column_regions(s, cols, synth.config_seed(5))
-    ncol = np.array([bin(int(m)).count("1") for m in masks])
-    nb = int(np.searchsorted(np.cumsum(ncol), 640, side="left")) + 1
-    centres, masks, radii = centres[:nb], masks[:nb], radii[:nb]
+    centres, masks, radii, ncol = first_step_regions(s, 65536, synth.config_seed(5))
     reg = el.Regions(ctx, mat, centres, radii, orb_mask=masks)
     z = synth.shift_grid(128)
-    K = len(z)
     cw = fermi_cw(z)
     out = el.region_solve(ctx, reg, z, cw, tol=1e-8, mixed=True)
     assert np.all(out["resid"].cpu().numpy() <= 1e-8)
-    xg = out["x"].cpu().numpy()
-    rho = out["rho"].cpu().numpy()
-    ctr = out["col_traces"].cpu().numpy()
-    print(f"\nC5: {reg.n_cols} sampled columns in {nb} regions of {reg.region_orbitals.min()}-"
+    print(f"\nC5: {reg.n_cols} sampled columns in {centres.size} regions of {reg.region_orbitals.min()}-"
           f"{reg.region_orbitals.max()} orbitals, outer iterations max {int(out['iters'].max())}", flush=True)
-    # seeded subsample: the largest region, the smallest, a multi-column region and two random ones;
-    # the oracle on the carved FP32-rounded pencil (what mixed precision solves) and, for the
-    # smaller ones, on the FP64 pencil
-    rng = np.random.default_rng(55)
-    big = int(np.argmax(reg.region_orbitals))
-    picks = [big, int(np.argmin(reg.region_orbitals))]
-    multi = np.nonzero(ncol[:nb] > 1)[0]
-    if multi.size:
-        picks.append(int(multi[0]))
-    picks += [int(r) for r in rng.choice(nb, size=2, replace=False)]
-    picks = list(dict.fromkeys(picks))
-    s32 = rounded(s)
-    jobs = []
-    for r in picks:
-        for c in np.nonzero(reg.col_region == r)[0]:
-            jobs.append((int(r), int(c), s32, 5e-7))
-            if r != big:
-                jobs.append((int(r), int(c), s, 1e-5))
-
-    def run(job):
-        r, c, sysm, bound = job
-        atoms = oracle.region_atoms(sysm, int(centres[r]), float(radii[r]))
-        Ar, Br, orb_map = oracle.carve_region(sysm, atoms)
-        loc = {int(g): l for l, g in enumerate(orb_map)}
-        j = int(reg.cols[c])
-        ref = oracle.shifted_solve(Ar, Br, np.array([loc[j]], dtype=np.int32), z, tol=1e-8 if r == big else 1e-9,
-                                   full=False, true_residual=False, nthreads=1)
-        # radius >= 6 A > the 4 A cutoff: the whole pattern of j lies inside the region, in the same order
-        rows_j = pattern_rows(s, j)
-        assert ref.pat_off[1] == rows_j.size
-        return job, ref.x.reshape(K, rows_j.size)
-
-    import concurrent.futures as cf
-    with cf.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
-        results = list(ex.map(run, jobs))
-    for (r, c, sysm, bound), xr in results:
-        j = int(reg.cols[c])
-        blk = xg[reg.pat_off[c] * K:reg.pat_off[c + 1] * K].reshape(K, -1)
-        assert np.abs(blk - xr).max() <= bound * np.abs(xr).max(), (r, c, bound)
-        # rho_ij = sum_k Im(c_k x_{j,k,i}) on the pattern (Eq. 12) and e_j^T rho X e_j (Eq. 7) from the
-        # oracle's x and the matrix values of row j
-        rho_r = np.imag(cw[:, None] * xr).sum(axis=0)
-        tb = float(rho_r @ pattern_values(s, j, "B"))
-        ta = float(rho_r @ pattern_values(s, j, "A"))
-        rg = rho[reg.pat_off[c]:reg.pat_off[c + 1]]
-        assert np.abs(rg - rho_r).max() <= 2 * bound * np.abs(rho_r).max(), (r, c)
-        assert abs(ctr[c, 0] - tb) <= 2 * bound * abs(tb) + 1e-14, (r, c)
-        assert abs(ctr[c, 1] - ta) <= 2 * bound * abs(ta) + 1e-14, (r, c)
-    print(f"C5 subsample against the oracle: regions of {sorted(int(reg.region_orbitals[r]) for r in picks)} "
-          f"orbitals", flush=True)
+    sizes = check_region_subsample(s, reg, centres, radii, ncol, out, z, cw, 55)
+    print(f"C5 subsample against the oracle: regions of {sizes} orbitals", flush=True)
