@@ -25,8 +25,9 @@
 // Per workgroup, the iterate of the overlap solve lives in LDS (it is
 // gathered by every sparse product of the inner iteration); the Lanczos
 // vectors live in a per-workgroup scratch area in global memory (touched a
-// few times per outer step, L2-resident); each lane keeps the new iterate of
-// its own rows in registers between the two barriers of a Richardson step.
+// few times per outer step); a Richardson step writes the new iterate of a
+// lane's rows to a per-workgroup block of that area and copies it into LDS
+// after the barrier that ends the step's gathers.
 //
 // The outer method is the same as in the global solver (shift.hip): a
 // Lanczos process for B^{-1}A in the B inner product from B^{-1} e_j (Eqs.
