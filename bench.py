@@ -607,6 +607,42 @@ def run_sampled(args):
     print(json.dumps(res), flush=True)
 
 
+def run_infer(args):
+    """The learned preconditioner's BF16 inference (matrix-core kernel) on every
+    atom pair of the c4 box (100000 atoms): pairs per second and dense BF16
+    TFLOP/s against the BF16 MFMA peak.  The network is a seeded random
+    initialisation (the time does not depend on the weights); the features are
+    computed once before the timed region; each timed call converts the
+    weights to BF16 and runs the inference kernel."""
+    import torch
+
+    import synth
+    import paper_1609_08377_amd as el
+
+    n_atoms = WORKLOADS["c4"][0]
+    sysm = synth.make_system(n_atoms, synth.config_seed(4))
+    ctx = el.Context(0)
+    mat = el.Matrix.from_system(ctx, sysm)
+    feat = el.spai_features(ctx, mat)
+    theta = torch.as_tensor(el.mlp_init(synth.config_seed(4) + 5), dtype=torch.float32).cuda()
+    n = int(feat.shape[0])
+    for _ in range(max(1, args.warmup)):
+        el.spai_predict(ctx, theta, feat, bf16=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        el.spai_predict(ctx, theta, feat, bf16=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    flop = 2.0 * sum(a * b for a, b in ((40, 128), (128, 128), (128, 128), (128, 16))) * n
+    print(json.dumps({"method": "infer", "pairs": n, "ms_per_call": round(dt * 1e3, 3),
+                      "pairs_per_s": round(n / dt, 1), "tflops_per_call": round(flop / dt / 1e12, 2),
+                      "flop_per_call": flop, "peak_tflops_bf16": 2500.0,
+                      "note": "per call: weight conversion to BF16, the inference kernel, allocation of "
+                              "its weight buffer and a stream synchronisation; the kernel's own time is "
+                              "in the rocprofv3 trace"}), flush=True)
+
+
 def run_pass(args):
     """The sparse pass alone at a workload's full matrix size: the Richardson step
     of the overlap solve (FP32-stored B with FP32 vectors for c5, FP64
@@ -677,7 +713,7 @@ def main():
     ap.add_argument("--max-outer", type=int, default=20000,
                     help="cap on outer iterations (profiling runs only: capped runs do not converge)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--method", default="shifted", choices=["shifted", "arnoldi", "balance", "pass"],
+    ap.add_argument("--method", default="shifted", choices=["shifted", "arnoldi", "balance", "pass", "infer"],
                     help="arnoldi: the multiple Arnoldi method on kappa-atom regions of the 50000-atom box; "
                          "balance: idle lanes of region tiles, amorphous box against a diamond crystal")
     ap.add_argument("--centres", type=int, default=4096, help="arnoldi: region centres (consecutive atoms)")
@@ -697,6 +733,9 @@ def main():
         return
     if args.method == "balance":
         run_balance(args)
+        return
+    if args.method == "infer":
+        run_infer(args)
         return
     if args.batch == 0:
         args.batch = 1280 if args.config in N_SAMPLED else 1024

@@ -420,8 +420,9 @@ elses_status elses_spai_train(elses_ctx ctx, float *params, int64_t n, const flo
                               const float *mask, int32_t steps, int32_t batch, double lr, uint64_t seed,
                               double *loss_history);
 /* Network outputs (DEVICE float [n][16]) for n feature rows; bf16 != 0: BF16
- * weights and activations (round to nearest even) with FP32 accumulation and
- * FP32 biases; otherwise FP32 throughout. */
+ * weights and activations (round to nearest even) on the matrix cores with
+ * FP32 accumulation and FP32 biases (feat must then be 16-byte aligned, else
+ * ELSES_ERR_INVALID_ARG); otherwise FP32 throughout. */
 elses_status elses_spai_predict(elses_ctx ctx, const float *params, int64_t n, const float *feat, int32_t bf16,
                                 float *out);
 /* M on B's pattern: features, inference and assembly (diagonal blocks

@@ -2699,6 +2699,9 @@ elses_status elses_spai_predict(elses_ctx ctx, const float* params, int64_t n, c
                                 float* out) {
     if (!ctx || !params || !feat || !out || n < 0) return ELSES_ERR_INVALID_ARG;
     if (n == 0) return ELSES_OK;
+    if (bf16 && (reinterpret_cast<uintptr_t>(feat) & 15u))
+        return set_err(ctx, ELSES_ERR_INVALID_ARG, "BF16 inference reads feature rows as 16-byte vectors: feat must "
+                                                   "be 16-byte aligned");
     hipStream_t st = ctx->stream;
     try {
         HCHECK(hipSetDevice(ctx->device));

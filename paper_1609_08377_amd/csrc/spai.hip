@@ -346,67 +346,161 @@ void launch_to_bf16(int64_t n, const float* x, uint16_t* y, hipStream_t st) {
     hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, y);
 }
 
-// One workgroup of 256 threads infers 64 pairs: activations in LDS, thread
-// (o, half) accumulates output neuron o for 32 pairs.
-__global__ __launch_bounds__(256) void infer_bf16_kernel(int64_t n, const uint16_t* __restrict__ W1,
-                                                         const float* __restrict__ b1,
-                                                         const uint16_t* __restrict__ W2,
-                                                         const float* __restrict__ b2,
-                                                         const uint16_t* __restrict__ W3,
-                                                         const float* __restrict__ b3,
-                                                         const uint16_t* __restrict__ W4,
-                                                         const float* __restrict__ b4,
-                                                         const float* __restrict__ feat, float* __restrict__ out) {
-    __shared__ float h[2][64][128];
-    const int64_t p0 = (int64_t)blockIdx.x * 64;
-    const int o = threadIdx.x & 127, half = threadIdx.x >> 7;
-    for (int e = threadIdx.x; e < 64 * 40; e += 256) {
-        const int pp = e / 40, f = e - pp * 40;
-        h[0][pp][f] = (p0 + pp < n) ? bf16_round(feat[(p0 + pp) * 40 + f]) : 0.f;
-    }
-    __syncthreads();
-    const uint16_t* Ws[4] = {W1, W2, W3, W4};
-    const float* bs[4] = {b1, b2, b3, b4};
-    const int nin[4] = {40, 128, 128, 128};
-    const int nout[4] = {128, 128, 128, 16};
-    int cur = 0;
-    for (int l = 0; l < 4; ++l) {
-        if (o < nout[l]) {
-            float acc[32];
+// BF16 inference on the matrix cores: v_mfma_f32_16x16x32_bf16, FP32
+// accumulation.  A workgroup of four waves stages the four weight matrices
+// once in LDS (BF16 rows padded by 16 bytes against bank conflicts; layer 1's
+// 40 inputs zero-padded to 64), then every wave runs tiles of 32 pairs
+// through the four layers on its own, looping over tiles with a grid stride.
+// Between layers a tile's activations live in the wave's LDS tile
+// ([32][128] BF16); each layer's 16 x 16 output blocks are finished in
+// registers (bias, GELU, BF16 rounding) and written back.  Operand layout
+// of the instruction: lane l supplies row l % 16 of A and column l % 16 of B,
+// each as the 8 consecutive k of k-group l / 16 (the same group for A and
+// B), and receives D[4 (l / 16) + i][l % 16], i = 0..3.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kIW = 4;        // waves per workgroup
+constexpr int kTP = 32;       // pairs per wave tile (two 16-row blocks)
+constexpr int kS1 = 64 + 8;   // LDS row stride (BF16 elements) of W1
+constexpr int kSH = 128 + 8;  // LDS row stride of W2, W3, W4 and of the activation tile
+
+__device__ __forceinline__ uint16_t bf16_bits(float x) { return (uint16_t)(__float_as_uint(bf16_round(x)) >> 16); }
+
+// 8 consecutive BF16 values (16-byte aligned) as one MFMA operand
+__device__ __forceinline__ bf16x8_t ld_frag(const uint16_t* p) {
+    return __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(p));
+}
+
+// acc[mt][nt] = sum over KS k-steps of 32: A block mt (rows of the tile) times
+// W^T block nt (W rows 16 nt .. 16 nt + 15, row stride ws in LDS)
+template <int KS, int NT>
+__device__ __forceinline__ void mfma_layer(const bf16x8_t (&a)[2][KS], const uint16_t* W, int ws, int lane,
+                                           f32x4_t (&acc)[2][NT]) {
+    const int r16 = lane & 15, kg = lane >> 4;
 #pragma unroll
-            for (int q = 0; q < 32; ++q) acc[q] = 0.f;
-            const uint16_t* w = Ws[l] + (size_t)o * nin[l];
-            for (int i = 0; i < nin[l]; ++i) {
-                const float wi = bf16_to_f(w[i]);
+    for (int nt = 0; nt < NT; ++nt) {
+        acc[0][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        acc[1][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int q = 0; q < 32; ++q) acc[q] = fmaf(wi, h[cur][half * 32 + q][i], acc[q]);
-            }
-            const float bb = bs[l][o];
-#pragma unroll
-            for (int q = 0; q < 32; ++q) {
-                const float z = acc[q] + bb;
-                if (l < 3) {
-                    h[cur ^ 1][half * 32 + q][o] = bf16_round(gelu_f(z));
-                } else {
-                    const int64_t p = p0 + half * 32 + q;
-                    if (p < n) out[p * 16 + o] = z;
-                }
-            }
+        for (int ks = 0; ks < KS; ++ks) {
+            const bf16x8_t b = ld_frag(W + (16 * nt + r16) * ws + 32 * ks + 8 * kg);
+            acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][ks], b, acc[0][nt], 0, 0, 0);
+            acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][ks], b, acc[1][nt], 0, 0, 0);
         }
-        __syncthreads();
-        cur ^= 1;
+    }
+}
+
+// hidden activations of a tile: H[row][n] = bf16(gelu(acc + b[n]))
+__device__ __forceinline__ void store_hidden(const f32x4_t (&acc)[2][8], const float* __restrict__ b, uint16_t* H,
+                                             int lane) {
+    const int r16 = lane & 15, kg = lane >> 4;
+#pragma unroll
+    for (int nt = 0; nt < 8; ++nt) {
+        const float bb = b[16 * nt + r16];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                H[(16 * mt + 4 * kg + i) * kSH + 16 * nt + r16] = bf16_bits(gelu_f(acc[mt][nt][i] + bb));
+    }
+}
+
+__device__ __forceinline__ void load_hidden(const uint16_t* H, int lane, bf16x8_t (&a)[2][4]) {
+    const int r16 = lane & 15, kg = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) a[mt][ks] = ld_frag(H + (16 * mt + r16) * kSH + 32 * ks + 8 * kg);
+}
+
+__global__ __launch_bounds__(kIW * 64) void infer_mfma_kernel(int64_t n, const uint16_t* __restrict__ Wbf,
+                                                               const float* __restrict__ params,
+                                                               const float* __restrict__ feat,
+                                                               float* __restrict__ out) {
+    __shared__ __align__(16) uint16_t W1s[128 * kS1];
+    __shared__ __align__(16) uint16_t W2s[128 * kSH];
+    __shared__ __align__(16) uint16_t W3s[128 * kSH];
+    __shared__ __align__(16) uint16_t W4s[16 * kSH];
+    __shared__ __align__(16) uint16_t Hs[kIW][kTP * kSH];
+    // offsets of the flat parameter layout (W1, b1, W2, b2, W3, b3, W4, b4)
+    constexpr size_t oW1 = 0, ob1 = oW1 + 128 * 40, oW2 = ob1 + 128, ob2 = oW2 + 128 * 128, oW3 = ob2 + 128,
+                     ob3 = oW3 + 128 * 128, oW4 = ob3 + 128, ob4 = oW4 + 16 * 128;
+    for (int e = threadIdx.x; e < 128 * 64; e += blockDim.x) {
+        const int r = e >> 6, c = e & 63;
+        W1s[r * kS1 + c] = (c < 40) ? Wbf[oW1 + r * 40 + c] : (uint16_t)0;
+    }
+    for (int e = threadIdx.x; e < 128 * 128; e += blockDim.x) {
+        const int r = e >> 7, c = e & 127;
+        W2s[r * kSH + c] = Wbf[oW2 + e];
+        W3s[r * kSH + c] = Wbf[oW3 + e];
+    }
+    for (int e = threadIdx.x; e < 16 * 128; e += blockDim.x) W4s[(e >> 7) * kSH + (e & 127)] = Wbf[oW4 + e];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r16 = lane & 15, kg = lane >> 4;
+    uint16_t* H = Hs[w];
+    const int64_t n_tiles = (n + kTP - 1) / kTP;
+    for (int64_t t = (int64_t)blockIdx.x * kIW + w; t < n_tiles; t += (int64_t)gridDim.x * kIW) {
+        const int64_t p0 = t * kTP;
+        f32x4_t acc[2][8];
+        {
+            // layer 1 operands: the BF16-rounded features (k >= 40 and pairs past n are zero)
+            bf16x8_t a[2][2];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    const int64_t p = p0 + 16 * mt + r16;
+                    const int k0 = 32 * ks + 8 * kg;
+                    uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                    if (p < n && k0 < 40) {
+                        const float4 f0 = *reinterpret_cast<const float4*>(feat + p * 40 + k0);
+                        const float4 f1 = *reinterpret_cast<const float4*>(feat + p * 40 + k0 + 4);
+                        v[0] = bf16_bits(f0.x); v[1] = bf16_bits(f0.y); v[2] = bf16_bits(f0.z); v[3] = bf16_bits(f0.w);
+                        v[4] = bf16_bits(f1.x); v[5] = bf16_bits(f1.y); v[6] = bf16_bits(f1.z); v[7] = bf16_bits(f1.w);
+                    }
+                    a[mt][ks] = __builtin_bit_cast(bf16x8_t, v);
+                }
+            mfma_layer<2, 8>(a, W1s, kS1, lane, acc);
+        }
+        // the wave's own tile: order its LDS writes and reads (lanes exchange rows through it)
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        store_hidden(acc, params + ob1, H, lane);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        for (int l = 0; l < 2; ++l) {
+            bf16x8_t a[2][4];
+            load_hidden(H, lane, a);
+            mfma_layer<4, 8>(a, l == 0 ? W2s : W3s, kSH, lane, acc);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            store_hidden(acc, params + (l == 0 ? ob2 : ob3), H, lane);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        }
+        bf16x8_t a[2][4];
+        load_hidden(H, lane, a);
+        f32x4_t o[2][1];
+        mfma_layer<4, 1>(a, W4s, kSH, lane, o);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        const float bb = params[ob4 + r16];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t p = p0 + 16 * mt + 4 * kg + i;
+                if (p < n) out[p * 16 + r16] = o[mt][0][i] + bb;
+            }
     }
 }
 
 void launch_infer_bf16(int64_t n, const uint16_t* Wbf, const float* params, const float* feat, float* out,
                        hipStream_t st) {
     if (n == 0) return;
-    // offsets of the flat parameter layout
-    const size_t oW1 = 0, ob1 = oW1 + 128 * 40, oW2 = ob1 + 128, ob2 = oW2 + 128 * 128, oW3 = ob2 + 128,
-                 ob3 = oW3 + 128 * 128, oW4 = ob3 + 128, ob4 = oW4 + 16 * 128;
-    hipLaunchKernelGGL(infer_bf16_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, n, Wbf + oW1,
-                       params + ob1, Wbf + oW2, params + ob2, Wbf + oW3, params + ob3, Wbf + oW4, params + ob4, feat,
-                       out);
+    int dev = 0, n_cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t n_tiles = (n + kTP - 1) / kTP;
+    // one workgroup per CU holds the 127 KB of LDS; more would wait for it
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_tiles + kIW - 1) / kIW, n_cu));
+    hipLaunchKernelGGL(infer_mfma_kernel, dim3(grid), dim3(kIW * 64), 0, st, n, Wbf, params, feat, out);
 }
 
 // Assemble M on B's pattern (internal layout, FP64) from the upper-pair blocks:
