@@ -273,7 +273,9 @@ struct Rich {
     int d = 2;
     double g0 = 0;
     std::vector<double> tau;  // steps k = 1 .. d-1
+    double reached = 0;       // 1/T_d(c/h): the residual factor the plan guarantees on [lo, hi]
 };
+constexpr int kRichMaxDegree = 400;
 
 // Richardson iteration for B v = s with the d roots of the Chebyshev
 // polynomial of the interval [lo, hi] as inverse step lengths,
@@ -289,13 +291,14 @@ Rich richardson_plan(double lo, double hi, double tol) {
     const double sigma = cen / half;
     double t0 = 1.0, t1 = sigma;
     int d = 1;
-    while (1.0 / t1 > tol && d < 400) {
+    while (1.0 / t1 > tol && d < kRichMaxDegree) {
         const double t2 = 2.0 * sigma * t1 - t0;
         t0 = t1;
         t1 = t2;
         ++d;
     }
     r.d = std::max(d, 3);  // a first step, at least one middle or last step
+    r.reached = 1.0 / t1;
     const double pi = 3.14159265358979323846;
     std::vector<double> roots(r.d);
     for (int i = 0; i < r.d; ++i) roots[i] = cen + half * cos((2.0 * i + 1.0) * pi / (2.0 * r.d));
@@ -324,6 +327,17 @@ Rich richardson_plan(double lo, double hi, double tol) {
     r.g0 = 1.0 / ord[0];
     for (int k = 1; k < r.d; ++k) r.tau.push_back(1.0 / ord[k]);
     return r;
+}
+
+// A plan capped at kRichMaxDegree steps does not reach its tolerance: the
+// overlap solve would be less accurate than asked.  Refuse such solves.
+elses_status check_rich(elses_ctx ctx, const Rich& r, double tol, double lo, double hi) {
+    if (r.reached <= tol * (1.0 + 1e-12)) return ELSES_OK;
+    return set_err(ctx, ELSES_ERR_INVALID_ARG,
+                   "the overlap solve on B's interval [" + std::to_string(lo) + ", " + std::to_string(hi) +
+                       "] would need more than " + std::to_string(kRichMaxDegree) +
+                       " Richardson steps to reach " + std::to_string(tol) + " (it reaches " +
+                       std::to_string(r.reached) + ")");
 }
 
 }  // namespace
@@ -1352,6 +1366,8 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
     // FP64: one Richardson solve to inner_tol.  Mixed: two FP32 rounds (the
     // solve, then the solve of the FP64 residual), each to sqrt(inner_tol).
     const Rich rich = richardson_plan(mat->b_lo, mat->b_hi, mixed ? std::sqrt(o.inner_tol) : o.inner_tol);
+    if (check_rich(ctx, rich, mixed ? std::sqrt(o.inner_tol) : o.inner_tol, mat->b_lo, mat->b_hi) != ELSES_OK)
+        return ELSES_ERR_INVALID_ARG;
 
     // host-side pattern offsets
     std::vector<int64_t> row_off(n_cols + 1, 0);
@@ -1851,6 +1867,8 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
     if (traces_out) traces_out[0] = traces_out[1] = 0.0;
     const bool mixed = o.use_mixed != 0;
     const Rich rich = richardson_plan(mat->b_lo, mat->b_hi, mixed ? std::sqrt(o.inner_tol) : o.inner_tol);
+    if (check_rich(ctx, rich, mixed ? std::sqrt(o.inner_tol) : o.inner_tol, mat->b_lo, mat->b_hi) != ELSES_OK)
+        return ELSES_ERR_INVALID_ARG;
     // one launch per vector-width group: LDS of its largest iterate, resident workgroups
     size_t glds[3] = {0, 0, 0};
     int gwg[3] = {0, 0, 0};
@@ -2586,6 +2604,7 @@ elses_status elses_spai_targets(elses_ctx ctx, elses_mat mat, float* target, flo
         DevPool pool;
         const DevPairs D = upload_pairs(pool, make_pairs(h), st);
         const Rich rich = richardson_plan(mat->b_lo, mat->b_hi, 1e-13);
+        if (check_rich(ctx, rich, 1e-13, mat->b_lo, mat->b_hi) != ELSES_OK) return ELSES_ERR_INVALID_ARG;
         constexpr int kChunk = 1024;
         const size_t vsz = (size_t)h.M * kChunk;
         double* S = pool.get<double>(vsz);
@@ -2880,6 +2899,7 @@ elses_status elses_overlap_solve(elses_ctx ctx, elses_mat mat, const double* M_v
             bracket_out[1] = hi;
         }
         const Rich rich = richardson_plan(lo, hi, tol);
+        if (check_rich(ctx, rich, tol, lo, hi) != ELSES_OK) return ELSES_ERR_INVALID_ARG;
         const size_t vsz = (size_t)M * nvec;
         double* Z = pool.get<double>(vsz);
         double* Xa = pool.get<double>(vsz);
@@ -3189,6 +3209,7 @@ elses_status arnoldi_core(elses_ctx ctx, elses_mat mat, const elses_regions_s* r
     const int n_ch = (int)ch_r0.size();
     const int Kmax = 4 * nu + 4;
     const Rich rich = richardson_plan(mat->b_lo, mat->b_hi, inner_tol);
+    if (check_rich(ctx, rich, inner_tol, mat->b_lo, mat->b_hi) != ELSES_OK) return ELSES_ERR_INVALID_ARG;
     // pattern of each column (rows in the matrix of the passes)
     std::vector<int64_t> row_off(n_cols + 1, 0);
     if (rp) {

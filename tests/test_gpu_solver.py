@@ -155,6 +155,27 @@ def test_density_matrix_traces_closed_form(el, ctx):
     assert np.abs(ct[:, 0] - tb).max() <= 1e-8 * np.abs(tb).max()
 
 
+def test_overlap_interval_beyond_the_richardson_cap_is_refused(el, ctx):
+    """An SPD overlap with eigenvalues 0.0201 .. 1: its widened interval (2 % of the width
+    on each side, about [4.8e-4, 1.02]) needs about 700 steps of the overlap solve's
+    Chebyshev-Richardson plan to reach 1e-13 (R4), beyond the 400-step cap: the solve is
+    refused with what it would reach, instead of returning results of an overlap solve
+    less accurate than inner_tol."""
+    n_at = 6
+    n_orb = np.array([1] * n_at, np.int8)
+    rp = np.arange(n_at + 1, dtype=np.int64)
+    bc = np.arange(n_at, dtype=np.int32)
+    Av = np.linspace(-0.5, 0.5, n_at)
+    Bv = np.array([0.0201, 0.3, 0.5, 0.7, 0.9, 1.0])
+    mat = el.Matrix(ctx, n_orb, rp, bc, Av, Bv)
+    z = synth.shift_grid(4, eta=0.05)
+    lo, hi = mat.b_interval
+    assert 0.0 < lo < 1e-3 and hi > 1.0
+    with pytest.raises(el.ElsesError) as e:
+        el.shifted_solve(ctx, mat, np.arange(n_at, dtype=np.int32), z, tol=1e-8)
+    assert "Richardson steps" in str(e.value)
+
+
 def test_diagonal_pencil_one_iteration(el, ctx):
     """A, B diagonal (only on-site blocks): x = e_j / (z B_jj - A_jj) after one step."""
     n_at = 10
