@@ -235,3 +235,103 @@ def test_compact_invalid_arguments(el, ctx, box):
         el.Regions(ctx, mat, [carbon], [5.0], orb_mask=[0b10000])  # selects no orbital
     ok = el.Regions(ctx, mat, [hydrogen], [5.0], orb_mask=[0b1])
     assert ok.n_cols == 1
+
+
+def test_compact_edge_cases(el, ctx, box):
+    """Degenerate and extreme inputs of the compact path against exact answers.
+
+    - Regions holding only their centre atom (radius below the shortest pair distance,
+      1 A): the Krylov space of a 1- or 4-orbital pencil is exhausted within its size, the
+      process stops at the breakdown (R5b) and x must equal the dense solve of the carved
+      pencil; one slice of 64 positions holds the 1 or 4 real rows.
+    - One shift (K = 1) and the largest accepted count (K = 256).
+    - A region larger than the periodic box: the whole system, equal to the global solve.
+    - Column widths 1, 2 and 4 (orbital masks) and regions of very different size in one
+      launch.
+    - No regions, or K outside [1, 256], are refused."""
+    s, mat, _ = box
+    carbons = np.nonzero(s.n_orb == 4)[0]
+    hyd = np.nonzero(s.n_orb == 1)[0]
+    # single-atom regions: dense comparison of full vectors, FP64 audit
+    centres = np.sort(np.array([carbons[5], hyd[7], hyd[8]])).astype(np.int32)
+    reg = el.Regions(ctx, mat, centres, np.full(3, 0.5))
+    assert sorted(reg.region_orbitals.tolist()) == [1, 1, 4]
+    z = synth.shift_grid(8)
+    K = len(z)
+    out = el.region_solve(ctx, reg, z, tol=1e-10, full=True, audit=True)
+    xf = out["x"].cpu().numpy()
+    assert np.all(out["resid"].cpu().numpy() <= 1e-10)
+    assert np.all(out["iters"].cpu().numpy() <= 4)
+    for c in range(reg.n_cols):
+        r = reg.col_region[c]
+        Ar, Br, loc = carved(s, centres[r], 0.5)
+        m = Ar.n
+        j = int(reg.cols[c])
+        e = np.zeros(m)
+        e[loc[j]] = 1.0
+        xv = xf[reg.full_off[c] * K:reg.full_off[c + 1] * K].reshape(K, m)
+        for k in range(K):
+            xd = np.linalg.solve(z[k] * Br.dense() - Ar.dense(), e)
+            assert np.linalg.norm(xv[k] - xd) <= 1e-12 * np.linalg.norm(xd), (c, k)
+    # K = 1 and K = 256 on the same ragged region set (radii 2.5 .. 7 A), against the oracle
+    rng = np.random.default_rng(81)
+    centres = np.sort(rng.choice(s.n_atoms, size=10, replace=False)).astype(np.int32)
+    radii = rng.uniform(2.5, 7.0, size=10)
+    reg = el.Regions(ctx, mat, centres, radii)
+    B = oracle.to_csr(s, "B")
+    for K in (1, 256):
+        z = synth.shift_grid(K)
+        out = el.region_solve(ctx, reg, z, tol=1e-9)
+        assert np.all(out["resid"].cpu().numpy() <= 1e-9)
+        xg = out["x"].cpu().numpy()
+        for c in range(0, reg.n_cols, 3):
+            r = reg.col_region[c]
+            Ar, Br, loc = carved(s, centres[r], radii[r])
+            j = int(reg.cols[c])
+            ref = oracle.shifted_solve(Ar, Br, np.array([loc[j]], np.int32), z, tol=1e-11, full=True,
+                                       true_residual=False)
+            rows = B.ci[B.rp[j]:B.rp[j + 1]]
+            xr = np.array([[ref.x[0, k, loc[int(i)]] if int(i) in loc else 0.0 for i in rows] for k in range(K)])
+            blk = xg[reg.pat_off[c] * K:reg.pat_off[c + 1] * K].reshape(K, -1)
+            assert np.abs(blk - xr).max() <= 1e-8 * np.abs(xr).max(), (K, c)
+    # the whole box as one region (radius beyond the box), a carbon centre with all four
+    # columns, against the global solve of the same columns
+    c0 = int(carbons[11])
+    whole = el.Regions(ctx, mat, [c0], [1000.0])
+    assert whole.region_orbitals[0] == s.M and whole.n_cols == 4
+    z = synth.shift_grid(16)
+    K = len(z)
+    a = el.region_solve(ctx, whole, z, tol=1e-10)
+    g = el.shifted_solve(ctx, mat, whole.cols, z, tol=1e-10)
+    xa, xg = a["x"].cpu().numpy(), g["x"].cpu().numpy()
+    assert np.array_equal(np.asarray(g["pat_off"]), whole.pat_off)
+    assert np.abs(xa - xg).max() <= 1e-8 * np.abs(xg).max()
+    # widths 1, 2 and 4 in one launch, with a tiny and a large region
+    centres = np.sort(np.array([carbons[20], carbons[21], carbons[22], hyd[30], hyd[31]])).astype(np.int32)
+    masks = {int(carbons[20]): 0b0001, int(carbons[21]): 0b0110, int(carbons[22]): 0b1111, int(hyd[30]): 1,
+             int(hyd[31]): 1}
+    radii = {int(carbons[20]): 6.5, int(carbons[21]): 3.0, int(carbons[22]): 5.0, int(hyd[30]): 0.5,
+             int(hyd[31]): 7.0}
+    mk = np.array([masks[int(c)] for c in centres], np.uint8)
+    rd = np.array([radii[int(c)] for c in centres])
+    reg = el.Regions(ctx, mat, centres, rd, orb_mask=mk)
+    assert reg.n_cols == 1 + 2 + 4 + 1 + 1
+    z = synth.shift_grid(12)
+    K = len(z)
+    out = el.region_solve(ctx, reg, z, tol=1e-10)
+    xg = out["x"].cpu().numpy()
+    for c in range(reg.n_cols):
+        r = reg.col_region[c]
+        Ar, Br, loc = carved(s, centres[r], rd[r])
+        j = int(reg.cols[c])
+        ref = oracle.shifted_solve(Ar, Br, np.array([loc[j]], np.int32), z, tol=1e-11, full=True,
+                                   true_residual=False)
+        rows = B.ci[B.rp[j]:B.rp[j + 1]]
+        xr = np.array([[ref.x[0, k, loc[int(i)]] if int(i) in loc else 0.0 for i in rows] for k in range(K)])
+        blk = xg[reg.pat_off[c] * K:reg.pat_off[c + 1] * K].reshape(K, -1)
+        assert np.abs(blk - xr).max() <= 1e-8 * np.abs(xr).max(), c
+    # refusals
+    with pytest.raises(el.ElsesError):
+        el.Regions(ctx, mat, np.zeros(0, np.int32), np.zeros(0))
+    with pytest.raises(el.ElsesError):
+        el.region_solve(ctx, reg, synth.shift_grid(257))
