@@ -126,11 +126,15 @@ typedef struct {
                          /* c % audit_every == 0 are also carried on every row of their     */
                          /* region and their resid_out entries receive the recomputed FP64  */
                          /* true residual instead of the estimate; 0 (default) = none       */
-    int32_t precond;     /* compact region sets: 1 = overlap solves by conjugate gradients  */
-                         /* preconditioned with the learned M of elses_mat_set_preconditioner */
-                         /* (the set must be created after it); a region whose M fails      */
-                         /* (a non-positive curvature, or inner_max steps without reaching  */
-                         /* inner_tol) falls back to the plain iteration; default 0         */
+    int32_t precond;     /* 1 = overlap solves preconditioned with the learned M of          */
+                         /* elses_mat_set_preconditioner; default 0.  Compact region sets   */
+                         /* (created after it): conjugate gradients with M; a region whose  */
+                         /* M fails (a non-positive curvature, or inner_max steps without   */
+                         /* reaching inner_tol) falls back to the plain iteration.  Global  */
+                         /* solves (FP64 only, no graph): Richardson steps                  */
+                         /* x <- x + tau_k M (s - B x) with the Chebyshev roots of M B's    */
+                         /* interval; a matrix whose M is not SPD runs the plain steps      */
+                         /* (one fallback counted).  Tile region sets: INVALID_ARG.         */
     int32_t inner_max;   /* preconditioned CG steps per solve before the fallback; 200      */
 } elses_opts;
 
@@ -435,14 +439,19 @@ elses_status elses_spai_apply(elses_ctx ctx, elses_mat mat, const float *params,
  * the assembly of M ~ B^{-1} on B's pattern (diagonal blocks symmetrised),
  * and keeps M with the matrix.  Region sets created afterwards carry M's
  * values with A and B (FP64, and FP32 for ELSES_MIXED), and their solves
- * with opts->precond use it.  params = NULL removes M.  Needs atom positions.
+ * with opts->precond use it; global solves with opts->precond use the device
+ * copy of M kept here and the spectral interval of M B estimated here, once
+ * (Lanczos in the B inner product; a non-positive lower end marks M as not
+ * SPD).  params = NULL removes M.  Needs atom positions.
  * Errors: ELSES_ERR_INVALID_ARG for a non-finite network output. */
 elses_status elses_mat_set_preconditioner(elses_ctx ctx, elses_mat mat, const float *params, int32_t bf16);
-/* Work of the last compact region solve on this context: sparse products
- * launched (A, B and M products, summed over the regions; per region one
- * product serves all of its columns) and the number of regions whose
- * preconditioned overlap solve fell back to the plain iteration (HOST
- * outputs, each may be NULL). */
+/* Work of the last solve on this context.  Compact region solves: sparse
+ * products launched (A, B and M products, summed over the regions; per region
+ * one product serves all of its columns) and the number of regions whose
+ * preconditioned overlap solve fell back to the plain iteration.  Global
+ * solves: products 0 (not counted), fallbacks 1 if opts->precond was asked
+ * for and the matrix's M is not SPD, else 0.  (HOST outputs, each may be
+ * NULL.) */
 elses_status elses_ctx_solve_counts(elses_ctx ctx, int64_t *products, int64_t *fallbacks);
 /* Overlap solve x = p(B) s for nvec right-hand sides (DEVICE double
  * [M][nvec], nvec a multiple of 64) to relative residual tol by Richardson

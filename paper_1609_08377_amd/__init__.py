@@ -272,7 +272,7 @@ def _variant(v) -> int:
 
 
 def make_opts(tol=1e-8, max_outer=20000, inner_tol=1e-13, full=False, slots=0, mixed=False, audit=False,
-              variant="auto", graph=False) -> Opts:
+              variant="auto", graph=False, precond=False) -> Opts:
     o = Opts()
     lib().elses_opts_default(ctypes.byref(o))
     o.tol = tol
@@ -284,6 +284,7 @@ def make_opts(tol=1e-8, max_outer=20000, inner_tol=1e-13, full=False, slots=0, m
     o.audit = 1 if audit else 0
     o.variant = _variant(variant)
     o.graph = 1 if graph else 0
+    o.precond = 1 if precond else 0
     return o
 
 
@@ -294,7 +295,7 @@ def _shifts_ri(shifts) -> np.ndarray:
 
 def shifted_solve(ctx: Context, mat: Matrix, cols, shifts, *, tol=1e-8, max_outer=20000, inner_tol=1e-13,
                   full=False, slots=0, mixed=False, audit=False, want_x=True, allow_not_converged=False,
-                  variant="auto", graph=False):
+                  variant="auto", graph=False, precond=False):
     """(z_k B - A) x = e_j for j in cols and every shift; returns torch tensors on the device."""
     torch = _torch()
     cols = np.ascontiguousarray(cols, dtype=np.int32)
@@ -311,7 +312,7 @@ def shifted_solve(ctx: Context, mat: Matrix, cols, shifts, *, tol=1e-8, max_oute
     x = torch.empty(2 * nx, dtype=torch.float64, device=dev) if want_x else None
     iters = torch.empty(nc, dtype=torch.int32, device=dev)
     resid = torch.empty(nc * K, dtype=torch.float64, device=dev)
-    opts = make_opts(tol, max_outer, inner_tol, full, slots, mixed, audit, variant, graph)
+    opts = make_opts(tol, max_outer, inner_tol, full, slots, mixed, audit, variant, graph, precond)
     st = lib().elses_shifted_solve(ctx._h, mat._h, nc, _np_ptr(cols), K, _np_ptr(z), ctypes.byref(opts),
                                    _dev_ptr(x), _dev_ptr(iters), _dev_ptr(resid))
     ctx.check(st, allow_warn=allow_not_converged)
@@ -324,7 +325,8 @@ def shifted_solve(ctx: Context, mat: Matrix, cols, shifts, *, tol=1e-8, max_oute
 
 
 def density_matrix(ctx: Context, mat: Matrix, cols, shifts, c, *, tol=1e-8, max_outer=20000, inner_tol=1e-13,
-                   slots=0, mixed=False, want_x=False, allow_not_converged=False, variant="auto", graph=False):
+                   slots=0, mixed=False, want_x=False, allow_not_converged=False, variant="auto", graph=False,
+                   precond=False):
     """rho_ij = sum_k Im(c_k x_{j,k,i}) on the pattern, plus the traces Tr[rho B], Tr[rho A] over cols."""
     torch = _torch()
     cols = np.ascontiguousarray(cols, dtype=np.int32)
@@ -342,7 +344,7 @@ def density_matrix(ctx: Context, mat: Matrix, cols, shifts, c, *, tol=1e-8, max_
     iters = torch.empty(nc, dtype=torch.int32, device=dev)
     resid = torch.empty(nc * K, dtype=torch.float64, device=dev)
     traces = np.zeros(2)
-    opts = make_opts(tol, max_outer, inner_tol, False, slots, mixed, False, variant, graph)
+    opts = make_opts(tol, max_outer, inner_tol, False, slots, mixed, False, variant, graph, precond)
     st = lib().elses_density_matrix(ctx._h, mat._h, nc, _np_ptr(cols), K, _np_ptr(z), _np_ptr(cw),
                                     ctypes.byref(opts), _dev_ptr(rho), _np_ptr(traces), _dev_ptr(col_tr),
                                     _dev_ptr(x), _dev_ptr(iters), _dev_ptr(resid))

@@ -402,7 +402,7 @@ void elses_mat_destroy(elses_mat m) {
     if (!m) return;
     DevMatrix& d = m->d;
     void* ptrs[] = {d.atom_off, d.orb_atom, d.brow, d.bsplit, d.borb, d.voff, d.asc_borb,
-                    d.asc_n,    d.asc_voff, d.A,    d.B,      d.A32,  d.B32};
+                    d.asc_n,    d.asc_voff, d.A,    d.B,      d.A32,  d.B32, m->M_dev};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& C : d.cl) {
@@ -1327,6 +1327,22 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
             seen[cols[c]] = 1;
         }
     }
+    const bool want_pre = o.precond != 0;
+    if (want_pre) {
+        if (rp)
+            return set_err(ctx, ELSES_ERR_INVALID_ARG,
+                           "the learned preconditioner runs in global solves and compact region sets, not in tiles");
+        if (o.use_mixed)
+            return set_err(ctx, ELSES_ERR_INVALID_ARG, "the preconditioned global solve runs in FP64 (use_mixed = 0)");
+        if (o.graph)
+            return set_err(ctx, ELSES_ERR_INVALID_ARG, "graph replay is not available with the preconditioned solve");
+        if (!mat->M_dev)
+            return set_err(ctx, ELSES_ERR_INVALID_ARG, "precond needs elses_mat_set_preconditioner first");
+    }
+    // M not SPD on the matrix (its M B interval has no positive lower end): the plain overlap solve
+    const bool pre = want_pre && mat->mb_spd;
+    ctx->last_products = 0;
+    ctx->last_fallbacks = (want_pre && !pre) ? 1 : 0;
     if (traces_out) traces_out[0] = traces_out[1] = 0.0;
     if (n_cols == 0) return ELSES_OK;
 
@@ -1365,8 +1381,10 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
     const int rmax = full ? M : h.pmax;
     // FP64: one Richardson solve to inner_tol.  Mixed: two FP32 rounds (the
     // solve, then the solve of the FP64 residual), each to sqrt(inner_tol).
-    const Rich rich = richardson_plan(mat->b_lo, mat->b_hi, mixed ? std::sqrt(o.inner_tol) : o.inner_tol);
-    if (check_rich(ctx, rich, mixed ? std::sqrt(o.inner_tol) : o.inner_tol, mat->b_lo, mat->b_hi) != ELSES_OK)
+    // the polynomial on B's interval, or with M on the interval of M B (x <- x + tau_k M (s - B x))
+    const double ilo = pre ? mat->mb_lo : mat->b_lo, ihi = pre ? mat->mb_hi : mat->b_hi;
+    const Rich rich = richardson_plan(ilo, ihi, mixed ? std::sqrt(o.inner_tol) : o.inner_tol);
+    if (check_rich(ctx, rich, mixed ? std::sqrt(o.inner_tol) : o.inner_tol, ilo, ihi) != ELSES_OK)
         return ELSES_ERR_INVALID_ARG;
 
     // host-side pattern offsets
@@ -1393,6 +1411,9 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
             buf[i] = pool.get<double>(vsz);
             HCHECK(hipMemsetAsync(buf[i], 0, vsz * sizeof(double), st));
         }
+        // the preconditioned steps' residual and M-product blocks
+        double* Rpre = pre ? pool.get<double>(vsz) : nullptr;
+        double* Qpre = pre ? pool.get<double>(vsz) : nullptr;
         float* buf32[6] = {};
         if (mixed)
             for (int i = 0; i < 6; ++i) {
@@ -1616,7 +1637,27 @@ elses_status solve_core(elses_ctx ctx, elses_mat mat, int n_cols, const int32_t*
                 pa.vals32 = valsB32;
                 pa.Tn = Tn;
                 double* vout = nullptr;
-                if (!mixed) {
+                if (pre) {
+                    // s = s' - alpha t_n into F1; x_1 = g0 M s, then
+                    // x_{k+1} = x_k + tau_k M (s - B x_k), k = 1 .. d-1; v.s and s.s partials
+                    const int64_t nv = (int64_t)M * vw;
+                    launch_overlap_start(M, vw, Tp, Tn, alpha, inv_beta, row_tile, 0.0, F1, F2, nullptr, nullptr,
+                                         st);
+                    launch_spmm_generic(gd, mat->M_dev, ld, ld, F1, Qpre, st);
+                    launch_axpby(nv, 0.0, nullptr, rich.g0, Qpre, F2, st);
+                    double* xcur = F2;
+                    double* xoth = Tp;
+                    for (int k = 1; k < rich.d; ++k) {
+                        launch_spmm_generic(gd, gd.B, ld, ld, xcur, Rpre, st);
+                        launch_axpby(nv, 1.0, F1, -1.0, Rpre, Rpre, st);
+                        launch_spmm_generic(gd, mat->M_dev, ld, ld, Rpre, Qpre, st);
+                        launch_axpby(nv, 1.0, xcur, rich.tau[k - 1], Qpre, xoth, st);
+                        std::swap(xcur, xoth);
+                    }
+                    launch_dots2_partial(M, ld, n_groups, xcur, F1, part0, part1, st);
+                    vout = xcur;
+                    F2 = xoth;
+                } else if (!mixed) {
                     // s = s' - alpha t_n into F1, x_1 = g0 s into F2; then steps 1 .. d-1
                     launch_overlap_start(M, vw, Tp, Tn, alpha, inv_beta, row_tile, rich.g0, F1, F2, nullptr,
                                          nullptr, st);
@@ -2562,6 +2603,72 @@ double* richardson_solve(const DevMatrix& d, const Rich& rich, int nvec, const d
 
 }  // namespace
 
+// Interval of the spectrum of M B (M the learned preconditioner, values in the
+// internal layout): Lanczos in the B inner product, where M B is self-adjoint,
+// widened like B's own interval.  M B has a positive spectrum iff M is SPD;
+// returns false when the lower end is not positive.
+bool mb_interval(elses_mat mat, const double* M_vals, DevPool& pool, hipStream_t st, double& lo, double& hi) {
+    const DevMatrix& d = mat->d;
+    const int M = d.M;
+
+    // spectral interval of M B: Lanczos in the B inner product (M B is
+    // self-adjoint there); M B has positive spectrum iff M is SPD
+    double* v = pool.get<double>(M);
+    double* u = pool.get<double>(M);
+    double* vp = pool.get<double>(M);
+    double* w = pool.get<double>(M);
+    double* uw = pool.get<double>(M);
+    double* junk = pool.get<double>(M);
+    const int nbl = std::min(256, (M + 255) / 256);
+    double* part = pool.get<double>(nbl);
+    std::vector<double> hv(M), hp(nbl);
+    uint64_t r = 0x9E3779B97F4A7C15ULL;
+    for (int i = 0; i < M; ++i) {
+        r ^= r << 13;
+        r ^= r >> 7;
+        r ^= r << 17;
+        hv[i] = (double)(r >> 11) / 9007199254740992.0 - 0.5;
+    }
+    auto dotdev = [&](const double* a, const double* b) {
+        launch_dot_partial(a, b, M, part, nbl, st);
+        HCHECK(hipMemcpyAsync(hp.data(), part, sizeof(double) * nbl, hipMemcpyDeviceToHost, st));
+        HCHECK(hipStreamSynchronize(st));
+        double t = 0;
+        for (double q : hp) t += q;
+        return t;
+    };
+    HCHECK(hipMemcpyAsync(v, hv.data(), sizeof(double) * M, hipMemcpyHostToDevice, st));
+    HCHECK(hipMemsetAsync(vp, 0, sizeof(double) * M, st));
+    launch_spmm_generic(d, d.B, 1, 1, v, u, st);
+    const double n0 = std::sqrt(dotdev(v, u));
+    launch_lanczos_shift(junk, v, v, 1.0 / n0, M, st);
+    launch_lanczos_shift(junk, u, u, 1.0 / n0, M, st);
+    std::vector<double> ta, tb;
+    double bprev = 0.0;
+    const int steps = std::min(M, 60);
+    for (int k = 0; k < steps; ++k) {
+        launch_spmm_generic(d, M_vals, 1, 1, u, w, st);  // w = M B v
+        const double al = dotdev(u, w);
+        launch_lanczos_orth(w, v, vp, al, bprev, M, st);
+        launch_spmm_generic(d, d.B, 1, 1, w, uw, st);
+        const double bb2 = dotdev(w, uw);
+        ta.push_back(al);
+        if (k + 1 == steps || !(bb2 > 1e-24 * al * al)) break;
+        const double bb = std::sqrt(bb2);
+        tb.push_back(bb);
+        launch_lanczos_shift(vp, v, w, 1.0 / bb, M, st);
+        launch_lanczos_shift(junk, u, uw, 1.0 / bb, M, st);
+        bprev = bb;
+    }
+    tb.resize(ta.size() - 1);
+    const double tmin = tri_eig(ta, tb, 0), tmax = tri_eig(ta, tb, (int)ta.size() - 1);
+    const double width = tmax - tmin;
+    lo = tmin - 0.02 * width - 1e-3 * std::fabs(tmin);
+    hi = tmax + 0.02 * width + 1e-3 * std::fabs(tmax);
+    return (lo > 0.0) && std::isfinite(hi);
+
+}
+
 extern "C" {
 
 elses_status elses_spai_pairs(elses_mat mat, int64_t* n_pairs, int32_t* pairs) {
@@ -2779,8 +2886,15 @@ elses_status elses_spai_apply(elses_ctx ctx, elses_mat mat, const float* params,
 elses_status elses_mat_set_preconditioner(elses_ctx ctx, elses_mat mat, const float* params, int32_t bf16) {
     if (!ctx || !mat) return ELSES_ERR_INVALID_ARG;
     HostMatrix& h = mat->h;
+    auto drop_device_copy = [&]() {
+        if (mat->M_dev) (void)hipFree(mat->M_dev);
+        mat->M_dev = nullptr;
+        mat->mb_spd = false;
+        mat->mb_lo = mat->mb_hi = 0.0;
+    };
     if (!params) {
         h.M_in.clear();
+        drop_device_copy();
         return ELSES_OK;
     }
     if (h.n_orb.empty()) return set_err(ctx, ELSES_ERR_INVALID_ARG, "the preconditioner needs a caller-created matrix");
@@ -2796,7 +2910,19 @@ elses_status elses_mat_set_preconditioner(elses_ctx ctx, elses_mat mat, const fl
         if (st != ELSES_OK) return st;
         HCHECK(hipMemcpy(Mi.data(), Mv, sizeof(double) * nnz, hipMemcpyDeviceToHost));
         HCHECK(hipMemcpy(asc_voff.data(), mat->d.asc_voff, sizeof(int64_t) * nnzb, hipMemcpyDeviceToHost));
+        for (int64_t e = 0; e < nnz; ++e)
+            if (!std::isfinite(Mi[e])) return set_err(ctx, ELSES_ERR_INVALID_ARG, "the network produced a non-finite M");
+        // the device copy for the global solves and the interval of M B, once
+        drop_device_copy();
+        double lo = 0.0, hi = 0.0;
+        const bool spd = mb_interval(mat, Mv, pool, ctx->stream, lo, hi);
+        HCHECK(hipMalloc((void**)&mat->M_dev, sizeof(double) * nnz));
+        HCHECK(hipMemcpy(mat->M_dev, Mv, sizeof(double) * nnz, hipMemcpyDeviceToDevice));
+        mat->mb_spd = spd;
+        mat->mb_lo = lo;
+        mat->mb_hi = hi;
     } catch (const HipFail& f) {
+        drop_device_copy();
         return hip_err(ctx, f);
     }
     std::vector<double> Min(nnz);
@@ -2833,66 +2959,10 @@ elses_status elses_overlap_solve(elses_ctx ctx, elses_mat mat, const double* M_v
         DevPool pool;
         double lo = mat->b_lo, hi = mat->b_hi;
         bool pre = M_vals != nullptr;
-        if (pre) {
-            // spectral interval of M B: Lanczos in the B inner product (M B is
-            // self-adjoint there); M B has positive spectrum iff M is SPD
-            double* v = pool.get<double>(M);
-            double* u = pool.get<double>(M);
-            double* vp = pool.get<double>(M);
-            double* w = pool.get<double>(M);
-            double* uw = pool.get<double>(M);
-            double* junk = pool.get<double>(M);
-            const int nbl = std::min(256, (M + 255) / 256);
-            double* part = pool.get<double>(nbl);
-            std::vector<double> hv(M), hp(nbl);
-            uint64_t r = 0x9E3779B97F4A7C15ULL;
-            for (int i = 0; i < M; ++i) {
-                r ^= r << 13;
-                r ^= r >> 7;
-                r ^= r << 17;
-                hv[i] = (double)(r >> 11) / 9007199254740992.0 - 0.5;
-            }
-            auto dotdev = [&](const double* a, const double* b) {
-                launch_dot_partial(a, b, M, part, nbl, st);
-                HCHECK(hipMemcpyAsync(hp.data(), part, sizeof(double) * nbl, hipMemcpyDeviceToHost, st));
-                HCHECK(hipStreamSynchronize(st));
-                double t = 0;
-                for (double q : hp) t += q;
-                return t;
-            };
-            HCHECK(hipMemcpyAsync(v, hv.data(), sizeof(double) * M, hipMemcpyHostToDevice, st));
-            HCHECK(hipMemsetAsync(vp, 0, sizeof(double) * M, st));
-            launch_spmm_generic(d, d.B, 1, 1, v, u, st);
-            const double n0 = std::sqrt(dotdev(v, u));
-            launch_lanczos_shift(junk, v, v, 1.0 / n0, M, st);
-            launch_lanczos_shift(junk, u, u, 1.0 / n0, M, st);
-            std::vector<double> ta, tb;
-            double bprev = 0.0;
-            const int steps = std::min(M, 60);
-            for (int k = 0; k < steps; ++k) {
-                launch_spmm_generic(d, M_vals, 1, 1, u, w, st);  // w = M B v
-                const double al = dotdev(u, w);
-                launch_lanczos_orth(w, v, vp, al, bprev, M, st);
-                launch_spmm_generic(d, d.B, 1, 1, w, uw, st);
-                const double bb2 = dotdev(w, uw);
-                ta.push_back(al);
-                if (k + 1 == steps || !(bb2 > 1e-24 * al * al)) break;
-                const double bb = std::sqrt(bb2);
-                tb.push_back(bb);
-                launch_lanczos_shift(vp, v, w, 1.0 / bb, M, st);
-                launch_lanczos_shift(junk, u, uw, 1.0 / bb, M, st);
-                bprev = bb;
-            }
-            tb.resize(ta.size() - 1);
-            const double tmin = tri_eig(ta, tb, 0), tmax = tri_eig(ta, tb, (int)ta.size() - 1);
-            const double width = tmax - tmin;
-            lo = tmin - 0.02 * width - 1e-3 * std::fabs(tmin);
-            hi = tmax + 0.02 * width + 1e-3 * std::fabs(tmax);
-            if (!(lo > 0.0) || !std::isfinite(hi)) {
-                pre = false;  // M is not SPD: fall back to the plain overlap solve
-                lo = mat->b_lo;
-                hi = mat->b_hi;
-            }
+        if (pre && !mb_interval(mat, M_vals, pool, st, lo, hi)) {
+            pre = false;  // M is not SPD: fall back to the plain overlap solve
+            lo = mat->b_lo;
+            hi = mat->b_hi;
         }
         if (bracket_out) {
             bracket_out[0] = lo;

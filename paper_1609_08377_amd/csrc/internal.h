@@ -117,6 +117,11 @@ struct elses_mat_s {
     elses::HostMatrix h;
     elses::DevMatrix d;
     double b_lo = 0, b_hi = 0;  // interval enclosing the spectrum of B
+    // learned preconditioner (elses_mat_set_preconditioner): M in the internal
+    // value layout (device, FP64), the interval of M B, and whether M is SPD
+    double* M_dev = nullptr;
+    double mb_lo = 0, mb_hi = 0;
+    bool mb_spd = false;
     // autotuned pass variant and slot count per precision (0 FP64, 1 mixed);
     // slots 0: not tuned
     int tuned_variant[2] = {0, 0};
@@ -294,6 +299,12 @@ void launch_reweight(int n_cols, int K, const double *cw, const int64_t *pat_off
 
 // Partial dot products (deterministic two-stage): out[b] = sum over block b
 void launch_dot_partial(const double *a, const double *b, int n, double *part, int nblocks, hipStream_t st);
+// out = a x + b y over n values (x may be null when a == 0)
+void launch_axpby(int64_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t st);
+// per column c of [M][ld] blocks v, s: part0[g][c] = sum of v s and part1[g][c] = sum of s s
+// over the rows of chunk g (n_groups equal chunks, fixed order)
+void launch_dots2_partial(int M, int ld, int n_groups, const double *v, const double *s, double *part0,
+                          double *part1, hipStream_t st);
 
 // Learned SPAI (spai.hip): features, exact-inverse targets, FP32 training,
 // BF16 inference, assembly of M on B's pattern.

@@ -330,6 +330,42 @@ void launch_spmm_generic(const DevMatrix& m, const double* vals, int nvec, int l
                        m.orb_atom, m.brow, m.bsplit, m.borb, m.voff, vals, m.M, nvec, ld, x, y);
 }
 
+__global__ void axpby_kernel(int64_t n, double a, const double* __restrict__ x, double b,
+                             const double* __restrict__ y, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double t = b * y[i];
+    out[i] = (a != 0.0) ? fma(a, x[i], t) : t;
+}
+
+void launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(axpby_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, x, b, y, out);
+}
+
+__global__ void dots2_partial_kernel(int M, int ld, int n_groups, const double* __restrict__ v,
+                                     const double* __restrict__ s, double* __restrict__ part0,
+                                     double* __restrict__ part1) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y;
+    if (c >= ld) return;
+    const int r0 = (int)((int64_t)M * g / n_groups), r1 = (int)((int64_t)M * (g + 1) / n_groups);
+    double vs = 0.0, ss = 0.0;
+    for (int r = r0; r < r1; ++r) {
+        const double sv = s[(size_t)r * ld + c];
+        vs = fma(v[(size_t)r * ld + c], sv, vs);
+        ss = fma(sv, sv, ss);
+    }
+    part0[(size_t)g * ld + c] = vs;
+    part1[(size_t)g * ld + c] = ss;
+}
+
+void launch_dots2_partial(int M, int ld, int n_groups, const double* v, const double* s, double* part0,
+                          double* part1, hipStream_t st) {
+    hipLaunchKernelGGL(dots2_partial_kernel, dim3((unsigned)((ld + 255) / 256), (unsigned)n_groups), dim3(256), 0,
+                       st, M, ld, n_groups, v, s, part0, part1);
+}
+
 // ||e_j - (z_k B - A) x||_2 for full-mode solutions x_full [n_cols][K][M] complex,
 // one workgroup per (column, shift); FP64 arithmetic on the stored values
 // (FP64, or the FP32 values of a mixed-precision matrix upcast exactly).

@@ -205,9 +205,51 @@ def test_preconditioned_region_solves(el, ctx, trained):
             assert np.abs(blk - xr).max() <= (1e-8 if not mixed else 5e-7) * np.abs(xr).max(), (precision, c)
 
 
+def test_preconditioned_global_solves(el, ctx, trained):
+    """The learned M in the global path (FP64): shifted solves and the density matrix of an
+    unseen box with every overlap solve run as Richardson steps x <- x + tau_k M (s - B x)
+    on the interval of M B, against the oracle (shifted COCG with CG overlap solves, tol
+    1e-11, and its density assembly) and against the plain solve; mixed precision and
+    graph replay are refused with M."""
+    theta = trained[0]
+    s = synth.make_system(300, 4343)
+    mat = el.Matrix.from_system(ctx, s)
+    el.set_preconditioner(ctx, mat, theta, bf16=True)
+    z = synth.shift_grid(16)
+    K = len(z)
+    cols = np.arange(0, s.M, 5, dtype=np.int32)
+    plain = el.shifted_solve(ctx, mat, cols, z, tol=1e-10)
+    pre = el.shifted_solve(ctx, mat, cols, z, tol=1e-10, precond=True)
+    _, fb = el.solve_counts(ctx)
+    assert fb == 0
+    assert np.all(pre["resid"].cpu().numpy() <= 1e-10)
+    A, B = oracle.to_csr(s, "A"), oracle.to_csr(s, "B")
+    ref = oracle.shifted_solve(A, B, cols, z, tol=1e-11, full=False, true_residual=False)
+    xp, xq = plain["x"].cpu().numpy(), pre["x"].cpu().numpy()
+    assert np.abs(xq - xp).max() <= 1e-8 * np.abs(xp).max()
+    for c in range(len(cols)):
+        p0, p1 = int(ref.pat_off[c]), int(ref.pat_off[c + 1])
+        xr = ref.x[p0 * K:p1 * K].reshape(K, -1)
+        assert np.abs(xq[p0 * K:p1 * K].reshape(K, -1) - xr).max() <= 1e-8 * np.abs(xr).max(), c
+    cw = oracle.fermi_weights(z, mu=0.0, tau=0.02)
+    d = el.density_matrix(ctx, mat, cols, z, cw, tol=1e-10, precond=True)
+    rho_r, trB, trA = oracle.density_from_x(B, A, cols, ref.x, ref.pat_off, cw)
+    assert np.abs(d["rho"].cpu().numpy() - rho_r).max() <= 1e-8 * np.abs(rho_r).max()
+    ctr = d["col_traces"].cpu().numpy()
+    assert np.abs(ctr[:, 0] - trB).max() <= 1e-8 * np.abs(trB).max()
+    assert np.abs(ctr[:, 1] - trA).max() <= 1e-8 * np.abs(trA).max()
+    with pytest.raises(el.ElsesError):
+        el.shifted_solve(ctx, mat, cols, z, precond=True, graph=True)
+    m32 = el.Matrix.from_system(ctx, s, precision="mixed")
+    el.set_preconditioner(ctx, m32, theta, bf16=True)
+    with pytest.raises(el.ElsesError):
+        el.shifted_solve(ctx, m32, cols, z, mixed=True, precond=True)
+
+
 def test_preconditioner_fallback(el, ctx):
     """An indefinite M (a network whose output is minus the identity blocks on every pair) is judged by
-    CG's curvature test: every region falls back to the plain iteration and the answers are unchanged."""
+    CG's curvature test: every region falls back to the plain iteration and the answers are unchanged;
+    in the global path the interval of M B has no positive lower end and the plain steps run."""
     s = synth.make_system(600, 4242)
     mat = el.Matrix.from_system(ctx, s)
     theta = np.zeros(mlp.N_PARAM, dtype=np.float32)
@@ -223,6 +265,15 @@ def test_preconditioner_fallback(el, ctx):
     _, fb = el.solve_counts(ctx)
     assert fb == centres.size
     assert np.array_equal(plain["x"].cpu().numpy(), pre["x"].cpu().numpy())
+    # the global path: M B has no positive interval, the solve runs the plain steps
+    cols = np.arange(0, s.M, 37, dtype=np.int32)
+    gp = el.shifted_solve(ctx, mat, cols, z, tol=1e-10)
+    gq = el.shifted_solve(ctx, mat, cols, z, tol=1e-10, precond=True)
+    _, fb = el.solve_counts(ctx)
+    assert fb == 1
+    assert np.array_equal(gp["x"].cpu().numpy(), gq["x"].cpu().numpy())
     el.set_preconditioner(ctx, mat, None)
+    with pytest.raises(el.ElsesError):  # M removed: the global path refuses precond too
+        el.shifted_solve(ctx, mat, cols, z, precond=True)
     with pytest.raises(el.ElsesError):  # a set built without M cannot run the preconditioned path
         el.region_solve(ctx, el.Regions(ctx, mat, centres, radii), z, precond=True)
