@@ -1911,8 +1911,9 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
     if (check_rich(ctx, rich, mixed ? std::sqrt(o.inner_tol) : o.inner_tol, mat->b_lo, mat->b_hi) != ELSES_OK)
         return ELSES_ERR_INVALID_ARG;
     // one launch per vector-width group: LDS of its largest iterate, resident workgroups
+    // (two iterate buffers when that keeps as many workgroups resident as one)
     size_t glds[3] = {0, 0, 0};
-    int gwg[3] = {0, 0, 0};
+    int gwg[3] = {0, 0, 0}, ghalf[3] = {0, 0, 0};
     for (int g = 0; g < 3; ++g) {
         const int cnt = C.goff[g + 1] - C.goff[g];
         if (cnt == 0) continue;
@@ -1921,6 +1922,10 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         if (occ < 1)
             return set_err(ctx, ELSES_ERR_INVALID_ARG,
                            "the largest region's overlap iterate does not fit in LDS; use tile_width 64 or 128");
+        if (compact_occupancy(!mixed, C.gcw[g], precond, 2 * glds[g]) >= occ) {
+            ghalf[g] = C.gmaxP[g] * C.gcw[g];
+            glds[g] *= 2;
+        }
         gwg[g] = std::max(1, std::min(cnt, occ * ctx->n_cu));
     }
     // carried rows per column: the pattern, or every position of the region (full output, audits)
@@ -2097,6 +2102,7 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
             }
             a.order = C.d_order + C.goff[g];
             a.n_regions = cnt;
+            a.lds_half = ghalf[g];
             a.queue = counters + g;
             a.vec = vec_g[g];
             a.vec_stride = nblk * C.gmaxP[g] * C.gcw[g];

@@ -372,6 +372,8 @@ struct CompactArgs {
     int max_outer;
     int d;                        // Richardson degree (per round)
     const double* tau;            // [d-1] inverse Chebyshev roots (Leja order)
+    int lds_half;                 // > 0: a second LDS iterate buffer starts this many values after the
+                                  // first (Richardson steps ping-pong in LDS); 0: staged through vec
     double g0;
     double inner_tol;             // overlap solve tolerance (preconditioned CG: per round)
     int inner_max;                // preconditioned CG steps per round before the fallback

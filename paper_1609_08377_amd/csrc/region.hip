@@ -119,8 +119,9 @@ __device__ __forceinline__ void row_product(const uint16_t* __restrict__ ib, con
                                             int len, const TX* src, TA (&acc)[C]) {
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = TA(0);
+    const int main = len & ~15;
 #pragma unroll 16
-    for (int k = 0; k < len; ++k) {
+    for (int k = 0; k < main; ++k) {
         const uint32_t e = e0 + 64u * (uint32_t)k;
         const uint32_t j = ib[e];
         const TA v = static_cast<TA>(vb[e]);
@@ -128,6 +129,26 @@ __device__ __forceinline__ void row_product(const uint16_t* __restrict__ ib, con
         ldv<C>(src + j * (uint32_t)C, xv);
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = fma(v, static_cast<TA>(xv[c]), acc[c]);
+    }
+    if (main < len) {
+        // the last len - main (< 16) entries as one batch of loads; slots past
+        // the end re-read the last entry (a cache hit) with weight zero
+        uint32_t j[16];
+        TV v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const uint32_t e = e0 + 64u * (uint32_t)min(main + q, len - 1);
+            j[q] = ib[e];
+            v[q] = vb[e];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            TX xv[C];
+            ldv<C>(src + j[q] * (uint32_t)C, xv);
+            const TA w = (main + q < len) ? static_cast<TA>(v[q]) : TA(0);
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] = fma(w, static_cast<TA>(xv[c]), acc[c]);
+        }
     }
 }
 
@@ -163,7 +184,8 @@ __device__ __forceinline__ const TV* pick(const double* d, const float* f) {
 
 // One Richardson round X <- p(B) rhs:  x_1 = g0 rhs,
 // x_{k+1} = x_k + tau_k (rhs - B x_k), k = 1 .. d-1, with TV arithmetic.
-// rhs [P][C] (global, this lane's positions only), X [P][C] in LDS.  The new
+// rhs [P][C] (global, this lane's positions only), X [P][C] in LDS.  With a
+// second LDS buffer the steps ping-pong between the two; otherwise the new
 // iterate of a lane's rows goes through the per-workgroup block Xn (global,
 // this lane's positions only) until every gather of the old one is done.
 template <int C, typename TV>
@@ -179,6 +201,39 @@ __device__ __forceinline__ void richardson(const CompactArgs& a, const RView<TV>
         stv<C>(X + (size_t)pos * C, r);
     }
     __syncthreads();
+    if (a.lds_half > 0) {
+        // two LDS buffers: step k gathers from one and writes the other, so one
+        // barrier per step ends both the gathers and the writes
+        TV* cur = X;
+        TV* nxt = X + a.lds_half;
+        for (int k = 1; k < a.d; ++k) {
+            const TV tau = static_cast<TV>(a.tau[k - 1]);
+            for (int sl = w; sl < R.ns; sl += kRW) {
+                const int pos = sl * 64 + lane;
+                TV acc[C], r[C], xo[C], xn[C];
+                row_product<C>(R.idx, R.Bv, (uint32_t)(R.sent[sl] + lane), R.slen[sl], cur, acc);
+                ldv<C>(rhs + (size_t)pos * C, r);
+                ldv<C>(cur + (size_t)pos * C, xo);
+#pragma unroll
+                for (int c = 0; c < C; ++c) xn[c] = xo[c] + tau * (r[c] - acc[c]);
+                stv<C>(nxt + (size_t)pos * C, xn);
+            }
+            __syncthreads();
+            TV* t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        if (cur != X) {
+            for (int sl = w; sl < R.ns; sl += kRW) {
+                const int pos = sl * 64 + lane;
+                TV xn[C];
+                ldv<C>(cur + (size_t)pos * C, xn);
+                stv<C>(X + (size_t)pos * C, xn);
+            }
+            __syncthreads();
+        }
+        return;
+    }
     for (int k = 1; k < a.d; ++k) {
         const TV tau = static_cast<TV>(a.tau[k - 1]);
         for (int sl = w; sl < R.ns; sl += kRW) {
