@@ -1,0 +1,70 @@
+"""Build check of the compact region kernel's product loop schedule (CPU, hipcc).
+
+The solve streams every region's matrix once per sparse product, and a wave
+hides the memory latency only while the 16 index and 16 value loads of an
+unrolled batch of entries are all in flight before their gathers.  Under a
+tighter occupancy target the compiler has scheduled the same loop as load,
+wait, gather, wait, FMA for every entry (32 waits on vector memory per 16
+entries) and the solve ran 2.5x slower.  This compiles region.hip for gfx950
+to assembly and checks that the FP32 one-column kernel (the benchmark's) keeps
+its 16-deep product loops batched.
+"""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1609_08377_amd", "csrc")
+KERNEL = "_ZN5elses12_GLOBAL__N_114compact_kernelIfLi1ELi0EEEvNS_11CompactArgsE"
+
+
+def hipcc():
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if c and os.path.exists(c):
+            return c
+    return None
+
+
+def product_loops(asm: str, symbol: str):
+    """(global loads, LDS reads, vector-memory waits) of every loop of `symbol`
+    without a barrier that holds at least 32 global loads and 16 LDS reads."""
+    lines = asm.split("\n")
+    start = next(i for i, l in enumerate(lines) if l.startswith(symbol + ":"))
+    end = next(i for i in range(start, len(lines)) if lines[i].startswith(".Lfunc_end"))
+    body = lines[start:end]
+    labels = {}
+    for k, l in enumerate(body):
+        m = re.match(r"^(\.LBB\d+_\d+):", l)
+        if m:
+            labels[m.group(1)] = k
+    out = []
+    for k, l in enumerate(body):
+        m = re.search(r"s_c?branch\w*\s+(\.LBB\d+_\d+)", l)
+        if m and m.group(1) in labels and labels[m.group(1)] < k:
+            seg = body[labels[m.group(1)]:k + 1]
+            loads = sum("global_load" in x for x in seg)
+            lds = sum("ds_read" in x for x in seg)
+            if loads >= 32 and lds >= 16 and not any("s_barrier" in x for x in seg) and len(seg) < 400:
+                out.append((loads, lds, sum("s_waitcnt vmcnt" in x for x in seg)))
+    return out
+
+
+def test_product_loops_keep_their_loads_in_flight(tmp_path):
+    cc = hipcc()
+    if cc is None:
+        pytest.skip("hipcc not available")
+    out = tmp_path / "region.s"
+    cmd = [cc, "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", "-Wno-unused-command-line-argument", "-munsafe-fp-atomics",
+           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "--cuda-device-only", "-S",
+           os.path.join(CSRC, "region.hip"), "-o", str(out)]
+    subprocess.run(cmd, check=True, stdout=subprocess.PIPE, stderr=subprocess.PIPE, timeout=900)
+    loops = product_loops(out.read_text(), KERNEL)
+    assert loops, "no 16-deep product loop found in the FP32 one-column kernel"
+    # a serialised loop waits once per load (or more); a batched one issues its loads
+    # before the first wait and needs clearly fewer waits than loads
+    for loads, lds, waits in loops:
+        assert waits <= loads - 6, (loads, lds, waits)
