@@ -343,6 +343,14 @@ elses_status elses_regions_info(elses_regions reg, int32_t *n_cols, int32_t *n_t
 /* Region of each column (HOST int32 [n_cols], in the column order of
  * elses_regions_info). */
 elses_status elses_regions_columns(elses_regions reg, int32_t *col_region);
+/* Overlap interval of each region of a compact set (HOST double [n_regions]
+ * each): the extreme Ritz values of the region's B from 40 Lanczos steps at
+ * creation, widened by 2 % of the width and 1e-3 relative on each side and
+ * kept inside B's interval (a region's B is a principal submatrix of B:
+ * its spectrum lies inside B's, Cauchy interlacing).  Each region's overlap
+ * solves take the Chebyshev-Richardson plan of its own interval.  Tile sets:
+ * ELSES_ERR_INVALID_ARG. */
+elses_status elses_regions_overlap_intervals(elses_regions reg, double *lo, double *hi);
 /* Solve (z_k B_r - A_r) x = e_j for every column of every region and every
  * shift (HOST, Im z > 0), in pattern mode: x_out, rho_out, col_traces_out,
  * iters_out and resid_out are laid out as in elses_density_matrix for the

@@ -127,6 +127,8 @@ def lib():
         L.elses_regions_create_ex.restype = ctypes.c_int
         L.elses_regions_columns.argtypes = [P, P]
         L.elses_regions_columns.restype = ctypes.c_int
+        L.elses_regions_overlap_intervals.argtypes = [P, P, P]
+        L.elses_regions_overlap_intervals.restype = ctypes.c_int
         L.elses_mat_set_preconditioner.argtypes = [P, P, P, I32]
         L.elses_mat_set_preconditioner.restype = ctypes.c_int
         L.elses_ctx_solve_counts.argtypes = [P, P, P]
@@ -420,6 +422,13 @@ class Regions:
         ctx.check(lib().elses_regions_columns(h, _np_ptr(self.col_region)))
         # first entry of each column's block of full region vectors ([K][m_r] per column)
         self.full_off = np.concatenate([[0], np.cumsum(self.region_orbitals[self.col_region].astype(np.int64))])
+
+    def overlap_intervals(self):
+        """(lo, hi) per region of a compact set: the overlap interval its Richardson plan uses."""
+        lo = np.zeros(self.region_orbitals.shape[0])
+        hi = np.zeros_like(lo)
+        self.ctx.check(lib().elses_regions_overlap_intervals(self._h, _np_ptr(lo), _np_ptr(hi)))
+        return lo, hi
 
     def close(self):
         if getattr(self, "_h", None):

@@ -32,6 +32,37 @@
 namespace elses {
 void launch_lanczos_orth(double* w, const double* v, const double* u, double a, double b, int n, hipStream_t st);
 void launch_lanczos_shift(double* u, double* v, const double* w, double s, int n, hipStream_t st);
+// Smallest / largest eigenvalue of the symmetric tridiagonal (a, b) by
+// Sturm-sequence bisection.
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double x) {
+    int cnt = 0;
+    double d = 1.0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        const double bb = (i == 0) ? 0.0 : b[i - 1] * b[i - 1];
+        d = (a[i] - x) - (i == 0 ? 0.0 : bb / d);
+        if (d == 0.0) d = -1e-300;
+        if (d < 0) ++cnt;
+    }
+    return cnt;
+}
+
+double tri_eig(const std::vector<double>& a, const std::vector<double>& b, int idx) {
+    double lo = 1e300, hi = -1e300;
+    for (size_t i = 0; i < a.size(); ++i) {
+        const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < a.size() ? fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (sturm_count(a, b, mid) > idx)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 }  // namespace elses
 
 using namespace elses;
@@ -76,37 +107,6 @@ struct DevPool {
         for (void* p : ptrs) (void)hipFree(p);
     }
 };
-
-// Smallest / largest eigenvalue of the symmetric tridiagonal (a, b) by
-// Sturm-sequence bisection.
-int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double x) {
-    int cnt = 0;
-    double d = 1.0;
-    for (size_t i = 0; i < a.size(); ++i) {
-        const double bb = (i == 0) ? 0.0 : b[i - 1] * b[i - 1];
-        d = (a[i] - x) - (i == 0 ? 0.0 : bb / d);
-        if (d == 0.0) d = -1e-300;
-        if (d < 0) ++cnt;
-    }
-    return cnt;
-}
-
-double tri_eig(const std::vector<double>& a, const std::vector<double>& b, int idx) {
-    double lo = 1e300, hi = -1e300;
-    for (size_t i = 0; i < a.size(); ++i) {
-        const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < a.size() ? fabs(b[i]) : 0.0);
-        lo = std::min(lo, a[i] - r);
-        hi = std::max(hi, a[i] + r);
-    }
-    for (int it = 0; it < 200; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (sturm_count(a, b, mid) > idx)
-            hi = mid;
-        else
-            lo = mid;
-    }
-    return 0.5 * (lo + hi);
-}
 
 // Clusters of at most max_atoms consecutive atoms whose coupled orbitals
 // (the union over the cluster) fit in max_rows LDS rows.  Greedy in atom
@@ -873,6 +873,7 @@ struct elses_regions_s {
         std::vector<RegionDesc> reg;
         std::vector<int> col_region, region_nnz, order;
         std::vector<int64_t> region_ent;
+        std::vector<double> ritz_lo, ritz_hi;  // extreme Ritz values of each region's B
         // regions grouped by vector width (4, 2, 1): group g is order[goff[g] .. goff[g+1]);
         // one launch per group
         int goff[4] = {0, 0, 0, 0};
@@ -957,6 +958,8 @@ elses_status compact_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, con
     auto& C = P->cp;
     C.reg = H.reg;
     C.col_region = H.col_region;
+    C.ritz_lo = H.ritz_lo;
+    C.ritz_hi = H.ritz_hi;
     C.has32 = gm->precision == ELSES_MIXED;
     // per region: nonzeros (algorithmic bytes) and padded entries; lane-rows
     C.region_nnz.assign(n_regions, 0);
@@ -1865,6 +1868,15 @@ size_t round256(size_t b) { return (std::max<size_t>(b, 1) + 255) & ~(size_t)255
 // from it, the groups run one after another on the context stream with as
 // many workgroups as the arena holds, and no stream, event or allocation is
 // created.
+// Overlap interval of region r of a compact set: the extreme Ritz values of
+// its B widened like B's own interval (2 % of the width and 1e-3 relative on
+// each side) and kept inside B's interval.
+void region_interval(const elses_regions_s* rp, int r, double& lo, double& hi) {
+    const double tl = rp->cp.ritz_lo[r], th = rp->cp.ritz_hi[r], w = th - tl;
+    lo = std::max(rp->gm->b_lo, tl - 0.02 * w - 1e-3 * std::fabs(tl));
+    hi = std::min(rp->gm->b_hi, th + 0.02 * w + 1e-3 * std::fabs(th));
+}
+
 elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, const double* shifts, const double* cw,
                            const elses_opts* opts_in, double* x_out, int32_t* iters_out, double* resid_out,
                            double* rho_out, double* traces_out, double* col_traces_out, char* arena = nullptr,
@@ -1910,6 +1922,24 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
     const Rich rich = richardson_plan(mat->b_lo, mat->b_hi, mixed ? std::sqrt(o.inner_tol) : o.inner_tol);
     if (check_rich(ctx, rich, mixed ? std::sqrt(o.inner_tol) : o.inner_tol, mat->b_lo, mat->b_hi) != ELSES_OK)
         return ELSES_ERR_INVALID_ARG;
+    // the Richardson plan of each region on its own overlap interval: the
+    // extreme Ritz values of its B, widened like B's own interval and kept
+    // inside it (a region's B is a principal submatrix of B, so its spectrum
+    // lies inside B's); never a higher degree than B's plan
+    const int n_reg = rp->n_regions;
+    const double round_tol = mixed ? std::sqrt(o.inner_tol) : o.inner_tol;
+    const int tau_stride = std::max(1, rich.d - 1);
+    std::vector<int> h_rdeg(n_reg);
+    std::vector<double> h_rg0(n_reg), h_rtau((size_t)n_reg * tau_stride, 0.0);
+    for (int r = 0; r < n_reg; ++r) {
+        double lo = 0.0, hi = 0.0;
+        region_interval(rp, r, lo, hi);
+        Rich pr = (lo > 0.0 && hi > lo) ? richardson_plan(lo, hi, round_tol) : rich;
+        if (pr.d > rich.d || pr.reached > round_tol * (1.0 + 1e-12)) pr = rich;
+        h_rdeg[r] = pr.d;
+        h_rg0[r] = pr.g0;
+        std::copy(pr.tau.begin(), pr.tau.end(), h_rtau.begin() + (size_t)r * tau_stride);
+    }
     // one launch per vector-width group: LDS of its largest iterate, resident workgroups
     // (two iterate buffers when that keeps as many workgroups resident as one)
     size_t glds[3] = {0, 0, 0};
@@ -1946,7 +1976,8 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         // fixed part of the arena, in the order and rounding of the gets below
         size_t fixed = round256(sizeof(int64_t) * (n_cols + 1)) * 2 + round256(sizeof(int) * n_cols) +
                        round256(sizeof(double) * 2 * K) * (density ? 2 : 1) +
-                       round256(sizeof(double) * std::max<size_t>(1, rich.tau.size())) +
+                       round256(sizeof(int) * n_reg) + round256(sizeof(double) * n_reg) +
+                       round256(sizeof(double) * n_reg * tau_stride) +
                        round256(sizeof(double) * n_cols * K * 2) * 2 + round256(sizeof(double) * n_cols * K) +
                        round256(sizeof(double) * n_cols * K * 4) + round256(sizeof(int) * n_cols * K) +
                        round256(sizeof(double) * carry_off[n_cols] * 2) * 2 + round256(sizeof(int) * 8) +
@@ -2029,11 +2060,16 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         a.cw = d_cw;
         a.tol = o.tol;
         a.max_outer = o.max_outer;
-        a.d = rich.d;
-        double* d_tau = pool.get<double>(std::max<size_t>(1, rich.tau.size()));
-        HCHECK(hipMemcpyAsync(d_tau, rich.tau.data(), sizeof(double) * rich.tau.size(), hipMemcpyHostToDevice, st));
-        a.tau = d_tau;
-        a.g0 = rich.g0;
+        int* d_rdeg = pool.get<int>(n_reg);
+        double* d_rg0 = pool.get<double>(n_reg);
+        double* d_rtau = pool.get<double>((size_t)n_reg * tau_stride);
+        HCHECK(hipMemcpyAsync(d_rdeg, h_rdeg.data(), sizeof(int) * n_reg, hipMemcpyHostToDevice, st));
+        HCHECK(hipMemcpyAsync(d_rg0, h_rg0.data(), sizeof(double) * n_reg, hipMemcpyHostToDevice, st));
+        HCHECK(hipMemcpyAsync(d_rtau, h_rtau.data(), sizeof(double) * h_rtau.size(), hipMemcpyHostToDevice, st));
+        a.rdeg = d_rdeg;
+        a.rg0 = d_rg0;
+        a.rtau = d_rtau;
+        a.tau_stride = tau_stride;
         a.eta = pool.get<double>((size_t)n_cols * K * 2);
         a.zeta = pool.get<double>((size_t)n_cols * K * 2);
         a.res = pool.get<double>((size_t)n_cols * K);
@@ -2138,7 +2174,6 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         std::vector<int32_t> it_h(n_cols);
         HCHECK(hipMemcpy(it_h.data(), iters, sizeof(int32_t) * n_cols, hipMemcpyDeviceToHost));
         const double vb = mixed ? 4.0 : 8.0;
-        const double products = mixed ? (2.0 * (rich.d - 1) + 1.0) : (double)(rich.d - 1);
         double gbytes[3] = {0, 0, 0}, gflops[3] = {0, 0, 0};
         int64_t outer = 0;
         for (int r = 0; r < rp->n_regions; ++r) {
@@ -2151,6 +2186,7 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
                 carried += (double)(carry_off[c + 1] - carry_off[c]);
             }
             const double nnz = (double)C.region_nnz[r];
+            const double products = mixed ? (2.0 * (h_rdeg[r] - 1) + 1.0) : (double)(h_rdeg[r] - 1);
             const double per_it = nnz * (2.0 + vb) * products + nnz * (2.0 + vb) + 64.0 * carried +
                                   18.0 * 8.0 * (double)D.m * D.cw;
             gbytes[g] += (n_it + 1) * per_it;
@@ -2386,6 +2422,12 @@ elses_status elses_regions_solve_noalloc(elses_ctx ctx, elses_regions reg, int32
 elses_status elses_regions_columns(elses_regions reg, int32_t* col_region) {
     if (!reg || !col_region) return ELSES_ERR_INVALID_ARG;
     std::copy(reg->cp.col_region.begin(), reg->cp.col_region.end(), col_region);
+    return ELSES_OK;
+}
+
+elses_status elses_regions_overlap_intervals(elses_regions reg, double* lo, double* hi) {
+    if (!reg || !lo || !hi || !reg->compact) return ELSES_ERR_INVALID_ARG;
+    for (int r = 0; r < reg->n_regions; ++r) region_interval(reg, r, lo[r], hi[r]);
     return ELSES_OK;
 }
 

@@ -370,11 +370,14 @@ struct CompactArgs {
     const double* cw;
     double tol;
     int max_outer;
-    int d;                        // Richardson degree (per round)
-    const double* tau;            // [d-1] inverse Chebyshev roots (Leja order)
+    // Richardson plan of each region (per round, on its own overlap interval):
+    // degree, first step, and the inverse roots of steps 1 .. d-1 at rtau[r * tau_stride]
+    const int* rdeg;
+    const double* rg0;
+    const double* rtau;
+    int tau_stride;
     int lds_half;                 // > 0: a second LDS iterate buffer starts this many values after the
                                   // first (Richardson steps ping-pong in LDS); 0: staged through vec
-    double g0;
     double inner_tol;             // overlap solve tolerance (preconditioned CG: per round)
     int inner_max;                // preconditioned CG steps per round before the fallback
     unsigned long long* products; // sparse products launched (A, B and M), summed over regions
@@ -400,6 +403,10 @@ void launch_compact(const CompactArgs& a, bool fp64, int cw, bool precond, int n
 // n ints set to zero by a kernel (no memset node, so the call can be captured)
 void launch_zero_ints(int* p, size_t n, hipStream_t st);
 
+// idx-th smallest eigenvalue of the symmetric tridiagonal matrix with
+// diagonal a and off-diagonal b (Sturm-sequence bisection).
+double tri_eig(const std::vector<double>& a, const std::vector<double>& b, int idx);
+
 // Host-side construction of the compact layout (region_host.hip).
 struct CompactHost {
     std::vector<RegionDesc> reg;
@@ -415,6 +422,7 @@ struct CompactHost {
     std::vector<double> pat_B, pat_A;
     std::vector<int> region_orbs;
     std::vector<int64_t> region_nnz;   // nonzeros of each region's matrices
+    std::vector<double> ritz_lo, ritz_hi;  // extreme Ritz values of each region's B (Lanczos)
     int max_slices = 0;
     int64_t useful = 0;
     size_t lds_fp64 = 0, lds_fp32 = 0;  // LDS of the largest region (P x cw values)

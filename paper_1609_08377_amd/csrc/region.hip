@@ -164,6 +164,10 @@ struct RView {
     const double* A64;        // entries: FP64 values (refinement and audits)
     const double* B64;
     const TV* Mv;             // entries: values of the learned preconditioner M (or null)
+    // the region's Richardson plan (per round): degree d, first step g0, inverse roots tau[0 .. d-2]
+    int d;
+    double g0;
+    const double* tau;
 };
 
 // Per-column scalars of the region being solved, in LDS (uniform values kept
@@ -191,7 +195,7 @@ __device__ __forceinline__ const TV* pick(const double* d, const float* f) {
 template <int C, typename TV>
 __device__ __forceinline__ void richardson(const CompactArgs& a, const RView<TV>& R, const TV* rhs, TV* X, TV* Xn) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const TV g0 = static_cast<TV>(a.g0);
+    const TV g0 = static_cast<TV>(R.g0);
     for (int sl = w; sl < R.ns; sl += kRW) {
         const int pos = sl * 64 + lane;
         TV r[C];
@@ -206,8 +210,8 @@ __device__ __forceinline__ void richardson(const CompactArgs& a, const RView<TV>
         // barrier per step ends both the gathers and the writes
         TV* cur = X;
         TV* nxt = X + a.lds_half;
-        for (int k = 1; k < a.d; ++k) {
-            const TV tau = static_cast<TV>(a.tau[k - 1]);
+        for (int k = 1; k < R.d; ++k) {
+            const TV tau = static_cast<TV>(R.tau[k - 1]);
             for (int sl = w; sl < R.ns; sl += kRW) {
                 const int pos = sl * 64 + lane;
                 TV acc[C], r[C], xo[C], xn[C];
@@ -234,8 +238,8 @@ __device__ __forceinline__ void richardson(const CompactArgs& a, const RView<TV>
         }
         return;
     }
-    for (int k = 1; k < a.d; ++k) {
-        const TV tau = static_cast<TV>(a.tau[k - 1]);
+    for (int k = 1; k < R.d; ++k) {
+        const TV tau = static_cast<TV>(R.tau[k - 1]);
         for (int sl = w; sl < R.ns; sl += kRW) {
             const int pos = sl * 64 + lane;
             TV acc[C], r[C], xo[C], xn[C];
@@ -453,7 +457,7 @@ __device__ __forceinline__ void overlap_round(const CompactArgs& a, const RView<
         }
     }
     richardson<C, TV>(a, R, rhs, X, Xn);
-    if (threadIdx.x == 0) atomicAdd(a.products, (unsigned long long)(a.d - 1));
+    if (threadIdx.x == 0) atomicAdd(a.products, (unsigned long long)(R.d - 1));
 }
 
 // v = p(B) s for the region's columns: S, V [P][C] FP64 (global); Rw scratch
@@ -557,7 +561,7 @@ __device__ __forceinline__ void audit_column(const CompactArgs& a, const RView<T
 
 
 template <int C, typename TV, int PC>
-__device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionDesc& D, double* vbase, TV* X,
+__device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionDesc& D, int ri, double* vbase, TV* X,
                                              double* red, ColState& cs) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int K = a.K;
@@ -566,6 +570,9 @@ __device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionD
     R.ns = D.nslice;
     R.P = D.nslice * 64;
     R.ncol = D.ncol;
+    R.d = a.rdeg[ri];
+    R.g0 = a.rg0[ri];
+    R.tau = a.rtau + (size_t)ri * a.tau_stride;
     R.slen = a.slice_len + D.slice0;
     R.sent = a.slice_ent + D.slice0;
     R.idx = a.idx + D.ent0;
@@ -906,8 +913,9 @@ __global__ __launch_bounds__(kRegThreads, 2) void compact_kernel(CompactArgs a) 
         const int r = s_r;
         __syncthreads();
         if (r >= a.n_regions) return;
-        const RegionDesc D = a.reg[a.order[r]];
-        solve_region<C, TV, PC>(a, D, vbase, X, red, cs);
+        const int ri = a.order[r];
+        const RegionDesc D = a.reg[ri];
+        solve_region<C, TV, PC>(a, D, ri, vbase, X, red, cs);
     }
 }
 

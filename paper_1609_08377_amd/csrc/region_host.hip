@@ -213,6 +213,8 @@ const char* build_compact(const HostMatrix& h, int n_regions, const int* centres
     out.pat_pos.assign(pat, -1);
     out.pat_B.assign(pat, 0.0);
     out.pat_A.assign(pat, 0.0);
+    out.ritz_lo.assign(n_regions, 0.0);
+    out.ritz_hi.assign(n_regions, 0.0);
     {
         int c = 0;
         for (int r = 0; r < n_regions; ++r)
@@ -285,6 +287,63 @@ const char* build_compact(const HostMatrix& h, int n_regions, const int* centres
             e_rel += (int64_t)len * 64;
         }
         if (e_rel != P.n_ent) bad.store(1);
+        // extreme Ritz values of the region's B: 40 Lanczos steps on the
+        // layout just built (FP64 values), from a fixed pseudo-random start on
+        // the region's rows (padding positions stay zero)
+        {
+            const int Pn = P.nslice * 64;
+            std::vector<double> v(Pn, 0.0), vp(Pn, 0.0), w(Pn, 0.0);
+            uint64_t xs = 0x9E3779B97F4A7C15ULL ^ ((uint64_t)(r + 1) * 0xD1B54A32D192ED03ULL);
+            double nrm = 0.0;
+            for (int p = 0; p < P.m; ++p) {
+                xs ^= xs << 13;
+                xs ^= xs >> 7;
+                xs ^= xs << 17;
+                v[p] = (double)(xs >> 11) / 9007199254740992.0 - 0.5;
+                nrm += v[p] * v[p];
+            }
+            nrm = std::sqrt(nrm);
+            for (int p = 0; p < P.m; ++p) v[p] /= nrm;
+            auto bprod = [&](const std::vector<double>& x, std::vector<double>& y) {
+                for (int s = 0; s < P.nslice; ++s) {
+                    const int len = out.slice_len[D.slice0 + s];
+                    const int64_t e0 = D.ent0 + out.slice_ent[D.slice0 + s];
+                    for (int l = 0; l < 64; ++l) {
+                        double acc = 0.0;
+                        for (int k = 0; k < len; ++k) {
+                            const int64_t e = e0 + (int64_t)k * 64 + l;
+                            acc += out.B64[e] * x[out.idx[e]];
+                        }
+                        y[64 * s + l] = acc;
+                    }
+                }
+            };
+            std::vector<double> ta, tb;
+            double bprev = 0.0;
+            const int steps = std::min(P.m, 40);
+            for (int k = 0; k < steps; ++k) {
+                bprod(v, w);
+                double al = 0.0;
+                for (int p = 0; p < Pn; ++p) al += v[p] * w[p];
+                double bb = 0.0;
+                for (int p = 0; p < Pn; ++p) {
+                    w[p] -= al * v[p] + bprev * vp[p];
+                    bb += w[p] * w[p];
+                }
+                bb = std::sqrt(bb);
+                ta.push_back(al);
+                if (k + 1 == steps || !(bb > 1e-12 * std::fabs(al))) break;
+                tb.push_back(bb);
+                for (int p = 0; p < Pn; ++p) {
+                    vp[p] = v[p];
+                    v[p] = w[p] / bb;
+                }
+                bprev = bb;
+            }
+            tb.resize(ta.size() - 1);
+            out.ritz_lo[r] = tri_eig(ta, tb, 0);
+            out.ritz_hi[r] = tri_eig(ta, tb, (int)ta.size() - 1);
+        }
         // columns and their patterns (the caller's pattern of column j: the
         // orbitals of the atoms coupled to j's atom, ascending)
         const int C = centres[r];

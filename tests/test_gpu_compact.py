@@ -335,3 +335,23 @@ def test_compact_edge_cases(el, ctx, box):
         el.Regions(ctx, mat, np.zeros(0, np.int32), np.zeros(0))
     with pytest.raises(el.ElsesError):
         el.region_solve(ctx, reg, synth.shift_grid(257))
+
+
+def test_region_overlap_intervals_enclose_spectra(el, ctx, box):
+    """Each compact region's overlap interval (the one its Chebyshev-Richardson plan uses:
+    extreme Ritz values of its B, widened) encloses the exact spectrum of the carved B_r
+    and lies inside B's interval (Cauchy interlacing); typical regions get a narrower
+    interval than B's, so a lower polynomial degree."""
+    s, mat, _ = box
+    centres, radii = sample(s, 24, 93, 2.0, 9.0)
+    reg = el.Regions(ctx, mat, centres, radii)
+    lo, hi = reg.overlap_intervals()
+    blo, bhi = mat.b_interval
+    widths = []
+    for r in range(len(centres)):
+        Ar, Br, loc = carved(s, centres[r], radii[r])
+        ev = np.linalg.eigvalsh(Br.dense())
+        assert blo <= lo[r] <= ev[0], (r, blo, lo[r], ev[0])
+        assert ev[-1] <= hi[r] <= bhi, (r, ev[-1], hi[r], bhi)
+        widths.append(hi[r] / lo[r])
+    assert np.median(widths) < bhi / blo
