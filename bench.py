@@ -505,6 +505,7 @@ def run_sampled(args):
     total, width = ctypes.c_int64(), ctypes.c_int32()
     lib.elses_ctx_pass_stats(ctx._h, ctypes.byref(launches), ctypes.byref(avg_us), ctypes.byref(nbytes),
                              ctypes.byref(flops), ctypes.byref(total), ctypes.byref(width))
+    idle_share, _ = el.region_idle(ctx)
     lib.elses_ctx_set_profiling(ctx._h, 0)
     iters = torch.cat(iters_all).cpu().numpy()
     value = n_solves / dt
@@ -543,6 +544,7 @@ def run_sampled(args):
                    "trace_rhoB_timed_columns": trace_b,
                    "sparse_products_per_region_iteration": round(products / max(1, region_iters(sets, iters_all, args,
                                                                                                   n_sets)), 2),
+                   "idle_workgroup_share": round(idle_share, 4),
                    "learned_preconditioner": precond, "preconditioner_fallbacks": fallbacks,
                    "system_generation_s": round(t_gen, 1), "matrix_upload_s": round(t_mat, 1),
                    "network_training_s": round(t_train, 1), "region_set_build_s": round(t_sets, 1)},

@@ -213,6 +213,13 @@ elses_status elses_density_matrix(elses_ctx ctx, elses_mat mat, int32_t n_cols, 
 elses_status elses_ctx_set_profiling(elses_ctx ctx, int32_t stride);
 elses_status elses_ctx_pass_stats(elses_ctx ctx, int64_t *launches, double *avg_us, double *bytes, double *flops,
                                   int64_t *total_passes, int32_t *slots);
+/* Load balance of the profiled compact region solves since the last
+ * elses_ctx_set_profiling: the mean over those solves of the share of
+ * resident workgroup time spent without a region, 1 - (sum of workgroup
+ * lifetimes) / (workgroups x span of the solve), from per-workgroup stamps
+ * of the device's constant-rate clock (the analogue of the paper's barrier
+ * time from load imbalance, Table II); solves = how many were measured. */
+elses_status elses_ctx_region_idle(elses_ctx ctx, double *idle_share, int64_t *solves);
 
 /*
  * Time `reps` back-to-back launches of one sparse pass on scratch blocks of

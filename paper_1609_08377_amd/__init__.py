@@ -129,6 +129,8 @@ def lib():
         L.elses_regions_columns.restype = ctypes.c_int
         L.elses_regions_overlap_intervals.argtypes = [P, P, P]
         L.elses_regions_overlap_intervals.restype = ctypes.c_int
+        L.elses_ctx_region_idle.argtypes = [P, P, P]
+        L.elses_ctx_region_idle.restype = ctypes.c_int
         L.elses_mat_set_preconditioner.argtypes = [P, P, P, I32]
         L.elses_mat_set_preconditioner.restype = ctypes.c_int
         L.elses_ctx_solve_counts.argtypes = [P, P, P]
@@ -445,6 +447,13 @@ class Regions:
 def set_preconditioner(ctx: Context, mat: Matrix, params=None, bf16: bool = True):
     """Keep the learned M (network params: FP32 device tensor, or None to remove it) with the matrix."""
     ctx.check(lib().elses_mat_set_preconditioner(ctx._h, mat._h, _dev_ptr(params), 1 if bf16 else 0))
+
+
+def region_idle(ctx: Context) -> tuple[float, int]:
+    """(mean idle share of resident workgroups, profiled compact solves measured) since profiling was set."""
+    v, n = ctypes.c_double(), ctypes.c_int64()
+    ctx.check(lib().elses_ctx_region_idle(ctx._h, ctypes.byref(v), ctypes.byref(n)))
+    return float(v.value), int(n.value)
 
 
 def solve_counts(ctx: Context) -> tuple[int, int]:

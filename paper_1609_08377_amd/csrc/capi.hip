@@ -2109,6 +2109,7 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         // each launch when profiling is enabled.
         hipEvent_t ev[3][2] = {};
         const bool timed = ctx->prof_stride > 0 && !noalloc;
+        unsigned long long* clk[3] = {nullptr, nullptr, nullptr};  // per-workgroup start / end stamps
         hipStream_t gst[3] = {st, st, st};
         hipStream_t own[3] = {nullptr, nullptr, nullptr};  // streams created here
         hipEvent_t ready = nullptr, gdone[3] = {};
@@ -2142,7 +2143,10 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
             a.queue = counters + g;
             a.vec = vec_g[g];
             a.vec_stride = nblk * C.gmaxP[g] * C.gcw[g];
+            a.wg_clock = nullptr;
             if (timed) {
+                clk[g] = pool.get<unsigned long long>(2 * (size_t)gwg[g]);
+                a.wg_clock = clk[g];
                 HCHECK(hipEventCreate(&ev[g][0]));
                 HCHECK(hipEventCreate(&ev[g][1]));
                 HCHECK(hipEventRecord(ev[g][0], gst[g]));
@@ -2222,6 +2226,26 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
                 ctx->prof_bytes = ctx->prof_bytes_acc / (double)ctx->prof_launches;
                 ctx->prof_flops = ctx->prof_flops_acc / (double)ctx->prof_launches;
                 ctx->prof_slots = C.gcw[gmost];
+                // idle share: 1 - (summed workgroup lifetimes) / (workgroups x span of the solve)
+                uint64_t t0 = ~0ull, t1 = 0;
+                double busy = 0.0, n_wg = 0.0;
+                std::vector<unsigned long long> hc;
+                for (int g = 0; g < 3; ++g) {
+                    if (!clk[g]) continue;
+                    hc.resize(2 * (size_t)gwg[g]);
+                    HCHECK(hipMemcpy(hc.data(), clk[g], sizeof(unsigned long long) * hc.size(),
+                                     hipMemcpyDeviceToHost));
+                    for (int w = 0; w < gwg[g]; ++w) {
+                        t0 = std::min<uint64_t>(t0, hc[2 * w]);
+                        t1 = std::max<uint64_t>(t1, hc[2 * w + 1]);
+                        busy += (double)(hc[2 * w + 1] - hc[2 * w]);
+                        n_wg += 1.0;
+                    }
+                }
+                if (t1 > t0 && n_wg > 0) {
+                    ctx->prof_idle_acc += 1.0 - busy / (n_wg * (double)(t1 - t0));
+                    ctx->prof_idle_n += 1;
+                }
             }
             for (auto& e : ev)
                 for (hipEvent_t x : e)
@@ -2265,6 +2289,8 @@ elses_status elses_ctx_set_profiling(elses_ctx ctx, int32_t stride) {
     ctx->prof_ms = 0.0;
     ctx->prof_bytes_acc = 0.0;
     ctx->prof_flops_acc = 0.0;
+    ctx->prof_idle_acc = 0.0;
+    ctx->prof_idle_n = 0;
     ctx->total_passes = 0;
     return ELSES_OK;
 }
@@ -2278,6 +2304,13 @@ elses_status elses_ctx_pass_stats(elses_ctx ctx, int64_t* launches, double* avg_
     if (flops) *flops = ctx->prof_flops;
     if (total_passes) *total_passes = ctx->total_passes;
     if (slots) *slots = ctx->prof_slots;
+    return ELSES_OK;
+}
+
+elses_status elses_ctx_region_idle(elses_ctx ctx, double* idle_share, int64_t* solves) {
+    if (!ctx) return ELSES_ERR_INVALID_ARG;
+    if (idle_share) *idle_share = ctx->prof_idle_n ? ctx->prof_idle_acc / (double)ctx->prof_idle_n : 0.0;
+    if (solves) *solves = ctx->prof_idle_n;
     return ELSES_OK;
 }
 

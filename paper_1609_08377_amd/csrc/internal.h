@@ -103,6 +103,9 @@ struct elses_ctx_s {
     double prof_flops = 0.0;
     double prof_bytes_acc = 0.0;  // compact region launches: sums over the timed launches
     double prof_flops_acc = 0.0;
+    // profiled compact solves: summed share of resident workgroup time without a region
+    double prof_idle_acc = 0.0;
+    int64_t prof_idle_n = 0;
     int64_t total_passes = 0;
     int prof_slots = 0;
     // last compact region solve: sparse products launched (A, B, M; summed over
@@ -388,6 +391,7 @@ struct CompactArgs {
     int* conv;                       // [n_cols][K] iteration of convergence, 0 running
     double *xs, *ps;                 // carried x and p (complex)
     int* queue;
+    unsigned long long* wg_clock;    // profiled launches: [n_wg][2] start and end stamps (wall clock), else null
     int* n_notconv;
     double* x_out;
     int* iters_out;

@@ -907,12 +907,16 @@ __global__ __launch_bounds__(kRegThreads, 2) void compact_kernel(CompactArgs a) 
     extern __shared__ __align__(16) unsigned char s_dyn[];
     TV* X = reinterpret_cast<TV*>(s_dyn);
     double* vbase = a.vec + (size_t)blockIdx.x * a.vec_stride;
+    if (a.wg_clock && threadIdx.x == 0) a.wg_clock[2 * blockIdx.x] = wall_clock64();
     for (;;) {
         if (threadIdx.x == 0) s_r = atomicAdd(a.queue, 1);
         __syncthreads();
         const int r = s_r;
         __syncthreads();
-        if (r >= a.n_regions) return;
+        if (r >= a.n_regions) {
+            if (a.wg_clock && threadIdx.x == 0) a.wg_clock[2 * blockIdx.x + 1] = wall_clock64();
+            return;
+        }
         const int ri = a.order[r];
         const RegionDesc D = a.reg[ri];
         solve_region<C, TV, PC>(a, D, ri, vbase, X, red, cs);
