@@ -1868,6 +1868,8 @@ size_t round256(size_t b) { return (std::max<size_t>(b, 1) + 255) & ~(size_t)255
 // from it, the groups run one after another on the context stream with as
 // many workgroups as the arena holds, and no stream, event or allocation is
 // created.
+constexpr int kRegionsPerCu = 1;  // resident workgroups per CU of a compact launch
+
 // Overlap interval of region r of a compact set: the extreme Ritz values of
 // its B widened like B's own interval (2 % of the width and 1e-3 relative on
 // each side) and kept inside B's interval.
@@ -1956,7 +1958,11 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
             ghalf[g] = C.gmaxP[g] * C.gcw[g];
             glds[g] *= 2;
         }
-        gwg[g] = std::max(1, std::min(cnt, occ * ctx->n_cu));
+        // at most one workgroup (one region) per CU: on the 10^6-atom benchmark the
+        // solve ran 9.9 s per step with 256 resident regions against 11.0 s with 512,
+        // with the same kernel; half as many resident region matrices stay in the
+        // last-level cache between their products
+        gwg[g] = std::max(1, std::min(cnt, std::min(occ, kRegionsPerCu) * ctx->n_cu));
     }
     // carried rows per column: the pattern, or every position of the region (full output, audits)
     std::vector<int> carry_full(n_cols, 0);
