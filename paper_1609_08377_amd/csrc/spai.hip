@@ -132,16 +132,29 @@ void launch_spai_targets(int64_t n, const int* pI, const int* pJ, const int* ato
 // ---------------------------------------------------------------------------
 
 // C(i, j) (=, or += when acc) sum_k A(i, k) B(k, j) with A(i, k) = A[i sa0 + k sa1],
-// B(k, j) = B[k sb0 + j sb1], C(i, j) = C[i sc0 + j].  64 x 64 tiles, K in steps
-// of 16 through LDS, 4 x 4 outputs per thread.
+// B(k, j) = B[k sb0 + j sb1], C(i, j) = C[i sc0 + j], on the matrix cores
+// (v_mfma_f32_16x16x4_f32, FP32 products and sums).  A workgroup of four
+// waves owns a 64 x 64 tile of C; K goes in steps of 16 through LDS (zero
+// outside the matrices); each wave computes a 32 x 32 quarter as 2 x 2
+// blocks of 16 x 16.  Operand layout of the instruction: lane l supplies
+// A(row l % 16, k l / 16) and B(k l / 16, column l % 16) and receives
+// C(4 (l / 16) + i, l % 16), i = 0..3.
+typedef float f32x4_mfma_t __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void gemm_kernel(int Mr, int N, int K, const float* __restrict__ A, int64_t sa0,
                                                    int64_t sa1, const float* __restrict__ B, int64_t sb0,
                                                    int64_t sb1, float* __restrict__ C, int64_t sc0, int acc) {
     __shared__ float As[16][68];
     __shared__ float Bs[16][68];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int wi = (w >> 1) * 32, wj = (w & 1) * 32;  // the wave's quarter of the tile
     const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-    float r[4][4] = {};
+    f32x4_mfma_t c[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) c[bi][bj] = f32x4_mfma_t{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < K; k0 += 16) {
         for (int e = threadIdx.x; e < 64 * 16; e += 256) {
             const int ii = e >> 4, kk = e & 15;
@@ -155,32 +168,29 @@ __global__ __launch_bounds__(256) void gemm_kernel(int Mr, int N, int K, const f
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            float a[4], b[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[q] = As[kk][ty * 4 + q];
-                b[q] = Bs[kk][tx * 4 + q];
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int w = 0; w < 4; ++w) r[q][w] = fmaf(a[q], b[w], r[q][w]);
+        for (int ks = 0; ks < 4; ++ks) {
+            const int kk = 4 * ks + kq;
+            const float a0 = As[kk][wi + r16], a1 = As[kk][wi + 16 + r16];
+            const float b0 = Bs[kk][wj + r16], b1 = Bs[kk][wj + 16 + r16];
+            c[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, c[0][0], 0, 0, 0);
+            c[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, c[0][1], 0, 0, 0);
+            c[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, c[1][0], 0, 0, 0);
+            c[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, c[1][1], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int gi = i0 + ty * 4 + q;
-        if (gi >= Mr) continue;
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const int gj = j0 + tx * 4 + w;
-            if (gj >= N) continue;
-            float* c = C + gi * sc0 + gj;
-            *c = acc ? *c + r[q][w] : r[q][w];
-        }
-    }
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gi = i0 + wi + 16 * bi + 4 * kq + q;
+                const int gj = j0 + wj + 16 * bj + r16;
+                if (gi >= Mr || gj >= N) continue;
+                float* out = C + gi * sc0 + gj;
+                *out = acc ? *out + c[bi][bj][q] : c[bi][bj][q];
+            }
 }
 
 void launch_gemm(int Mr, int N, int K, const float* A, int64_t sa0, int64_t sa1, const float* B, int64_t sb0,
