@@ -198,10 +198,12 @@ elses_status elses_density_matrix(elses_ctx ctx, elses_mat mat, int32_t n_cols, 
  * one solve counts as one launch from the first group's start to the last
  * group's end; bytes and flops are the means over the timed solves of the
  * algorithmic traffic of all groups: per outer step of each region its sparse
- * products (a 2-byte index plus the value, 4 or 8 bytes, per nonzero), the
- * carried x and p (read and written, 64 bytes per shift and row) and its
- * Lanczos vectors in scratch (18 x 8 bytes per row and column); slots = the
- * column width of the group that moved most bytes.
+ * products (the A product, the Richardson steps of the region's own plan and,
+ * in mixed precision, the refinement product; a 2-byte index plus the value,
+ * 4 or 8 bytes, per nonzero), the carried x and p (read and written, 64 bytes
+ * per shift and row) and its Lanczos vectors in scratch (18 x 8 bytes per
+ * row and column); slots = the column width of the group that moved most
+ * bytes.  A compact launch holds at most one workgroup (one region) per CU.
  * Multiple Arnoldi calls (elses_arnoldi, elses_regions_arnoldi) sample their
  * Gram-Schmidt update passes instead (every stride-th launch, one launch per
  * sample; block b subtracts the projections of two candidates on the 2b basis
@@ -312,11 +314,13 @@ elses_status elses_spmm(elses_ctx ctx, elses_mat mat, int which, int32_t variant
  *
  * Layouts (tile_width):
  *  0        compact (default): every region keeps its own sub-pencil (at most
- *           4096 orbitals per region); one persistent launch solves them,
- *           one workgroup per region at a time, taking regions from a device
- *           queue largest first, with every step of a region's solve (outer
- *           Lanczos steps, overlap solves, shift updates, density assembly)
- *           inside the launch;
+ *           8192 orbitals per region, and its overlap iterate must fit in LDS);
+ *           one persistent launch per column-width group solves them, one
+ *           workgroup per region at a time and at most one per CU, taking
+ *           regions from a device queue largest first, with every step of a
+ *           region's solve (outer Lanczos steps, overlap solves with the
+ *           Chebyshev-Richardson plan of the region's own overlap interval,
+ *           shift updates, density assembly) inside the launch;
  *  64, 128  tiles: consecutive regions (which should be spatial neighbours)
  *           are packed into tiles of tile_width column slots of one
  *           block-diagonal matrix that advance through one launch sequence
