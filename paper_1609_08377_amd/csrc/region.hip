@@ -9,7 +9,9 @@
 // assembly) without leaving the kernel; finished workgroups take the next
 // region from a largest-first device queue, so regions of uneven size and
 // iteration count do not wait for each other (the load imbalance the paper
-// measures as barrier time, Table II).
+// measures as barrier time, Table II).  The host launches at most one
+// workgroup per CU, and gives each region the Chebyshev-Richardson plan of
+// its own overlap interval (degree, first step and roots per region).
 //
 // Layout of one region (built on the host, see build_compact):
 //  - its m orbitals are permuted to positions 0..P-1 (P = 64 x slices), rows
@@ -23,11 +25,11 @@
 //  - every vector is [P][C] (C columns of the region side by side).
 //
 // Per workgroup, the iterate of the overlap solve lives in LDS (it is
-// gathered by every sparse product of the inner iteration); the Lanczos
-// vectors live in a per-workgroup scratch area in global memory (touched a
-// few times per outer step); a Richardson step writes the new iterate of a
-// lane's rows to a per-workgroup block of that area and copies it into LDS
-// after the barrier that ends the step's gathers.
+// gathered by every sparse product of the inner iteration): in two buffers
+// that the Richardson steps ping-pong between when both fit, else staged
+// through the scratch area at each step; the Lanczos vectors live in a
+// per-workgroup scratch area in global memory (touched a few times per
+// outer step).
 //
 // The outer method is the same as in the global solver (shift.hip): a
 // Lanczos process for B^{-1}A in the B inner product from B^{-1} e_j (Eqs.
