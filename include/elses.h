@@ -217,8 +217,9 @@ elses_status elses_ctx_pass_stats(elses_ctx ctx, int64_t *launches, double *avg_
                                   int64_t *total_passes, int32_t *slots);
 /* Load balance of the profiled compact region solves since the last
  * elses_ctx_set_profiling: the mean over those solves of the share of
- * resident workgroup time spent without a region, 1 - (sum of workgroup
- * lifetimes) / (workgroups x span of the solve), from per-workgroup stamps
+ * resident workgroup time spent without a region in the vector-width group
+ * that moves most bytes, 1 - (sum of its workgroup lifetimes) / (its
+ * workgroups x span of the solve), from per-workgroup stamps
  * of the device's constant-rate clock (the analogue of the paper's barrier
  * time from load imbalance, Table II); solves = how many were measured. */
 elses_status elses_ctx_region_idle(elses_ctx ctx, double *idle_share, int64_t *solves);
@@ -317,7 +318,8 @@ elses_status elses_spmm(elses_ctx ctx, elses_mat mat, int which, int32_t variant
  *           8192 orbitals per region, and its overlap iterate must fit in LDS);
  *           one persistent launch per column-width group solves them, one
  *           workgroup per region at a time and at most one per CU, taking
- *           regions from a device queue largest first, with every step of a
+ *           regions from a device queue costliest first (nonzeros x sqrt(kappa
+ *           of the region's B)), with every step of a
  *           region's solve (outer Lanczos steps, overlap solves with the
  *           Chebyshev-Richardson plan of the region's own overlap interval,
  *           shift updates, density assembly) inside the launch;

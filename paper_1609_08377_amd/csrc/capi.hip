@@ -932,7 +932,7 @@ T* upload(const std::vector<T>& v) {
 }
 
 // Compact layout: each region's principal sub-pencil laid out on its own
-// (region.hip), solved by one persistent launch with a largest-first queue.
+// (region.hip), solved by one persistent launch with a costliest-first queue.
 elses_status compact_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, const int32_t* centres,
                                  const double* radii, const uint8_t* orb_mask, elses_regions* out) {
     const HostMatrix& h = gm->h;
@@ -970,7 +970,16 @@ elses_status compact_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, con
         C.region_ent[r] = (r + 1 < n_regions ? H.reg[r + 1].ent0 : (int64_t)H.idx.size()) - D.ent0;
         C.lane_rows += (int64_t)D.nslice * 64 * D.cw;
     }
-    // queue order per vector width: largest region first
+    // queue order per vector width: costliest region first, the cost of a
+    // region outer step taken as nonzeros x sqrt(kappa of its B overlap
+    // interval), the growth of the Chebyshev-Richardson degree
+    std::vector<double> cost(n_regions, 0.0);
+    for (int r = 0; r < n_regions; ++r) {
+        const double tl = H.ritz_lo[r], th = H.ritz_hi[r], w = th - tl;
+        const double lo = std::max(gm->b_lo, tl - 0.02 * w - 1e-3 * std::fabs(tl));
+        const double hi = std::min(gm->b_hi, th + 0.02 * w + 1e-3 * std::fabs(th));
+        cost[r] = (double)H.region_nnz[r] * std::sqrt(hi / std::max(lo, 1e-300));
+    }
     C.order.clear();
     for (int g = 0; g < 3; ++g) {
         C.goff[g] = (int)C.order.size();
@@ -980,8 +989,7 @@ elses_status compact_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, con
                 grp.push_back(r);
                 C.gmaxP[g] = std::max(C.gmaxP[g], H.reg[r].nslice * 64);
             }
-        std::stable_sort(grp.begin(), grp.end(),
-                         [&](int a, int b) { return H.reg[a].nslice > H.reg[b].nslice; });
+        std::stable_sort(grp.begin(), grp.end(), [&](int a, int b) { return cost[a] > cost[b]; });
         C.order.insert(C.order.end(), grp.begin(), grp.end());
     }
     C.goff[3] = (int)C.order.size();
@@ -2232,9 +2240,12 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
                 ctx->prof_bytes = ctx->prof_bytes_acc / (double)ctx->prof_launches;
                 ctx->prof_flops = ctx->prof_flops_acc / (double)ctx->prof_launches;
                 ctx->prof_slots = C.gcw[gmost];
-                // idle share: 1 - (summed workgroup lifetimes) / (workgroups x span of the solve)
+                // idle share of the group that moves most bytes: 1 - (summed
+                // lifetimes of its workgroups) / (its workgroups x span of the
+                // solve).  The small groups' few workgroups end early by design
+                // (one region each) and are not counted.
                 uint64_t t0 = ~0ull, t1 = 0;
-                double busy = 0.0, n_wg = 0.0;
+                double busy = 0.0;
                 std::vector<unsigned long long> hc;
                 for (int g = 0; g < 3; ++g) {
                     if (!clk[g]) continue;
@@ -2244,12 +2255,11 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
                     for (int w = 0; w < gwg[g]; ++w) {
                         t0 = std::min<uint64_t>(t0, hc[2 * w]);
                         t1 = std::max<uint64_t>(t1, hc[2 * w + 1]);
-                        busy += (double)(hc[2 * w + 1] - hc[2 * w]);
-                        n_wg += 1.0;
+                        if (g == gmost) busy += (double)(hc[2 * w + 1] - hc[2 * w]);
                     }
                 }
-                if (t1 > t0 && n_wg > 0) {
-                    ctx->prof_idle_acc += 1.0 - busy / (n_wg * (double)(t1 - t0));
+                if (t1 > t0 && clk[gmost]) {
+                    ctx->prof_idle_acc += 1.0 - busy / (gwg[gmost] * (double)(t1 - t0));
                     ctx->prof_idle_n += 1;
                 }
             }

@@ -349,7 +349,7 @@ struct RegionDesc {
 
 struct CompactArgs {
     const RegionDesc* reg;
-    const int* order;        // queue order of the regions (largest first)
+    const int* order;        // queue order of the regions (costliest first: nonzeros x sqrt(kappa of B))
     int n_regions;
     const int* slice_len;    // longest row of each slice
     const int* slice_ent;    // first entry of each slice, relative to its region

@@ -7,7 +7,7 @@
 // owns one region at a time and runs its whole shifted solve (every outer
 // Lanczos step, every overlap solve, the multi-shift update and the density
 // assembly) without leaving the kernel; finished workgroups take the next
-// region from a largest-first device queue, so regions of uneven size and
+// region from a costliest-first device queue, so regions of uneven size and
 // iteration count do not wait for each other (the load imbalance the paper
 // measures as barrier time, Table II).  The host launches at most one
 // workgroup per CU, and gives each region the Chebyshev-Richardson plan of
