@@ -889,6 +889,11 @@ struct elses_regions_s {
         float *d_A32 = nullptr, *d_B32 = nullptr, *d_M32 = nullptr;
         int64_t* d_pat_off = nullptr;
         bool hasM = false;  // the learned preconditioner was carved with the regions
+        // half layout of B (mixed precision): stored off-diagonal pairs per region
+        std::vector<int64_t> region_hnnz;
+        int *d_hslice_len = nullptr, *d_hslice_ent = nullptr;
+        uint16_t* d_hidx = nullptr;
+        float *d_hval = nullptr, *d_hdiag = nullptr;
     } cp;
     std::vector<int> cols;         // global orbital of each column, region by region
     std::vector<int> col_row;      // row of each column's unit vector in bm
@@ -915,7 +920,8 @@ struct elses_regions_s {
             if (q) (void)hipFree(q);
         void* c[] = {cp.d_reg,   cp.d_order, cp.d_slice_len, cp.d_slice_ent, cp.d_col_pos, cp.d_pat_pos,
                      cp.d_idx,   cp.d_pos_row, cp.d_A64,     cp.d_B64,       cp.d_pat_B,   cp.d_pat_A,
-                     cp.d_A32,   cp.d_B32,   cp.d_pat_off,   cp.d_M64,       cp.d_M32};
+                     cp.d_A32,   cp.d_B32,   cp.d_pat_off,   cp.d_M64,       cp.d_M32,
+                     cp.d_hslice_len, cp.d_hslice_ent, cp.d_hidx, cp.d_hval, cp.d_hdiag};
         for (void* q : c)
             if (q) (void)hipFree(q);
         if (bm) elses_mat_destroy(bm);
@@ -1010,6 +1016,12 @@ elses_status compact_create_impl(elses_ctx ctx, elses_mat gm, int n_regions, con
         if (C.has32) {
             C.d_A32 = upload(H.A32);
             C.d_B32 = upload(H.B32);
+            C.d_hslice_len = upload(H.hslice_len);
+            C.d_hslice_ent = upload(H.hslice_ent);
+            C.d_hidx = upload(H.hidx);
+            C.d_hval = upload(H.hval);
+            C.d_hdiag = upload(H.hdiag);
+            C.region_hnnz = H.region_hnnz;
         }
         if (!H.M64.empty()) {
             C.hasM = true;
@@ -1953,7 +1965,7 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
     // one launch per vector-width group: LDS of its largest iterate, resident workgroups
     // (two iterate buffers when that keeps as many workgroups resident as one)
     size_t glds[3] = {0, 0, 0};
-    int gwg[3] = {0, 0, 0}, ghalf[3] = {0, 0, 0};
+    int gwg[3] = {0, 0, 0}, ghalf[3] = {0, 0, 0}, gsym[3] = {0, 0, 0};
     for (int g = 0; g < 3; ++g) {
         const int cnt = C.goff[g + 1] - C.goff[g];
         if (cnt == 0) continue;
@@ -1965,6 +1977,14 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         if (compact_occupancy(!mixed, C.gcw[g], precond, 2 * glds[g]) >= occ) {
             ghalf[g] = C.gmaxP[g] * C.gcw[g];
             glds[g] *= 2;
+            // FP32 Richardson steps on the half layout of B: a 32-bit fixed-point
+            // transpose accumulator per position and column after the two iterate buffers
+            const size_t ys = (size_t)C.gmaxP[g] * C.gcw[g] * 4;
+            if (mixed && !precond && C.d_hidx &&
+                compact_occupancy(false, C.gcw[g], false, glds[g] + ys) >= std::min(occ, kRegionsPerCu)) {
+                gsym[g] = 1;
+                glds[g] += ys;
+            }
         }
         // at most one workgroup (one region) per CU: on the 10^6-atom benchmark the
         // solve ran 9.9 s per step with 256 resident regions against 11.0 s with 512,
@@ -2044,6 +2064,11 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
         a.inner_tol = o.inner_tol;
         a.inner_max = o.inner_max;
         a.pos_row = C.d_pos_row;
+        a.hslice_len = C.d_hslice_len;
+        a.hslice_ent = C.d_hslice_ent;
+        a.hidx = C.d_hidx;
+        a.hval = C.d_hval;
+        a.hdiag = C.d_hdiag;
         a.col_pos = C.d_col_pos;
         a.pat_off = C.d_pat_off;
         a.pat_pos = C.d_pat_pos;
@@ -2154,6 +2179,7 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
             a.order = C.d_order + C.goff[g];
             a.n_regions = cnt;
             a.lds_half = ghalf[g];
+            a.half = gsym[g];
             a.queue = counters + g;
             a.vec = vec_g[g];
             a.vec_stride = nblk * C.gmaxP[g] * C.gcw[g];
@@ -2205,7 +2231,12 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
             }
             const double nnz = (double)C.region_nnz[r];
             const double products = mixed ? (2.0 * (h_rdeg[r] - 1) + 1.0) : (double)(h_rdeg[r] - 1);
-            const double per_it = nnz * (2.0 + vb) * products + nnz * (2.0 + vb) + 64.0 * carried +
+            // Richardson products (2 (d - 1) mixed, d - 1 FP64), the rest (refinement, A) on the full layout;
+            // a half-layout product reads each stored pair once (index + value) and the diagonal
+            const double rich = mixed ? 2.0 * (h_rdeg[r] - 1) : (double)(h_rdeg[r] - 1);
+            const double full_b = nnz * (2.0 + vb);
+            const double rich_b = gsym[g] ? (double)C.region_hnnz[r] * (2.0 + vb) + 4.0 * D.m : full_b;
+            const double per_it = rich_b * rich + full_b * (products + 1.0 - rich) + 64.0 * carried +
                                   18.0 * 8.0 * (double)D.m * D.cw;
             gbytes[g] += (n_it + 1) * per_it;
             gflops[g] += (n_it + 1) * (2.0 * nnz * D.cw * (products + 1.0));

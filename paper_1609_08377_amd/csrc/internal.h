@@ -345,6 +345,9 @@ struct RegionDesc {
     int cw;        // column width of the region's vectors: 1, 2 or 4 (>= ncol)
     int64_t ent0;  // first entry of the region's slices
     int64_t pos0;  // first position in the position tables
+    int64_t hent0; // first entry of the region's slices in the half layout of B (mixed precision)
+    int heb;       // |B_pq| < 2^(heb - L) over the half layout's entries, where no position takes
+                   // more than 2^L - 1 transpose terms (fixed-point scale of its products)
 };
 
 struct CompactArgs {
@@ -359,6 +362,14 @@ struct CompactArgs {
     const double* M64;       // entries: learned preconditioner M (precond launches), FP64
     const float* M32;        //          and its FP32 copy (mixed precision)
     const uint16_t* pos_row; // region orbital of each position (>= m: padding)
+    // half layout of B (FP32): each off-diagonal pair {p, q} stored once, in
+    // the row of p when p + q is even and p < q or odd and p > q; diagonal apart
+    int half;                // 1: the FP32 Richardson steps use the half layout
+    const int* hslice_len;   // longest half row of each slice
+    const int* hslice_ent;   // first half entry of each slice, relative to its region
+    const uint16_t* hidx;    // half entries: column position inside the region
+    const float* hval;       // half entries: FP32 values of B
+    const float* hdiag;      // [positions] FP32 diagonal of B (0 on padding)
     const int* col_pos;      // [n_cols] position of the column's unit vector
     const int64_t* pat_off;  // [n_cols+1] pattern offsets (caller's layout)
     const int* pat_pos;      // position of each pattern entry (-1 outside the region)
@@ -418,6 +429,10 @@ struct CompactHost {
     std::vector<uint16_t> idx, pos_row;
     std::vector<double> A64, B64, M64;
     std::vector<float> A32, B32, M32;
+    std::vector<int> hslice_len, hslice_ent;  // half layout of B (mixed precision)
+    std::vector<uint16_t> hidx;
+    std::vector<float> hval, hdiag;
+    std::vector<int64_t> region_hnnz;         // stored off-diagonal pairs of each region's half layout
     std::vector<int> cols;      // global orbital of each column, region by region
     std::vector<int> col_pos;   // position of each column's unit vector in its region
     std::vector<int> col_region;

@@ -154,6 +154,57 @@ __device__ __forceinline__ void row_product(const uint16_t* __restrict__ ib, con
     }
 }
 
+// One lane's half row of B (the entries its row stores of the pairs split
+// between the two rows): acc += val * x[col] gathered from src ([P][C] FP32),
+// and the transpose half Ys[col] += val * xs (xs = the row's own x scaled by
+// 2^sh) in 32-bit fixed point: the terms are rounded to the nearest integer
+// (|term| < 2^(30 - L) for a region whose positions take at most 2^L - 1
+// transpose terms, so no sum overflows) and summed by LDS integer atomics,
+// which makes the sums independent of the order the waves reach them.
+// Entries go in batches of 16 written in issue order (index and value loads,
+// gathers, FMAs, atomics): an atomic is an ordered memory operation that
+// later loads may not pass, so interleaving them per entry would serialise
+// the loads.  The last batch re-reads the row's last entry in its unused
+// slots, with weight zero and no atomic.
+template <int C>
+__device__ __forceinline__ void half_row(const uint16_t* __restrict__ ib, const float* __restrict__ vb, uint32_t e0,
+                                         int len, const float* src, const float (&xs)[C], int* Ys,
+                                         float (&acc)[C]) {
+    for (int k0 = 0; k0 < len; k0 += 16) {
+        uint32_t j[16];
+        float v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const uint32_t e = e0 + 64u * (uint32_t)min(k0 + q, len - 1);
+            j[q] = ib[e];
+            v[q] = vb[e];
+        }
+        float xv[16][C];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) ldv<C>(src + j[q] * (uint32_t)C, xv[q]);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const float w = (k0 + q < len) ? v[q] : 0.0f;
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] = fmaf(w, xv[q][c], acc[c]);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (k0 + q < len) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) atomicAdd(Ys + j[q] * (uint32_t)C + c, (int)rintf(v[q] * xs[c]));
+            }
+        }
+    }
+}
+
+// Largest of m over the wave, folded into *slot (non-negative floats order as
+// their bit patterns).
+__device__ __forceinline__ void wave_max_into(unsigned int* slot, float m) {
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(slot, __float_as_uint(m));
+}
+
 // Per-region view of the arguments
 template <typename TV>
 struct RView {
@@ -170,6 +221,13 @@ struct RView {
     int d;
     double g0;
     const double* tau;
+    // half layout of B (FP32 Richardson steps when the launch sets it)
+    const int* hslen;         // [ns] longest half row of each slice
+    const int* hsent;         // [ns] first half entry of each slice (relative to the region)
+    const uint16_t* hidx;
+    const float* hval;
+    const float* hdiag;       // [P] diagonal
+    int heb;                  // |half values| < 2^(heb - L), 2^L > most transpose terms of a position
 };
 
 // Per-column scalars of the region being solved, in LDS (uniform values kept
@@ -194,8 +252,102 @@ __device__ __forceinline__ const TV* pick(const double* d, const float* f) {
 // second LDS buffer the steps ping-pong between the two; otherwise the new
 // iterate of a lane's rows goes through the per-workgroup block Xn (global,
 // this lane's positions only) until every gather of the old one is done.
+// The same round in FP32 with B in the half layout: per step, pass 1 takes
+// the step with each row's gathered half (into the second iterate buffer) and
+// forms the transpose half (fixed point, into Ys after the two iterate
+// buffers); pass 2 subtracts tau times the transpose half and clears Ys.  The
+// fixed-point scale of step k is 2^sh with sh = 30 - heb - e, max |x_k| < 2^e
+// (from the previous pass) and heb = the region's value exponent bound plus
+// L, so that every term |B_pq x_p| 2^sh < 2^(30 - L).
+template <int C>
+__device__ __forceinline__ void richardson_half(const CompactArgs& a, const RView<float>& R, const float* rhs,
+                                                float* X) {
+    __shared__ unsigned int xmax[2];  // max |x_k| of the current and the next iterate
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const float g0 = static_cast<float>(R.g0);
+    int* Ys = reinterpret_cast<int*>(X + 2 * a.lds_half);
+    if (threadIdx.x < 2) xmax[threadIdx.x] = 0u;
+    __syncthreads();
+    float m = 0.f;
+    for (int sl = w; sl < R.ns; sl += kRW) {
+        const int pos = sl * 64 + lane;
+        float r[C];
+        ldv<C>(rhs + (size_t)pos * C, r);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            r[c] *= g0;
+            m = fmaxf(m, fabsf(r[c]));
+            Ys[(size_t)pos * C + c] = 0;
+        }
+        stv<C>(X + (size_t)pos * C, r);
+    }
+    wave_max_into(&xmax[1], m);
+    __syncthreads();
+    float* cur = X;
+    float* nxt = X + a.lds_half;
+    for (int k = 1; k < R.d; ++k) {
+        const float tau = static_cast<float>(R.tau[k - 1]);
+        int ex = 0;
+        (void)frexpf(__uint_as_float(xmax[k & 1]), &ex);
+        const int sh = 30 - R.heb - ex;
+        if (threadIdx.x == 0) xmax[(k + 1) & 1] = 0u;  // read two barriers ago; refilled in pass 2
+        for (int sl = w; sl < R.ns; sl += kRW) {
+            const int pos = sl * 64 + lane;
+            float xo[C], xs[C], acc[C], r[C];
+            ldv<C>(cur + (size_t)pos * C, xo);
+            ldv<C>(rhs + (size_t)pos * C, r);
+            const float dg = R.hdiag[pos];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                xs[c] = ldexpf(xo[c], sh);
+                acc[c] = dg * xo[c];
+            }
+            half_row<C>(R.hidx, R.hval, (uint32_t)(R.hsent[sl] + lane), R.hslen[sl], cur, xs, Ys, acc);
+            // the step without the transpose half, which pass 2 subtracts
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] = xo[c] + tau * (r[c] - acc[c]);
+            stv<C>(nxt + (size_t)pos * C, acc);
+        }
+        __syncthreads();
+        float mm = 0.f;
+        for (int sl = w; sl < R.ns; sl += kRW) {
+            const int pos = sl * 64 + lane;
+            float g[C];
+            ldv<C>(nxt + (size_t)pos * C, g);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int t = Ys[(size_t)pos * C + c];
+                Ys[(size_t)pos * C + c] = 0;
+                g[c] = fmaf(-tau, ldexpf(static_cast<float>(t), -sh), g[c]);
+                mm = fmaxf(mm, fabsf(g[c]));
+            }
+            stv<C>(nxt + (size_t)pos * C, g);
+        }
+        wave_max_into(&xmax[(k + 1) & 1], mm);
+        __syncthreads();
+        float* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (cur != X) {
+        for (int sl = w; sl < R.ns; sl += kRW) {
+            const int pos = sl * 64 + lane;
+            float xn[C];
+            ldv<C>(cur + (size_t)pos * C, xn);
+            stv<C>(X + (size_t)pos * C, xn);
+        }
+        __syncthreads();
+    }
+}
+
 template <int C, typename TV>
 __device__ __forceinline__ void richardson(const CompactArgs& a, const RView<TV>& R, const TV* rhs, TV* X, TV* Xn) {
+    if constexpr (sizeof(TV) == 4) {
+        if (a.half) {
+            richardson_half<C>(a, R, rhs, X);
+            return;
+        }
+    }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const TV g0 = static_cast<TV>(R.g0);
     for (int sl = w; sl < R.ns; sl += kRW) {
@@ -583,6 +735,14 @@ __device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionD
     R.Av = pick<TV>(a.A64, a.A32) + D.ent0;
     R.Bv = pick<TV>(a.B64, a.B32) + D.ent0;
     R.Mv = PC ? pick<TV>(a.M64, a.M32) + D.ent0 : nullptr;
+    if (a.half) {
+        R.hslen = a.hslice_len + D.slice0;
+        R.hsent = a.hslice_ent + D.slice0;
+        R.hidx = a.hidx + D.hent0;
+        R.hval = a.hval + D.hent0;
+        R.hdiag = a.hdiag + D.pos0;
+        R.heb = D.heb;
+    }
     const int P = R.P;
     const size_t vs = (size_t)P * C;
     double* Q = vbase;
@@ -598,6 +758,13 @@ __device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionD
     ps.p = reinterpret_cast<TV*>(V + 5 * vs);
     ps.q = reinterpret_cast<TV*>(V + 6 * vs);
     ps.z = reinterpret_cast<TV*>(V + 7 * vs);
+
+    // q_n is kept in LDS too (over the iterate buffers, free between an outer
+    // step's overlap solve and the next A product) when [P][C] FP64 fits there:
+    // FP64 passes, or the two FP32 buffers of the ping-pong.  The A product then
+    // gathers q_n from LDS like the B products gather the iterate.
+    const bool qlds = sizeof(TV) == 8 || a.lds_half > 0;
+    double* Ql = reinterpret_cast<double*>(X);
 
     if (tid == 0) cs.fallback = 0;
     if (tid < C) {
@@ -643,6 +810,7 @@ __device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionD
         }
         stv<C>(Q + (size_t)pos * C, v);
         stv<C>(T1 + (size_t)pos * C, s);
+        if (qlds) stv<C>(Ql + (size_t)pos * C, v);
     }
     __syncthreads();
 
@@ -652,15 +820,21 @@ __device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionD
             double al[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) al[c] = 0.0;
-                        for (int sl = w; sl < R.ns; sl += kRW) {
-                const int pos = sl * 64 + lane;
-                double acc[C], q[C];
-                row_product<C>(R.idx, R.Av, (uint32_t)(R.sent[sl] + lane), R.slen[sl], (const double*)Q, acc);
-                ldv<C>(Q + (size_t)pos * C, q);
+            auto a_rows = [&](const double* qs) {
+                for (int sl = w; sl < R.ns; sl += kRW) {
+                    const int pos = sl * 64 + lane;
+                    double acc[C], q[C];
+                    row_product<C>(R.idx, R.Av, (uint32_t)(R.sent[sl] + lane), R.slen[sl], qs, acc);
+                    ldv<C>(qs + (size_t)pos * C, q);
 #pragma unroll
-                for (int c = 0; c < C; ++c) al[c] = fma(q[c], acc[c], al[c]);
-                stv<C>(S + (size_t)pos * C, acc);
-            }
+                    for (int c = 0; c < C; ++c) al[c] = fma(q[c], acc[c], al[c]);
+                    stv<C>(S + (size_t)pos * C, acc);
+                }
+            };
+            if (qlds)
+                a_rows(Ql);
+            else
+                a_rows(Q);
             wg_sum<C>(al, red);
             if (tid < C) cs.alpha[tid] = al[tid];
             if (tid == 0) atomicAdd(a.products, 1ull);
@@ -823,6 +997,7 @@ __device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionD
             stv<C>(Q + (size_t)pos * C, v);
             stv<C>(T0 + (size_t)pos * C, t1);
             stv<C>(T1 + (size_t)pos * C, s);
+            if (qlds) stv<C>(Ql + (size_t)pos * C, v);
         }
         __syncthreads();
     }

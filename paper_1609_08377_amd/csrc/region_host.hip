@@ -222,6 +222,12 @@ const char* build_compact(const HostMatrix& h, int n_regions, const int* centres
                 out.pat_off[c + 1] = out.pat_off[c] + h.atom_plen[centres[r]];
     }
     std::atomic<int> bad{0};
+    // half layout of B per region (mixed precision), concatenated after pass 2
+    std::vector<std::vector<uint16_t>> hidx_r(want32 ? n_regions : 0);
+    std::vector<std::vector<float>> hval_r(want32 ? n_regions : 0), hdiag_r(want32 ? n_regions : 0);
+    std::vector<std::vector<int>> hlen_r(want32 ? n_regions : 0);
+    std::vector<int> heb_r(n_regions, 0);
+    out.region_hnnz.assign(n_regions, 0);
     // pass 2: layout of every region
     parallel_for(n_regions, [&](int r, int t) {
         std::vector<int>& loc = loc_t[t];
@@ -287,6 +293,67 @@ const char* build_compact(const HostMatrix& h, int n_regions, const int* centres
             e_rel += (int64_t)len * 64;
         }
         if (e_rel != P.n_ent) bad.store(1);
+        // half layout of B from the rows just laid out: each off-diagonal pair
+        // {p, q} once, in row p when p + q is even and p < q or odd and p > q
+        // (a balanced split: every row keeps about half its pairs), diagonal apart
+        if (want32) {
+            std::vector<int>& hl = hlen_r[r];
+            std::vector<uint16_t>& hi = hidx_r[r];
+            std::vector<float>& hv = hval_r[r];
+            std::vector<float>& hd = hdiag_r[r];
+            hl.assign(P.nslice, 0);
+            hd.assign((size_t)P.nslice * 64, 0.0f);
+            std::vector<std::vector<std::pair<uint16_t, float>>> lane_rows(64);
+            std::vector<int> fan((size_t)P.nslice * 64, 0);  // transpose terms each position takes
+            float bmax = 0.0f;
+            int64_t stored = 0;
+            for (int s = 0; s < P.nslice; ++s) {
+                const int len = out.slice_len[D.slice0 + s];
+                const int64_t e0 = D.ent0 + out.slice_ent[D.slice0 + s];
+                int hmax = 0;
+                for (int l = 0; l < 64; ++l) {
+                    const int p = 64 * s + l;
+                    auto& lr = lane_rows[l];
+                    lr.clear();
+                    const int real = p < P.m ? row_len[perm[p]] : 0;
+                    for (int k = 0; k < real && k < len; ++k) {
+                        const int64_t e = e0 + (int64_t)k * 64 + l;
+                        const int q = out.idx[e];
+                        const float b = out.B32[e];
+                        if (q == p) {
+                            hd[p] = b;
+                        } else if (((p + q) & 1) == 0 ? (p < q) : (p > q)) {
+                            lr.emplace_back((uint16_t)q, b);
+                            bmax = std::max(bmax, std::fabs(b));
+                            ++fan[q];
+                        }
+                    }
+                    stored += (int64_t)lr.size();
+                    hmax = std::max(hmax, (int)lr.size());
+                }
+                hl[s] = hmax;
+                const size_t b0 = hi.size();
+                hi.resize(b0 + (size_t)hmax * 64);
+                hv.resize(b0 + (size_t)hmax * 64);
+                for (int l = 0; l < 64; ++l) {
+                    const int p = 64 * s + l;
+                    const auto& lr = lane_rows[l];
+                    for (int k = 0; k < hmax; ++k) {
+                        const size_t e = b0 + (size_t)k * 64 + l;
+                        hi[e] = k < (int)lr.size() ? lr[k].first : (uint16_t)p;  // zero padding
+                        hv[e] = k < (int)lr.size() ? lr[k].second : 0.0f;
+                    }
+                }
+            }
+            int eb = 0;
+            if (bmax > 0.0f) (void)std::frexp(bmax, &eb);  // bmax < 2^eb
+            eb = std::max(eb, -60);                         // keeps the scaled x inside FP32 range
+            const int fmax = *std::max_element(fan.begin(), fan.end());
+            int L = 0;
+            while ((1 << L) <= fmax) ++L;  // fmax < 2^L
+            heb_r[r] = eb + L;
+            out.region_hnnz[r] = stored;
+        }
         // extreme Ritz values of the region's B: 40 Lanczos steps on the
         // layout just built (FP64 values), from a fixed pseudo-random start on
         // the region's rows (padding positions stay zero)
@@ -371,6 +438,35 @@ const char* build_compact(const HostMatrix& h, int n_regions, const int* centres
         for (int a : P.atoms) loc[a] = -1;
     });
     if (bad.load()) return "internal: region layout sizes disagree";
+    if (want32) {
+        int64_t he = 0;
+        out.hslice_len.assign(out.slice_len.size(), 0);
+        out.hslice_ent.assign(out.slice_len.size(), 0);
+        for (int r = 0; r < n_regions; ++r) {
+            RegionDesc& D = out.reg[r];
+            D.hent0 = he;
+            D.heb = heb_r[r];
+            int64_t rel = 0;
+            for (int s = 0; s < D.nslice; ++s) {
+                out.hslice_len[D.slice0 + s] = hlen_r[r][s];
+                out.hslice_ent[D.slice0 + s] = (int)rel;
+                rel += (int64_t)hlen_r[r][s] * 64;
+            }
+            he += rel;
+        }
+        out.hidx.resize(he);
+        out.hval.resize(he);
+        out.hdiag.assign(out.pos_row.size(), 0.0f);
+        parallel_for(n_regions, [&](int r, int) {
+            const RegionDesc& D = out.reg[r];
+            std::copy(hidx_r[r].begin(), hidx_r[r].end(), out.hidx.begin() + D.hent0);
+            std::copy(hval_r[r].begin(), hval_r[r].end(), out.hval.begin() + D.hent0);
+            std::copy(hdiag_r[r].begin(), hdiag_r[r].end(), out.hdiag.begin() + D.pos0);
+            std::vector<uint16_t>().swap(hidx_r[r]);
+            std::vector<float>().swap(hval_r[r]);
+            std::vector<float>().swap(hdiag_r[r]);
+        });
+    }
     for (int r = 0; r < n_regions; ++r) out.useful += (int64_t)plan[r].m * plan[r].ncol;
     return nullptr;
 }

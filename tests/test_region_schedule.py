@@ -5,7 +5,9 @@ hides the memory latency only while the 16 index and 16 value loads of an
 unrolled batch of entries are all in flight before their gathers.  Under a
 tighter occupancy target the compiler has scheduled the same loop as load,
 wait, gather, wait, FMA for every entry (32 waits on vector memory per 16
-entries) and the solve ran 2.5x slower.  This compiles region.hip for gfx950
+entries) and the solve ran 2.5x slower; an LDS atomic placed between one
+entry's loads and the next entry's has the same effect (loads may not pass an
+atomic).  This compiles region.hip for gfx950
 to assembly and checks that the FP32 one-column kernel (the benchmark's) keeps
 its 16-deep product loops batched.
 """
@@ -29,7 +31,8 @@ def hipcc():
 
 
 def product_loops(asm: str, symbol: str):
-    """(global loads, LDS reads, vector-memory waits) of every loop of `symbol`
+    """(global loads, LDS reads, vector-memory waits, longest run of global loads
+    issued with no vector-memory wait between them) of every loop of `symbol`
     without a barrier that holds at least 32 global loads and 16 LDS reads."""
     lines = asm.split("\n")
     start = next(i for i, l in enumerate(lines) if l.startswith(symbol + ":"))
@@ -47,8 +50,15 @@ def product_loops(asm: str, symbol: str):
             seg = body[labels[m.group(1)]:k + 1]
             loads = sum("global_load" in x for x in seg)
             lds = sum("ds_read" in x for x in seg)
-            if loads >= 32 and lds >= 16 and not any("s_barrier" in x for x in seg) and len(seg) < 400:
-                out.append((loads, lds, sum("s_waitcnt vmcnt" in x for x in seg)))
+            if loads >= 32 and lds >= 16 and not any("s_barrier" in x for x in seg) and len(seg) < 800:
+                run = best = 0
+                for x in seg:
+                    if "global_load" in x:
+                        run += 1
+                        best = max(best, run)
+                    elif "s_waitcnt vmcnt" in x:
+                        run = 0
+                out.append((loads, lds, sum("s_waitcnt vmcnt" in x for x in seg), best))
     return out
 
 
@@ -64,7 +74,7 @@ def test_product_loops_keep_their_loads_in_flight(tmp_path):
     subprocess.run(cmd, check=True, stdout=subprocess.PIPE, stderr=subprocess.PIPE, timeout=900)
     loops = product_loops(out.read_text(), KERNEL)
     assert loops, "no 16-deep product loop found in the FP32 one-column kernel"
-    # a serialised loop waits once per load (or more); a batched one issues its loads
-    # before the first wait and needs clearly fewer waits than loads
-    for loads, lds, waits in loops:
-        assert waits <= loads - 6, (loads, lds, waits)
+    # a serialised loop waits after every load or two; a batched one issues the index
+    # and value loads of its 16 entries back to back before the first wait
+    for loads, lds, waits, run in loops:
+        assert run >= 16, (loads, lds, waits, run)
