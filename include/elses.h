@@ -200,7 +200,9 @@ elses_status elses_density_matrix(elses_ctx ctx, elses_mat mat, int32_t n_cols, 
  * algorithmic traffic of all groups: per outer step of each region its sparse
  * products (the A product, the Richardson steps of the region's own plan and,
  * in mixed precision, the refinement product; a 2-byte index plus the value,
- * 4 or 8 bytes, per nonzero), the carried x and p (read and written, 64 bytes
+ * 4 or 8 bytes, per nonzero, or for Richardson steps on the half layout of B
+ * 6 bytes per stored off-diagonal pair plus 4 per diagonal entry), the
+ * carried x and p (read and written, 64 bytes
  * per shift and row) and its Lanczos vectors in scratch (18 x 8 bytes per
  * row and column); slots = the column width of the group that moved most
  * bytes.  A compact launch holds at most one workgroup (one region) per CU.
@@ -322,7 +324,11 @@ elses_status elses_spmm(elses_ctx ctx, elses_mat mat, int which, int32_t variant
  *           of the region's B)), with every step of a
  *           region's solve (outer Lanczos steps, overlap solves with the
  *           Chebyshev-Richardson plan of the region's own overlap interval,
- *           shift updates, density assembly) inside the launch;
+ *           shift updates, density assembly) inside the launch; in mixed
+ *           precision the FP32 Richardson steps of regions with 1 or 2
+ *           columns read B's symmetric pairs once (a half layout built
+ *           with the set), summing the transpose half as 32-bit fixed
+ *           point, so results stay reproducible run to run;
  *  64, 128  tiles: consecutive regions (which should be spatial neighbours)
  *           are packed into tiles of tile_width column slots of one
  *           block-diagonal matrix that advance through one launch sequence

@@ -1978,9 +1978,12 @@ elses_status compact_solve(elses_ctx ctx, const elses_regions_s* rp, int K, cons
             ghalf[g] = C.gmaxP[g] * C.gcw[g];
             glds[g] *= 2;
             // FP32 Richardson steps on the half layout of B: a 32-bit fixed-point
-            // transpose accumulator per position and column after the two iterate buffers
+            // transpose accumulator per position and column after the two iterate buffers.
+            // Column widths 1 and 2 only: each stored pair costs one LDS atomic per
+            // column, and at 4 columns the atomics outweigh the halved stream (a
+            // 4-column region of the 10^6-atom benchmark ran 10.7 s against 7.0 s)
             const size_t ys = (size_t)C.gmaxP[g] * C.gcw[g] * 4;
-            if (mixed && !precond && C.d_hidx &&
+            if (mixed && !precond && C.d_hidx && C.gcw[g] <= 2 &&
                 compact_occupancy(false, C.gcw[g], false, glds[g] + ys) >= std::min(occ, kRegionsPerCu)) {
                 gsym[g] = 1;
                 glds[g] += ys;

@@ -342,7 +342,10 @@ __device__ __forceinline__ void richardson_half(const CompactArgs& a, const RVie
 
 template <int C, typename TV>
 __device__ __forceinline__ void richardson(const CompactArgs& a, const RView<TV>& R, const TV* rhs, TV* X, TV* Xn) {
-    if constexpr (sizeof(TV) == 4) {
+    // the half layout serves column widths 1 and 2 only (the host never sets it
+    // for 4); kept out of the 4-column kernel, whose product loops the compiler
+    // serialises under the extra register pressure
+    if constexpr (sizeof(TV) == 4 && C <= 2) {
         if (a.half) {
             richardson_half<C>(a, R, rhs, X);
             return;
