@@ -340,12 +340,13 @@ __device__ __forceinline__ void richardson_half(const CompactArgs& a, const RVie
     }
 }
 
-template <int C, typename TV>
+// HALF: the kernel carries the half-layout path (FP32, 1 or 2 columns, not
+// preconditioned: the only launches the host sets it for).  Kept out of every
+// other kernel, whose product loops the compiler serialises under the extra
+// register pressure of code they never run.
+template <int C, typename TV, bool HALF>
 __device__ __forceinline__ void richardson(const CompactArgs& a, const RView<TV>& R, const TV* rhs, TV* X, TV* Xn) {
-    // the half layout serves column widths 1 and 2 only (the host never sets it
-    // for 4); kept out of the 4-column kernel, whose product loops the compiler
-    // serialises under the extra register pressure
-    if constexpr (sizeof(TV) == 4 && C <= 2) {
+    if constexpr (HALF) {
         if (a.half) {
             richardson_half<C>(a, R, rhs, X);
             return;
@@ -613,7 +614,7 @@ __device__ __forceinline__ void overlap_round(const CompactArgs& a, const RView<
             __syncthreads();
         }
     }
-    richardson<C, TV>(a, R, rhs, X, Xn);
+    richardson<C, TV, PC == 0 && sizeof(TV) == 4 && C <= 2>(a, R, rhs, X, Xn);
     if (threadIdx.x == 0) atomicAdd(a.products, (unsigned long long)(R.d - 1));
 }
 
@@ -762,11 +763,13 @@ __device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionD
     ps.q = reinterpret_cast<TV*>(V + 6 * vs);
     ps.z = reinterpret_cast<TV*>(V + 7 * vs);
 
-    // q_n is kept in LDS too (over the iterate buffers, free between an outer
-    // step's overlap solve and the next A product) when [P][C] FP64 fits there:
-    // FP64 passes, or the two FP32 buffers of the ping-pong.  The A product then
-    // gathers q_n from LDS like the B products gather the iterate.
-    const bool qlds = sizeof(TV) == 8 || a.lds_half > 0;
+    // In mixed precision q_n is kept in LDS too (over the two FP32 iterate
+    // buffers of the ping-pong, free between an outer step's overlap solve and
+    // the next A product, exactly [P][C] FP64).  The A product then gathers q_n
+    // from LDS like the B products gather the iterate.  (Not in the FP64
+    // kernels: there it serialised the 4-column kernel's loops.)
+    constexpr bool kQ = sizeof(TV) == 4;
+    const bool qlds = kQ && a.lds_half > 0;
     double* Ql = reinterpret_cast<double*>(X);
 
     if (tid == 0) cs.fallback = 0;
@@ -834,10 +837,14 @@ __device__ __forceinline__ void solve_region(const CompactArgs& a, const RegionD
                     stv<C>(S + (size_t)pos * C, acc);
                 }
             };
-            if (qlds)
-                a_rows(Ql);
-            else
+            if constexpr (kQ) {
+                if (qlds)
+                    a_rows(Ql);
+                else
+                    a_rows(Q);
+            } else {
                 a_rows(Q);
+            }
             wg_sum<C>(al, red);
             if (tid < C) cs.alpha[tid] = al[tid];
             if (tid == 0) atomicAdd(a.products, 1ull);
