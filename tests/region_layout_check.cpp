@@ -13,7 +13,9 @@
 // int8 n_orb[N], int64 blk_row_ptr[N+1], int32 blk_col[nnzb],
 // int64 val_ptr[nnzb+1], double A[nnz], double B[nnz], double pos[3N],
 // int32 n_regions, int32 centres[n_regions], double radii[n_regions].
-// Prints one line of statistics and exits 0, or names the first failure.
+// Prints one line of statistics, then per region "ritz r lo hi" (the extreme
+// Ritz values of its B from the builder's Lanczos), and exits 0, or names the
+// first failure.
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -172,5 +174,6 @@ int main(int argc, char** argv) {
     }
     printf("ok regions %d pairs %lld slots %lld fill %.4f worst %.4f\n", nr, (long long)pairs_total,
            (long long)slots_total, slots_total ? (double)pairs_total / (double)slots_total : 1.0, worst_fill);
+    for (int r = 0; r < nr; ++r) printf("ritz %d %.17g %.17g\n", r, C.ritz_lo[r], C.ritz_hi[r]);
     return 0;
 }

@@ -6,7 +6,9 @@ compiles `tests/region_layout_check.cpp` against the built library, builds a
 region set of a seeded synthetic box with the library's own layout builder and
 checks the half layout against the full one: every pair once, in its owner row,
 with the full layout's FP32 value; the diagonal; the padding; the slice
-lengths; and the bound that keeps the fixed-point sums from overflowing.
+lengths; and the bound that keeps the fixed-point sums from overflowing.  The
+same build's extreme Ritz values of each region's B are checked against the
+dense spectrum of the oracle's carved B.
 """
 import os
 import shutil
@@ -15,6 +17,7 @@ import subprocess
 import numpy as np
 import pytest
 
+import oracle
 import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -75,3 +78,20 @@ def test_half_layout_of_b(tmp_path):
     # the split keeps the half rows of a slice close in length: most slots hold a pair
     fill = float(fields[fields.index("fill") + 1])
     assert fill >= 0.6, out.stdout
+    # the extreme Ritz values of each region's B (40 Lanczos steps on the built layout),
+    # which set the region's Chebyshev-Richardson plan, against the spectrum of the
+    # oracle's carved B: inside it (Ritz values of a symmetric matrix) and close to its ends
+    ritz = {}
+    for line in out.stdout.splitlines():
+        if line.startswith("ritz "):
+            _, r, lo, hi = line.split()
+            ritz[int(r)] = (float(lo), float(hi))
+    assert len(ritz) == len(centres)
+    sizes = [len(oracle.region_atoms(s, int(c), float(rad))) for c, rad in zip(centres, radii)]
+    for r in np.argsort(sizes)[:6]:
+        _, Br, _ = oracle.carve_region(s, oracle.region_atoms(s, int(centres[r]), float(radii[r])))
+        ev = np.linalg.eigvalsh(Br.dense())
+        lo, hi = ritz[int(r)]
+        width = ev[-1] - ev[0]
+        assert ev[0] - 1e-10 <= lo <= ev[0] + 0.02 * width, (r, lo, ev[0], ev[-1])
+        assert ev[-1] - 0.02 * width <= hi <= ev[-1] + 1e-10, (r, hi, ev[0], ev[-1])
