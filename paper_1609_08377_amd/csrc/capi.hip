@@ -269,13 +269,9 @@ void build_groups(const elses_system* sys, const HostMatrix& h, const std::vecto
     }
 }
 
-struct Rich {
-    int d = 2;
-    double g0 = 0;
-    std::vector<double> tau;  // steps k = 1 .. d-1
-    double reached = 0;       // 1/T_d(c/h): the residual factor the plan guarantees on [lo, hi]
-};
-constexpr int kRichMaxDegree = 400;
+}  // namespace
+
+namespace elses {
 
 // Richardson iteration for B v = s with the d roots of the Chebyshev
 // polynomial of the interval [lo, hi] as inverse step lengths,
@@ -328,6 +324,10 @@ Rich richardson_plan(double lo, double hi, double tol) {
     for (int k = 1; k < r.d; ++k) r.tau.push_back(1.0 / ord[k]);
     return r;
 }
+
+}  // namespace elses
+
+namespace {
 
 // A plan capped at kRichMaxDegree steps does not reach its tolerance: the
 // overlap solve would be less accurate than asked.  Refuse such solves.

@@ -422,6 +422,20 @@ void launch_zero_ints(int* p, size_t n, hipStream_t st);
 // diagonal a and off-diagonal b (Sturm-sequence bisection).
 double tri_eig(const std::vector<double>& a, const std::vector<double>& b, int idx);
 
+// Chebyshev-Richardson plan for B v = s on an interval [lo, hi] holding B's
+// spectrum: degree d (the smallest with 1/T_d(c/h) <= tol, c and h the
+// interval's centre and half width, at least 3, at most kRichMaxDegree), the
+// first step g0 = 1/theta_0 and the inverse roots tau_k = 1/theta_k of the
+// later steps, the roots theta of T_d on the interval in Leja order.
+struct Rich {
+    int d = 2;
+    double g0 = 0;
+    std::vector<double> tau;  // steps k = 1 .. d-1
+    double reached = 0;       // 1/T_d(c/h): the residual factor the plan guarantees on [lo, hi]
+};
+constexpr int kRichMaxDegree = 400;
+Rich richardson_plan(double lo, double hi, double tol);
+
 // Host-side construction of the compact layout (region_host.hip).
 struct CompactHost {
     std::vector<RegionDesc> reg;
