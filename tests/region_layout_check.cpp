@@ -13,7 +13,8 @@
 // int8 n_orb[N], int64 blk_row_ptr[N+1], int32 blk_col[nnzb],
 // int64 val_ptr[nnzb+1], double A[nnz], double B[nnz], double pos[3N],
 // int32 n_regions, int32 centres[n_regions], double radii[n_regions].
-// Prints one line of statistics, then per region "ritz r lo hi" (the extreme
+// Prints one line of statistics (with the most transpose terms any position
+// takes), then per region "ritz r lo hi" (the extreme
 // Ritz values of its B from the builder's Lanczos), and exits 0, or names the
 // first failure.
 #include <cmath>
@@ -90,6 +91,7 @@ int main(int argc, char** argv) {
     }
     int64_t pairs_total = 0, slots_total = 0;
     double worst_fill = 1.0;
+    int fan_most = 0;
     for (int r = 0; r < nr; ++r) {
         const elses::RegionDesc& D = C.reg[r];
         const int P = D.nslice * 64;
@@ -168,12 +170,14 @@ int main(int argc, char** argv) {
         for (int x : fan) fmax = std::max(fmax, x);
         if (!((double)bmax * (fmax + 1) < std::ldexp(1.0, D.heb)))
             return fail("fixed-point bound", r, fmax, D.heb);
+        fan_most = std::max(fan_most, fmax);
         pairs_total += (int64_t)half.size();
         slots_total += slots;
         if (slots > 0) worst_fill = std::min(worst_fill, (double)half.size() / (double)slots);
     }
-    printf("ok regions %d pairs %lld slots %lld fill %.4f worst %.4f\n", nr, (long long)pairs_total,
-           (long long)slots_total, slots_total ? (double)pairs_total / (double)slots_total : 1.0, worst_fill);
+    printf("ok regions %d pairs %lld slots %lld fill %.4f worst %.4f fan %d\n", nr, (long long)pairs_total,
+           (long long)slots_total, slots_total ? (double)pairs_total / (double)slots_total : 1.0, worst_fill,
+           fan_most);
     for (int r = 0; r < nr; ++r) printf("ritz %d %.17g %.17g\n", r, C.ritz_lo[r], C.ritz_hi[r]);
     return 0;
 }
